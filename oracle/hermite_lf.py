@@ -1,0 +1,317 @@
+"""FP64 CPU oracle of the Hermite-leapfrog scheme (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline``
+leg may use this module.  Nothing here is shared with the HIP path.
+
+System (the paper's pressure-velocity form, Sec. 4 and Sec. 5, with kappa = c^2
+constant):
+
+    p_t = -kappa * div(u),      u_t = -grad(p).
+
+Data (Sec. 2 and Sec. 5): every node stores scaled Taylor data
+    f~_alpha = prod_k h_k^{alpha_k} / alpha_k!  *  d^alpha f (node),
+    alpha in {0..m}^d.
+Pressure lives on the primal grid x_j = lo + j*h at integer time levels, every
+velocity component on the dual grid x_{j+1/2} at half-integer levels (Sec. 2,
+eqs. (pGrid), (dGrid); Sec. 5).  The grid is periodic; dual index q sits at
+x_{q+1/2}.
+
+One step (P^n, U^{n+1/2}) -> (P^{n+1}, U^{n+3/2}) is a p half-step followed by
+a u half-step:
+
+* p half-step at primal node j: the 2^d dual nodes q = j - 1 + eps
+  (eps in {0,1}^d) are the corners of the cell centred on x_j.  Each velocity
+  component is interpolated on that cell by the tensor-product Hermite-Birkhoff
+  interpolant of degree 2m+1 per variable (Sec. 2, eq. (interp); Sec. 5
+  dimension-by-dimension reconstruction).  The leapfrog difference keeps only
+  odd time derivatives (Sec. 2, eq. (update1)); Cauchy-Kowalevsky turns them
+  into space derivatives (Sec. 2, eq. (LFloop); Sec. 3.1.2, eq. (pdup)):
+      d_t^{2k+1} p = -kappa^{k+1} Lap^k div u,
+  so  P~_s <- P~_s - sum_k w_k kappa^{k+1} [Lap^k div c]_s,
+      w_k = 2 (dt/2)^{2k+1} / (2k+1)!,   s in {0..m}^d.
+* u half-step at dual node q: primal corners j = q + eps, interpolate p, and
+  (Sec. 3.1.2, eq. (vdup))  d_t^{2k+1} u = -kappa^k grad Lap^k p, so
+      U~_{i,s} <- U~_{i,s} - sum_k w_k kappa^k [D_i Lap^k c]_s.
+
+Readings of the paper taken here (each is listed in the design notes):
+the interpolant matches value and first m derivatives at each end (Sec. 2,
+text after eq. (interp)); the sum over odd j runs until the term vanishes
+(Sec. 2, after eq. (update1)); grad^{j-1} in eqs. (pdup)/(vdup) is read as
+Lap^{(j-1)/2}; the system signs of Sec. 4 are used in every dimension; a
+step is the p half-step then the u half-step.
+
+Arrays use the boundary's host layout: C order, node axes (x_1..x_d) then
+coefficient axes (a_1..a_d); U has a leading component axis (u_1..u_d).
+"""
+
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, replace
+from fractions import Fraction
+from math import comb, factorial
+
+import numpy as np
+
+__all__ = [
+    "Problem", "hermite_matrix_exact", "hermite_matrix", "p_half", "u_half",
+    "step", "startup", "p_update_cells", "u_update_cells",
+]
+
+_CHUNK = 1 << 14  # nodes per vectorised batch (bounds memory, not arithmetic)
+
+
+# ---------------------------------------------------------------------------
+# Problem description
+# ---------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Problem:
+    """Periodic constant-coefficient problem: dimension d, Hermite order m,
+    cells per dimension K, period length per dimension, time step dt and
+    kappa = c^2 (system of Sec. 4 / Sec. 5 with constant coefficient)."""
+
+    d: int
+    m: int
+    K: tuple
+    length: tuple
+    dt: float
+    kappa: float = 1.0
+
+    @property
+    def h(self):
+        return tuple(float(L) / int(k) for L, k in zip(self.length, self.K))
+
+    @property
+    def nc(self):
+        return (self.m + 1) ** self.d
+
+    def with_dt(self, dt):
+        return replace(self, dt=dt)
+
+    def p_shape(self):
+        return tuple(self.K) + (self.m + 1,) * self.d
+
+    def u_shape(self):
+        return (self.d,) + self.p_shape()
+
+
+# ---------------------------------------------------------------------------
+# Hermite-Birkhoff interpolation matrix (Sec. 2, eq. (interp))
+# ---------------------------------------------------------------------------
+def hermite_matrix_exact(m: int):
+    """H_m = [C^L; C^R]^{-1} in exact rationals (Sec. 2, eq. (interp)).
+
+    The interpolant on a cell is q(xi) = sum_{s=0}^{2m+1} c_s xi^s with
+    xi = (x - centre)/h.  Its scaled l-th derivative at xi0 is
+    sum_s binom(s, l) xi0^{s-l} c_s, which is C_{ls} of the paper with
+    xi0 = -1/2 (left end, C^L) and +1/2 (right end, C^R).  Rows of the
+    returned matrix are the coefficients c_s; columns are the data
+    (v^L_0..v^L_m, v^R_0..v^R_m).
+    """
+    n = 2 * m + 2
+    A = [[Fraction(0)] * n for _ in range(n)]
+    for side, xi0 in enumerate((Fraction(-1, 2), Fraction(1, 2))):
+        for l in range(m + 1):
+            for s in range(l, n):
+                A[side * (m + 1) + l][s] = comb(s, l) * xi0 ** (s - l)
+    # Gauss-Jordan elimination on [A | I] in exact arithmetic.
+    aug = [row[:] + [Fraction(int(i == j)) for j in range(n)] for i, row in enumerate(A)]
+    for col in range(n):
+        piv = next(r for r in range(col, n) if aug[r][col] != 0)
+        aug[col], aug[piv] = aug[piv], aug[col]
+        pv = aug[col][col]
+        aug[col] = [x / pv for x in aug[col]]
+        for r in range(n):
+            if r != col and aug[r][col] != 0:
+                f = aug[r][col]
+                aug[r] = [x - f * y for x, y in zip(aug[r], aug[col])]
+    return [row[n:] for row in aug]
+
+
+def hermite_matrix(m: int) -> np.ndarray:
+    """FP64 H_m: each entry is the correctly rounded exact rational."""
+    return np.array([[float(x) for x in row] for row in hermite_matrix_exact(m)],
+                    dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Coefficient-space operators on cell polynomials
+# ---------------------------------------------------------------------------
+def _interpolate(B: np.ndarray, H: np.ndarray, d: int, ns: int) -> np.ndarray:
+    """Tensor-product interpolation, one dimension at a time (Sec. 5).
+
+    B has shape (2,)*d + S + (m+1,)*d: corner e (left/right per dimension) of
+    a batch S of cells, scaled data alpha.  Returns c with shape
+    S + (2m+2,)*d, the coefficients of the interpolant in xi.
+    """
+    for k in range(d):
+        L, R = B[0], B[1]                 # consume the corner axis of dim k
+        ax = (d - k - 1) + ns + k         # data axis of dim k inside L / R
+        both = np.concatenate([L, R], axis=ax)
+        B = np.moveaxis(np.tensordot(H, np.moveaxis(both, ax, 0), axes=(1, 0)), 0, ax)
+    return B
+
+
+def _deriv(c: np.ndarray, i: int, h_i: float, ns: int) -> np.ndarray:
+    """x_i-derivative in coefficient space: (D_i c)_b = (b_i + 1) c_{b+e_i} / h_i."""
+    ax = ns + i
+    n = c.shape[ax]
+    out = np.zeros_like(c)
+    src = [slice(None)] * c.ndim
+    dst = [slice(None)] * c.ndim
+    src[ax] = slice(1, n)
+    dst[ax] = slice(0, n - 1)
+    shape = [1] * c.ndim
+    shape[ax] = n - 1
+    fac = np.arange(1, n, dtype=np.float64).reshape(shape)
+    out[tuple(dst)] = c[tuple(src)] * fac / h_i
+    return out
+
+
+def _laplacian(c: np.ndarray, h, d: int, ns: int) -> np.ndarray:
+    out = np.zeros_like(c)
+    for i in range(d):
+        out = out + _deriv(_deriv(c, i, h[i], ns), i, h[i], ns)
+    return out
+
+
+def _truncate(c: np.ndarray, m: int, d: int, ns: int) -> np.ndarray:
+    """Keep the coefficients s in {0..m}^d: the new nodal data are the Taylor
+    coefficients of the updated polynomial at the cell centre (Sec. 2)."""
+    idx = [slice(None)] * ns + [slice(0, m + 1)] * d
+    return c[tuple(idx)]
+
+
+def _w(k: int, dt: float) -> float:
+    """w_k = 2 (dt/2)^{2k+1} / (2k+1)!  (Sec. 2, eq. (update1), j = 2k+1)."""
+    return 2.0 * (dt / 2.0) ** (2 * k + 1) / factorial(2 * k + 1)
+
+
+def _is_zero(a: np.ndarray) -> bool:
+    return not np.any(a)
+
+
+# ---------------------------------------------------------------------------
+# Cell-level updates (batched over cells)
+# ---------------------------------------------------------------------------
+def p_update_cells(prob: Problem, p_vals: np.ndarray, u_corners, dt=None) -> np.ndarray:
+    """New pressure data at a batch of primal nodes.
+
+    p_vals: (n,) + (m+1,)*d, pressure data at the nodes at time t.
+    u_corners: sequence of d arrays, each (2,)*d + (n,) + (m+1,)*d: velocity
+    component i at the 2^d dual corners of each node's cell, time t + dt/2.
+    Returns p data at t + dt (Sec. 2, eq. (final1); Sec. 3.1.2, eq. (pdup)).
+    """
+    d, m = prob.d, prob.m
+    dt = prob.dt if dt is None else dt
+    h = prob.h
+    H = hermite_matrix(m)
+    r = None
+    for i in range(d):
+        ci = _interpolate(np.asarray(u_corners[i], dtype=np.float64), H, d, 1)
+        di = _deriv(ci, i, h[i], 1)
+        r = di if r is None else r + di            # div of the interpolant
+    incr = np.zeros_like(r)
+    term = r
+    k = 0
+    while not _is_zero(term):
+        incr = incr + _w(k, dt) * prob.kappa ** (k + 1) * term
+        term = _laplacian(term, h, d, 1)
+        k += 1
+    return p_vals - _truncate(incr, m, d, 1)
+
+
+def u_update_cells(prob: Problem, u_vals: np.ndarray, p_corners: np.ndarray,
+                   dt=None, weight_scale: float = 1.0) -> np.ndarray:
+    """New velocity data at a batch of dual nodes.
+
+    u_vals: (d, n) + (m+1,)*d at time t - dt/2 (or t for the start-up).
+    p_corners: (2,)*d + (n,) + (m+1,)*d, pressure at the 2^d primal corners of
+    each dual node's cell at time t.  Returns u at t + dt/2 (Sec. 3.1.2,
+    eq. (vdup)); ``weight_scale`` multiplies every w_k (1/2 for the start-up).
+    """
+    d, m = prob.d, prob.m
+    dt = prob.dt if dt is None else dt
+    h = prob.h
+    c = _interpolate(np.asarray(p_corners, dtype=np.float64), hermite_matrix(m), d, 1)
+    out = np.array(u_vals, dtype=np.float64, copy=True)
+    for i in range(d):
+        incr = np.zeros_like(c)
+        term = c                                   # Lap^k c
+        k = 0
+        while not _is_zero(term):
+            incr = incr + weight_scale * _w(k, dt) * prob.kappa ** k * _deriv(term, i, h[i], 1)
+            term = _laplacian(term, h, d, 1)
+            k += 1
+        out[i] = out[i] - _truncate(incr, m, d, 1)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Periodic gathers and half-steps
+# ---------------------------------------------------------------------------
+def _all_nodes(K) -> np.ndarray:
+    grids = np.meshgrid(*[np.arange(k) for k in K], indexing="ij")
+    return np.stack([g.ravel() for g in grids], axis=1)
+
+
+def _gather(F: np.ndarray, nodes: np.ndarray, offset: int, d: int, K) -> np.ndarray:
+    """Corner data F[(node + offset + eps) mod K] for eps in {0,1}^d, shaped
+    (2,)*d + (n,) + coefficient axes."""
+    n = nodes.shape[0]
+    out = np.empty((2,) * d + (n,) + F.shape[d:], dtype=F.dtype)
+    for eps in itertools.product((0, 1), repeat=d):
+        idx = tuple((nodes[:, k] + offset + eps[k]) % K[k] for k in range(d))
+        out[eps] = F[idx]
+    return out
+
+
+def p_half(prob: Problem, P: np.ndarray, U: np.ndarray, nodes=None, dt=None):
+    """Pressure half-step on the periodic grid.  P, U in natural layout.
+    Primal node j takes the dual corners q = j - 1 + eps (cell centred on x_j
+    with ends x_{j-1/2}, x_{j+1/2}).  With ``nodes`` (n, d) only those nodes
+    are computed and an (n,)+coef array is returned; else the new P."""
+    d, K = prob.d, tuple(prob.K)
+    full = nodes is None
+    nodes = _all_nodes(K) if full else np.asarray(nodes, dtype=np.int64).reshape(-1, d)
+    res = np.empty((nodes.shape[0],) + P.shape[d:], dtype=np.float64)
+    for a in range(0, nodes.shape[0], _CHUNK):
+        nd = nodes[a:a + _CHUNK]
+        uc = [_gather(U[i], nd, -1, d, K) for i in range(d)]
+        pv = P[tuple(nd[:, k] for k in range(d))]
+        res[a:a + _CHUNK] = p_update_cells(prob, pv, uc, dt=dt)
+    return res.reshape(P.shape) if full else res
+
+
+def u_half(prob: Problem, U: np.ndarray, P: np.ndarray, nodes=None, dt=None,
+           weight_scale: float = 1.0):
+    """Velocity half-step.  Dual node q takes the primal corners j = q + eps
+    (cell centred on x_{q+1/2} with ends x_q, x_{q+1})."""
+    d, K = prob.d, tuple(prob.K)
+    full = nodes is None
+    nodes = _all_nodes(K) if full else np.asarray(nodes, dtype=np.int64).reshape(-1, d)
+    res = np.empty((d, nodes.shape[0]) + P.shape[d:], dtype=np.float64)
+    for a in range(0, nodes.shape[0], _CHUNK):
+        nd = nodes[a:a + _CHUNK]
+        pc = _gather(P, nd, 0, d, K)
+        uv = np.stack([U[i][tuple(nd[:, k] for k in range(d))] for i in range(d)])
+        res[:, a:a + _CHUNK] = u_update_cells(prob, uv, pc, dt=dt, weight_scale=weight_scale)
+    return res.reshape(U.shape) if full else res
+
+
+def step(prob: Problem, P: np.ndarray, U: np.ndarray, nsteps: int = 1):
+    """nsteps full steps: (P^n, U^{n+1/2}) -> (P^{n+N}, U^{n+N+1/2})."""
+    P = np.array(P, dtype=np.float64, copy=True)
+    U = np.array(U, dtype=np.float64, copy=True)
+    for _ in range(int(nsteps)):
+        P = p_half(prob, P, U)
+        U = u_half(prob, U, P)
+    return P, U
+
+
+def startup(prob: Problem, P0: np.ndarray, U0: np.ndarray) -> np.ndarray:
+    """U^{1/2} from (P^0, U^0): the Taylor series of u over dt/2 about t0.
+    Odd terms are -(dt/2)^{2k+1}/(2k+1)! kappa^k grad Lap^k p, i.e. the u
+    half-step with every w_k halved; even terms are those of U^0 alone and are
+    dropped (exact when U^0 = 0, the start used here)."""
+    return u_half(prob, U0, P0, weight_scale=0.5)

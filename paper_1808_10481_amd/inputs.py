@@ -1,0 +1,172 @@
+"""Seeded synthetic inputs: closed-form fields sampled as scaled Taylor data.
+
+This module holds no arithmetic of the time-stepping method itself; it only
+samples given closed-form functions and their exact derivatives at grid nodes
+in the data format of the scheme (value and first m derivatives per
+dimension, scaled by h^a / a!; Sec. 2 and Sec. 5 of the paper).  Both the HIP
+path's tests and the oracle's tests take their inputs from here.
+
+Host layout of every array: C order, node axes (x_1..x_d) then coefficient
+axes (a_1..a_d); velocity arrays have a leading component axis.  Primal node
+j sits at x = j*h, dual node q at x = (q + 1/2)*h, on the periodic box
+[0, length).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+from math import factorial, pi, sqrt
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# 1D scaled derivative data of elementary functions
+# ---------------------------------------------------------------------------
+def scaled_sin(x, a, phase, h, m):
+    """Rows n = 0..m of (h^n / n!) d^n/dx^n sin(a x + phase) at points x."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.empty(x.shape + (m + 1,), dtype=np.float64)
+    for n in range(m + 1):
+        out[..., n] = (h * a) ** n / factorial(n) * np.sin(a * x + phase + n * pi / 2)
+    return out
+
+
+def scaled_gauss(s, w, h, m):
+    """Rows n = 0..m of (h^n/n!) d^n/ds^n exp(-(s/w)^2), via the physicists'
+    Hermite polynomials: d^n/ds^n e^{-y^2} = (-1)^n H_n(y) e^{-y^2}, y = s/w."""
+    y = np.asarray(s, dtype=np.float64) / w
+    g = np.exp(-y * y)
+    out = np.empty(y.shape + (m + 1,), dtype=np.float64)
+    Hm1, H0 = np.zeros_like(y), np.ones_like(y)
+    for n in range(m + 1):
+        out[..., n] = (h / w) ** n / factorial(n) * (-1) ** n * H0 * g
+        Hm1, H0 = H0, 2 * y * H0 - 2 * n * Hm1
+    return out
+
+
+def outer(factors):
+    """Tensor product of per-dimension data f_k with shape (K_k, m+1):
+    result[j_1..j_d, a_1..a_d] = prod_k f_k[j_k, a_k]."""
+    d = len(factors)
+    res = np.ones((1,) * (2 * d), dtype=np.float64)
+    for k, f in enumerate(factors):
+        shape = [1] * (2 * d)
+        shape[k] = f.shape[0]
+        shape[d + k] = f.shape[1]
+        res = res * f.reshape(shape)
+    return np.ascontiguousarray(res)
+
+
+# ---------------------------------------------------------------------------
+# Closed-form solutions of p_t = -kappa div u, u_t = -grad p
+# ---------------------------------------------------------------------------
+def standing_mode(d, m, K, length, waves, t_p, t_u, kappa=1.0):
+    """Product standing mode  p = cos(w t) prod_k sin(a_k x_k),
+    u_i = -(sin(w t)/w) a_i cos(a_i x_i) prod_{k!=i} sin(a_k x_k),
+    a_k = 2 pi waves_k / length_k, w = sqrt(kappa) |a|.
+    Returns (P at t_p on primal nodes, U at t_u on dual nodes)."""
+    K = tuple(int(k) for k in K)
+    length = tuple(float(v) for v in length)
+    h = [length[k] / K[k] for k in range(d)]
+    a = [2 * pi * waves[k] / length[k] for k in range(d)]
+    w = sqrt(kappa) * sqrt(sum(x * x for x in a))
+    xp = [np.arange(K[k]) * h[k] for k in range(d)]
+    xd = [(np.arange(K[k]) + 0.5) * h[k] for k in range(d)]
+    P = np.cos(w * t_p) * outer([scaled_sin(xp[k], a[k], 0.0, h[k], m) for k in range(d)])
+    U = np.empty((d,) + P.shape, dtype=np.float64)
+    for i in range(d):
+        fac = [scaled_sin(xd[k], a[k], pi / 2 if k == i else 0.0, h[k], m) for k in range(d)]
+        U[i] = -(np.sin(w * t_u) / w) * a[i] * outer(fac)
+    return P, U
+
+
+def gaussian_pulse(d, m, K, length, center, width):
+    """p0 = prod_k exp(-(s_k/width)^2), s_k the minimum-image distance of x_k to
+    center_k on the periodic box; returned as primal scaled data."""
+    K = tuple(int(k) for k in K)
+    fac = []
+    for k in range(d):
+        L = float(length[k])
+        h = L / K[k]
+        x = np.arange(K[k]) * h
+        s = np.mod(x - center[k] + 0.5 * L, L) - 0.5 * L
+        fac.append(scaled_gauss(s, width, h, m))
+    return outer(fac)
+
+
+def random_data(rng, d, m, K, ncomp=None):
+    """Uniform[-1,1] scaled data (any data is valid input to the linear scheme)."""
+    shape = tuple(int(k) for k in K) + (m + 1,) * d
+    if ncomp is not None:
+        shape = (ncomp,) + shape
+    return rng.uniform(-1.0, 1.0, size=shape)
+
+
+# ---------------------------------------------------------------------------
+# Workloads (seeded recipes)
+# ---------------------------------------------------------------------------
+@dataclass
+class Workload:
+    name: str
+    d: int
+    m: int
+    K: tuple
+    length: tuple
+    nu: float
+    kappa: float
+    steps: int
+    P0: np.ndarray | None = None
+    U0: np.ndarray | None = None      # U at t0 + dt/2, or U(t0) when startup
+    startup: bool = False
+    exact: object = None              # callable(t) -> P at time t, or None
+
+    @property
+    def h(self):
+        return tuple(self.length[k] / self.K[k] for k in range(self.d))
+
+    @property
+    def dt(self):
+        return self.nu * min(self.h) / sqrt(self.kappa)
+
+    @property
+    def cells(self):
+        return int(np.prod(self.K))
+
+
+def standing_wave_1d(K=200, m=1, nu=0.5, T=1.0, make_data=True):
+    """p_t + u_x = 0, u_t + p_x = 0 on periodic [0,1); p0 = sin(2 pi x),
+    u at dt/2 from the exact standing wave; run to T."""
+    wl = Workload("standing_wave_1d", 1, m, (K,), (1.0,), nu, 1.0, 0)
+    wl.steps = int(round(T / wl.dt))
+    if make_data:
+        wl.P0, wl.U0 = standing_mode(1, m, wl.K, wl.length, (1,), 0.0, wl.dt / 2)
+        wl.exact = lambda t: standing_mode(1, m, wl.K, wl.length, (1,), t, t)[0]
+    return wl
+
+
+def standing_mode_2d(seed=1, K=1024, m=3, nu=0.5, steps=1000, make_data=True):
+    """sin(2 pi k x) sin(2 pi l y) standing mode on the periodic unit square,
+    (k, l) seeded in [1, 8]."""
+    rng = np.random.default_rng(seed)
+    kl = tuple(int(v) for v in rng.integers(1, 9, 2))
+    wl = Workload("standing_mode_2d", 2, m, (K, K), (1.0, 1.0), nu, 1.0, steps)
+    wl.waves = kl
+    if make_data:
+        wl.P0, wl.U0 = standing_mode(2, m, wl.K, wl.length, kl, 0.0, wl.dt / 2)
+        wl.exact = lambda t: standing_mode(2, m, wl.K, wl.length, kl, t, t)[0]
+    return wl
+
+
+def gaussian_pulse_3d(seed=2, K=256, m=2, nu=0.5, steps=500, width=0.05, make_data=True):
+    """Gaussian pressure pulse of the given width at a seeded centre of the
+    periodic unit cube, u(t0) = 0 (the start-up builds u at dt/2)."""
+    rng = np.random.default_rng(seed)
+    center = tuple(float(v) for v in rng.random(3))
+    wl = Workload("gaussian_pulse_3d", 3, m, (K, K, K), (1.0, 1.0, 1.0), nu, 1.0, steps)
+    wl.center = center
+    wl.startup = True
+    if make_data:
+        wl.P0 = gaussian_pulse(3, m, wl.K, wl.length, center, width)
+        wl.U0 = np.zeros((3,) + wl.P0.shape)
+    return wl
