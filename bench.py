@@ -1,0 +1,215 @@
+"""Benchmark: Hermite-leapfrog cell-updates/s on one MI355X.
+
+Workload: 2D periodic unit square, constant coefficient (kappa = 1), Hermite
+order m = 3 (16 scaled coefficients per field per node), 1024 x 1024 cells,
+nu = c dt / h = 0.5, seeded standing mode sin(2 pi k x) sin(2 pi l y)
+(k, l in [1, 8]); the state starts resident in HBM.  A step is one pressure
+half-step plus one velocity half-step over the whole grid (one cell-update
+per node per step).  FP64 is the headline; FP32 is timed in the same run.
+
+Prints one JSON line.  Run as: python bench.py [--steps K] [--warmup W].
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Hermite cell-updates/s (FP64 vs FP32) at stated L2 error; % HBM roofline"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_precision(hl, torch, wl, prec, steps, warmup):
+    plan = hl.Plan(wl.d, wl.m, wl.K, dt=wl.dt, c=1.0, precision=prec)
+    p, u = plan.alloc()
+    plan.init(p, u, wl.P0, wl.U0)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.p_half(p, u)
+        plan.u_half(u, p)
+    # restart from the initial state so the timed run is the workload itself
+    plan.init(p, u, wl.P0, wl.U0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for n in range(steps):
+        plan.p_half(p, u)
+        ev[2 * n + 1].record(stream)
+        plan.u_half(u, p)
+        ev[2 * n + 2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tp = [ev[2 * n].elapsed_time(ev[2 * n + 1]) for n in range(steps)]
+    tu = [ev[2 * n + 1].elapsed_time(ev[2 * n + 2]) for n in range(steps)]
+    total_ms = ev[0].elapsed_time(ev[-1])
+    P, U = plan.export(p, u)
+    info = plan.info
+    plan.close()
+    del p, u
+    torch.cuda.empty_cache()
+    return dict(total_ms=total_ms, wall_s=wall, p_ms=float(np.mean(tp)), u_ms=float(np.mean(tu)),
+                P=P, U=U, word=info.word_bytes, nodes=info.nodes, nc=info.nc)
+
+
+def roofline(res, d):
+    """Dominant kernel: algorithmic HBM bytes per launch / average duration.
+    p half-step reads u (d fields) and p, writes p: (d + 2) nc words per node;
+    u half-step reads p and u, writes u: (2 d + 1) nc words per node."""
+    per = {"p_half": ((d + 2) * res["nc"] * res["word"], res["p_ms"]),
+           "u_half": ((2 * d + 1) * res["nc"] * res["word"], res["u_ms"])}
+    name = max(per, key=lambda k: per[k][1])
+    bpn, ms = per[name]
+    gbs = bpn * res["nodes"] / (ms * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_cell": bpn, "avg_ms": round(ms, 5)}
+
+
+def copy_probe(torch, nbytes=1 << 30, reps=20):
+    """Plain device copy y <- x of nbytes (the paper's "realistic peak"
+    vector-copy measurement); GB/s counts bytes read + written."""
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return {"bytes_moved": 2 * nbytes, "avg_ms": round(ms, 4), "gbs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
+def cpu_baseline(wl, rows):
+    """The oracle, as it stands, on one step over the nodes of `rows` grid rows."""
+    import oracle
+    prob = oracle.Problem(wl.d, wl.m, wl.K, wl.length, wl.dt, 1.0)
+    K0 = wl.K[0]
+    nodes = np.stack(np.meshgrid(np.arange(K0), np.arange(rows), indexing="ij"), -1).reshape(-1, 2)
+    t0 = time.perf_counter()
+    Pn = oracle.p_half(prob, wl.P0, wl.U0, nodes=nodes)
+    # the u half-step at these dual nodes needs the new P on their corners
+    # (rows 0..rows); compute that extra row and splice it in
+    P1 = np.array(wl.P0, copy=True)
+    P1[:, :rows] = Pn.reshape(K0, rows, *Pn.shape[1:])
+    extra = np.stack(np.meshgrid(np.arange(K0), np.array([rows % wl.K[1]]), indexing="ij"), -1).reshape(-1, 2)
+    P1[:, rows % wl.K[1]] = oracle.p_half(prob, wl.P0, wl.U0, nodes=extra).reshape(K0, *Pn.shape[1:])
+    Un = oracle.u_half(prob, wl.U0, P1, nodes=nodes)
+    sec = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    return dict(value=nodes.shape[0] / sec, seconds=sec, cores=cores, P=Pn, U=Un, rows=rows)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--K", type=int, default=1024)
+    ap.add_argument("--cpu-rows", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-copy-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the build has no "
+                          "multi-GPU path (see the sharding note in DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1808_10481_amd import hl, inputs
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    log(f"[bench] building workload standing_mode_2d K={args.K} m=3")
+    wl = inputs.standing_mode_2d(seed=1, K=args.K, m=3, steps=args.steps)
+    t_end = args.steps * wl.dt
+    Pex, _ = inputs.standing_mode(2, 3, wl.K, wl.length, wl.waves, t_end, 0.0)
+    vol = float(np.prod(wl.h))
+
+    log(f"[bench] fp64: {args.warmup} warmup + {args.steps} timed steps")
+    r64 = run_precision(hl, torch, wl, "fp64", args.steps, args.warmup)
+    value64 = wl.cells * args.steps / (r64["total_ms"] * 1e-3)
+    err64 = float(np.sqrt(vol * np.sum((r64["P"][..., 0, 0] - Pex[..., 0, 0]) ** 2)))
+    log(f"[bench] fp64 {r64['total_ms'] / args.steps:.4f} ms/step, p {r64['p_ms']:.4f} u {r64['u_ms']:.4f} ms")
+
+    out = {
+        "metric": METRIC, "value": value64, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["total_ms"] / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"standing_mode_2d m=3 {args.K}x{args.K} nu=0.5 kappa=1 "
+                               f"waves={list(wl.waves)}", "d": 2, "m": 3, "cells": list(wl.K),
+                   "steps": args.steps, "parallelism": "single_gpu"},
+        "roofline": roofline(r64, 2),
+        "l2": {"fp64_nodal_vs_exact": err64},
+    }
+
+    if not args.no_fp32:
+        log(f"[bench] fp32: {args.warmup} warmup + {args.steps} timed steps")
+        r32 = run_precision(hl, torch, wl, "fp32", args.steps, args.warmup)
+        value32 = wl.cells * args.steps / (r32["total_ms"] * 1e-3)
+        den = np.sqrt(np.sum(r64["P"] ** 2) + np.sum(r64["U"] ** 2))
+        rel = float(np.sqrt(np.sum((r32["P"] - r64["P"]) ** 2) + np.sum((r32["U"] - r64["U"]) ** 2)) / den)
+        err32 = float(np.sqrt(vol * np.sum((r32["P"][..., 0, 0] - Pex[..., 0, 0]) ** 2)))
+        v32 = np.concatenate([r32["P"][..., 0, 0].ravel(), r32["U"][..., 0, 0].ravel()])
+        v64 = np.concatenate([r64["P"][..., 0, 0].ravel(), r64["U"][..., 0, 0].ravel()])
+        relv = float(np.linalg.norm(v32 - v64) / np.linalg.norm(v64))
+        out["fp32"] = {"value": value32, "ms_per_step": r32["total_ms"] / args.steps,
+                       "rel_l2_vs_fp64_state": rel, "rel_l2_vs_fp64_nodal_values": relv,
+                       "nodal_l2_vs_exact": err32,
+                       "roofline": roofline(r32, 2), "speedup_vs_fp64": value32 / value64}
+        log(f"[bench] fp32 {r32['total_ms'] / args.steps:.4f} ms/step, rel L2 vs fp64 {rel:.3e}")
+
+    if not args.no_copy_probe:
+        out["copy_probe"] = copy_probe(torch)
+        log(f"[bench] copy probe {out['copy_probe']}")
+
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle, one step over {args.cpu_rows} of {args.K} rows")
+        cb = cpu_baseline(wl, args.cpu_rows)
+        # parity of the same sample against one GPU FP64 step
+        plan = hl.Plan(wl.d, wl.m, wl.K, dt=wl.dt, c=1.0, precision="fp64")
+        p, u = plan.alloc()
+        plan.init(p, u, wl.P0, wl.U0)
+        plan.step(p, u, 1)
+        P1, U1 = plan.export(p, u)
+        plan.close()
+        gp = P1[:, :args.cpu_rows].reshape(cb["P"].shape)
+        gu = np.stack([U1[i][:, :args.cpu_rows].reshape(cb["P"].shape) for i in range(2)])
+        num = np.sqrt(np.sum((gp - cb["P"]) ** 2) + np.sum((gu - cb["U"]) ** 2))
+        den = np.sqrt(np.sum(cb["P"] ** 2) + np.sum(cb["U"] ** 2))
+        out["l2"]["fp64_vs_oracle_one_step_sample"] = float(num / den)
+        out["cpu_baseline"] = {"value": cb["value"], "unit": "cell-updates/s", "cores": cb["cores"],
+                               "kind": "oracle",
+                               "sample": f"one step (p and u half-steps) over the {args.K * args.cpu_rows} "
+                                         f"nodes of {args.cpu_rows} of {args.K} rows, "
+                                         f"{cb['seconds']:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

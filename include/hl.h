@@ -1,0 +1,157 @@
+/*
+ * hl.h - C ABI of the Hermite-leapfrog wave-stepping library (libhermite_lf.so)
+ *
+ * The library advances the first-order acoustic system
+ *
+ *     p_t = -kappa div(u),     u_t = -grad(p),     kappa = c^2 constant,
+ *
+ * on a periodic box with the Hermite-leapfrog method of Vargas, Hagstrom,
+ * Chan and Warburton, "Leapfrog time-stepping for Hermite methods"
+ * (arXiv 1808.10481):
+ *   - data: value and first m derivatives per dimension at every node, scaled
+ *     by h^a/a! (Sec. 2; Sec. 5 tensor-product form);
+ *   - pressure on the primal grid x_j = j h at integer time levels, every
+ *     velocity component on the dual grid x_{j+1/2} at half-integer levels
+ *     (Sec. 2, eqs. (pGrid), (dGrid); Sec. 5);
+ *   - one step = pressure half-step then velocity half-step; each builds the
+ *     per-cell tensor-product Hermite-Birkhoff interpolant of degree 2m+1
+ *     (Sec. 2, eq. (interp)) from the 2^d staggered neighbours and applies
+ *     the odd-term leapfrog difference (Sec. 2, eq. (update1)) with
+ *     Cauchy-Kowalevsky time-to-space exchange (Sec. 2, eqs. (LFloop),
+ *     (final1); Sec. 3.1.2, eqs. (pdup), (vdup)).
+ *
+ * Conventions
+ *   - Every call returns an hl_status; HL_OK == 0.  No C++ exception crosses
+ *     the ABI.  On failure hl_last_error() returns a message (thread-local,
+ *     valid until the next call on the same thread).
+ *   - Arguments are validated on the host before anything is launched.
+ *   - Device pointers (p, u, ...) are caller-owned device memory of
+ *     hl_state_words() words of hl_info.word_bytes bytes each, in the
+ *     library's device layout (below).  The caller owns the stream; a NULL
+ *     stream is the default stream.  hl_step, hl_p_half and hl_u_half are
+ *     asynchronous on that stream; hl_init and hl_export are synchronous.
+ *   - The plan owns its operator tables and scratch; it must outlive the
+ *     work enqueued with it and is freed by hl_plan_destroy.
+ *
+ * Host layout (hl_init input, hl_export output): FP64, C order,
+ *   p[j_1]...[j_d][a_1]...[a_d],  u[i][j_1]...[j_d][a_1]...[a_d],
+ * node index j_k in [0, K_k), coefficient index a_k in [0, m], velocity
+ * component i in [0, d).  Primal node j is at x = j h, dual node q at
+ * x = (q + 1/2) h.
+ *
+ * Device layout (opaque to callers, fixed per plan): coefficient-major
+ * planes, p[c][n] and u[i][c][n], with node n = j_1 + K_1 (j_2 + K_2 j_3)
+ * and coefficient c = a_1 + (m+1)(a_2 + (m+1) a_3), in the plan precision.
+ */
+#ifndef HL_H
+#define HL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HL_OK = 0,
+  HL_ERR_ARG = 1,          /* invalid argument (NULL pointer, bad size, NaN) */
+  HL_ERR_CFL = 2,          /* c dt / min h outside (0, 1) */
+  HL_ERR_UNSUPPORTED = 3,  /* (d, m, precision) combination not built */
+  HL_ERR_DEVICE = 4,       /* HIP runtime error */
+  HL_ERR_NOMEM = 5,        /* host or device allocation failed */
+  HL_ERR_NONFINITE = 6     /* hl_norms found a NaN or Inf */
+} hl_status;
+
+typedef enum { HL_FP64 = 0, HL_FP32 = 1 } hl_precision;
+
+/* Problem statement (Sec. 4: system, CFL constant and time step; Sec. 5:
+ * tensor grid with spacing h_k per dimension). */
+typedef struct {
+  int32_t d;            /* space dimension, 1..3 */
+  int32_t m;            /* Hermite order: value + first m derivatives;
+                           supported 0..7 for d = 1, 0..5 for d = 2, 0..3 for d = 3 */
+  int64_t cells[3];     /* K_k >= 2 nodes per dimension (periodic); entries >= d ignored */
+  double  length[3];    /* period length per dimension, > 0; h_k = length_k / K_k */
+  double  dt;           /* time step > 0, or 0 to derive dt = cfl * min_k h_k / c */
+  double  cfl;          /* used when dt == 0 */
+  double  c;            /* wave speed > 0; kappa = c^2 */
+  int32_t precision;    /* hl_precision: storage and arithmetic type of the state */
+  int32_t reserved;     /* must be 0 */
+} hl_problem;
+
+typedef struct {
+  double  dt;           /* time step in use */
+  double  nu;           /* c dt / min_k h_k, in (0, 1) */
+  int64_t nodes;        /* prod_k K_k */
+  int32_t nc;           /* (m+1)^d coefficients per node per field */
+  int32_t word_bytes;   /* 8 (FP64) or 4 (FP32) */
+  int64_t p_words;      /* nc * nodes */
+  int64_t u_words;      /* d * nc * nodes */
+} hl_info;
+
+typedef struct hl_plan_s* hl_plan_t;
+
+/* Build a plan: validates the problem (HL_ERR_ARG, HL_ERR_CFL when
+ * c dt / min h is not in (0, 1) - the domain-of-dependence bound of
+ * Sec. 3.1.1 - and HL_ERR_UNSUPPORTED), builds the interpolation operator of
+ * Sec. 2 eq. (interp) exactly in rationals and the Cauchy-Kowalevsky weight
+ * tables in FP64, casts them to the plan precision and uploads them to the
+ * current HIP device.  *out receives the handle (unchanged on failure). */
+hl_status hl_plan(const hl_problem* prob, hl_plan_t* out);
+
+/* Free the plan and its device tables.  NULL is accepted. */
+hl_status hl_plan_destroy(hl_plan_t plan);
+
+/* Sizes and the time step the plan uses. */
+hl_status hl_plan_info(hl_plan_t plan, hl_info* out);
+
+/* Convert host FP64 data (host layout) to the device layout and precision,
+ * writing device buffers p (p_words) and u (u_words).  p0 must be non-NULL;
+ * u0 == NULL means zero velocity.
+ * flags == 0:               u0 holds u at t0 + dt/2 (Sec. 2: staggered data).
+ * flags & HL_INIT_STARTUP:  u0 holds u at t0; u at t0 + dt/2 is built on the
+ *                           device from the odd Taylor terms over dt/2
+ *                           (velocity half-step with halved weights; the
+ *                           even terms of u0 are dropped, exact for u0 = 0).
+ * Synchronous: returns after the data are on the device. */
+#define HL_INIT_STARTUP 1u
+hl_status hl_init(hl_plan_t plan, const double* p0, const double* u0, uint32_t flags,
+                  void* p, void* u, void* stream);
+
+/* Copy device state back to host FP64 arrays in host layout.  Either output
+ * may be NULL to skip it.  Synchronous (waits for work on the stream). */
+hl_status hl_export(hl_plan_t plan, const void* p, const void* u,
+                    double* p_out, double* u_out, void* stream);
+
+/* Advance (P^n, U^{n+1/2}) to (P^{n+nsteps}, U^{n+nsteps+1/2}) in place:
+ * nsteps times a pressure half-step (Sec. 3.1.2, eq. (pdup)) followed by a
+ * velocity half-step (eq. (vdup)).  nsteps >= 0.  Asynchronous. */
+hl_status hl_step(hl_plan_t plan, void* p, void* u, int64_t nsteps, void* stream);
+
+/* One pressure half-step P <- P - sum_k w_k kappa^{k+1} Lap^k div I(U).
+ * Asynchronous.  p and u must not alias. */
+hl_status hl_p_half(hl_plan_t plan, void* p, const void* u, void* stream);
+
+/* One velocity half-step U <- U - s * sum_k w_k kappa^k grad Lap^k I(P),
+ * s = weight_scale (1 for the scheme, 0.5 for the start-up).  Asynchronous. */
+hl_status hl_u_half(hl_plan_t plan, void* u, const void* p, double weight_scale, void* stream);
+
+/* Diagnostics (off the stepping path): out[0] = sum of squares of p,
+ * out[1] = sum of squares of u, accumulated in FP64 on the device; out is a
+ * host array of 2 doubles.  Returns HL_ERR_NONFINITE if either is not
+ * finite.  Synchronous. */
+hl_status hl_norms(hl_plan_t plan, const void* p, const void* u, double* out);
+
+/* Discrete adjoint of hl_step (gradient of a misfit with respect to kappa).
+ * Not built yet: always returns HL_ERR_UNSUPPORTED. */
+hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* p,
+                          const void* u, void* grad_kappa, int64_t nsteps, void* stream);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* hl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HL_H */

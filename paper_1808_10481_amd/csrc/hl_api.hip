@@ -1,0 +1,636 @@
+// hl_api.cpp - C ABI of the Hermite-leapfrog library: validation, operator
+// tables, host<->device layout conversion, stepping and diagnostics.
+//
+// Operator tables (built once per plan, FP64, then cast to the plan
+// precision):
+//  * H_m = [C^L; C^R]^{-1} (Sec. 2, eq. (interp)), by exact rational
+//    Gauss-Jordan elimination; C_{ls} = binom(s, l) xi0^{s-l}, xi0 = -+1/2.
+//  * the weight operators of the leapfrog difference with Cauchy-Kowalevsky
+//    exchange (Sec. 2, eqs. (update1), (final1); Sec. 3.1.2, eqs. (pdup),
+//    (vdup)): with w_k = 2 (dt/2)^{2k+1} / (2k+1)!,
+//      pressure:   W_p   = sum_k w_k kappa^{k+1} Lap^k      (divergence folded
+//                                                            into the passes)
+//      velocity i: W_u,i = sum_k w_k kappa^k D_i Lap^k
+//    as coefficient-space operators on the cell polynomial, restricted to
+//    output coefficients s in {0..m}^d (the new nodal data are the Taylor
+//    coefficients at the node, Sec. 2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "hl.h"
+#include "hl_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hl_status fail(hl_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+hl_status hip_fail(hipError_t e, const char* where) {
+  return fail(HL_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Exact rationals for H_m (entries are small; __int128 with gcd reduction).
+// ---------------------------------------------------------------------------
+struct Rat {
+  __int128 n = 0, d = 1;
+};
+__int128 gcd128(__int128 a, __int128 b) {
+  if (a < 0) a = -a;
+  if (b < 0) b = -b;
+  while (b) {
+    __int128 t = a % b;
+    a = b;
+    b = t;
+  }
+  return a ? a : 1;
+}
+Rat mk(__int128 n, __int128 d) {
+  if (d < 0) n = -n, d = -d;
+  const __int128 g = gcd128(n, d);
+  return Rat{n / g, d / g};
+}
+Rat add(Rat a, Rat b) { return mk(a.n * b.d + b.n * a.d, a.d * b.d); }
+Rat sub(Rat a, Rat b) { return mk(a.n * b.d - b.n * a.d, a.d * b.d); }
+Rat mul(Rat a, Rat b) { return mk(a.n * b.n, a.d * b.d); }
+Rat dvd(Rat a, Rat b) { return mk(a.n * b.d, a.d * b.n); }
+double to_double(Rat a) { return (double)(long double)a.n / (double)(long double)a.d; }
+
+long long binom(int n, int k) {
+  long long r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// H[s][col], s = 0..2m+1, col = (L_0..L_m, R_0..R_m).
+std::vector<double> hermite_matrix(int m) {
+  const int n = 2 * m + 2;
+  std::vector<Rat> A(n * 2 * n);
+  for (int side = 0; side < 2; ++side) {
+    const Rat xi0 = mk(side ? 1 : -1, 2);
+    for (int l = 0; l <= m; ++l)
+      for (int s = l; s < n; ++s) {
+        Rat pw = mk(1, 1);
+        for (int q = 0; q < s - l; ++q) pw = mul(pw, xi0);
+        A[(side * (m + 1) + l) * 2 * n + s] = mul(mk(binom(s, l), 1), pw);
+      }
+  }
+  for (int r = 0; r < n; ++r) A[r * 2 * n + n + r] = mk(1, 1);
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    while (A[piv * 2 * n + col].n == 0) ++piv;
+    if (piv != col)
+      for (int c = 0; c < 2 * n; ++c) std::swap(A[piv * 2 * n + c], A[col * 2 * n + c]);
+    const Rat pv = A[col * 2 * n + col];
+    for (int c = 0; c < 2 * n; ++c) A[col * 2 * n + c] = dvd(A[col * 2 * n + c], pv);
+    for (int r = 0; r < n; ++r) {
+      if (r == col || A[r * 2 * n + col].n == 0) continue;
+      const Rat f = A[r * 2 * n + col];
+      for (int c = 0; c < 2 * n; ++c) A[r * 2 * n + c] = sub(A[r * 2 * n + c], mul(f, A[col * 2 * n + c]));
+    }
+  }
+  std::vector<double> H(n * n);
+  for (int s = 0; s < n; ++s)
+    for (int c = 0; c < n; ++c) H[s * n + c] = to_double(A[s * 2 * n + n + c]);
+  return H;
+}
+
+// ---------------------------------------------------------------------------
+// Coefficient-space polynomial operators on (2m+2)^d dense arrays, index
+// b = b_1 + N2 (b_2 + N2 b_3).
+// ---------------------------------------------------------------------------
+struct PolyOps {
+  int d, N2, size;
+  double h[3];
+  int stride(int k) const { return k == 0 ? 1 : (k == 1 ? N2 : N2 * N2); }
+  int dig(int b, int k) const { return (b / stride(k)) % N2; }
+  // D_k: (D_k c)_b = (b_k + 1) c_{b + e_k} / h_k
+  std::vector<double> deriv(const std::vector<double>& c, int k) const {
+    std::vector<double> o(size, 0.0);
+    for (int b = 0; b < size; ++b) {
+      const int bk = dig(b, k);
+      if (bk + 1 < N2) o[b] = (bk + 1) * c[b + stride(k)] / h[k];
+    }
+    return o;
+  }
+  std::vector<double> lap(const std::vector<double>& c) const {
+    std::vector<double> o(size, 0.0);
+    for (int k = 0; k < d; ++k) {
+      std::vector<double> t = deriv(deriv(c, k), k);
+      for (int b = 0; b < size; ++b) o[b] += t[b];
+    }
+    return o;
+  }
+};
+
+bool all_zero(const std::vector<double>& v) {
+  for (double x : v)
+    if (x != 0.0) return false;
+  return true;
+}
+
+// W[s][beta] for s in {0..m}^d (index s_1 + MP (s_2 + MP s_3)) and beta in
+// {0..2m+1}^d: the coefficient of xi^s in  sum_k c_k Lap^k (D_i) xi^beta,
+// c_k = w_k kappa^{k + kshift} * scale.  deriv = -1: no D_i.
+std::vector<double> weight_operator(const PolyOps& P, int m, double dt, double kappa, int kshift, int deriv) {
+  const int MP = m + 1;
+  int NC = 1;
+  for (int k = 0; k < P.d; ++k) NC *= MP;
+  std::vector<double> W((size_t)NC * P.size, 0.0);
+  for (int beta = 0; beta < P.size; ++beta) {
+    std::vector<double> term(P.size, 0.0), acc(P.size, 0.0);
+    term[beta] = 1.0;
+    if (deriv >= 0) term = P.deriv(term, deriv);
+    double fact = 1.0;  // (2k+1)!
+    for (int k = 0; !all_zero(term); ++k) {
+      if (k > 0) fact *= (double)(2 * k) * (double)(2 * k + 1);
+      const double wk = 2.0 * std::pow(dt / 2.0, 2 * k + 1) / fact;
+      const double ck = wk * std::pow(kappa, k + kshift);
+      for (int b = 0; b < P.size; ++b) acc[b] += ck * term[b];
+      term = P.lap(term);
+    }
+    for (int s = 0; s < NC; ++s) {
+      int b = 0;
+      for (int k = 0; k < P.d; ++k) b += ((s / (k == 0 ? 1 : (k == 1 ? MP : MP * MP))) % MP) * P.stride(k);
+      W[(size_t)s * P.size + beta] = acc[b];
+    }
+  }
+  return W;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct hl_plan_s {
+  hl_problem prob;
+  int d, m, precision, nc, word_bytes;
+  double dt, nu, kappa, h[3];
+  hl::Grid grid;
+  hl::KernelSet ks;
+  void* dtab = nullptr;
+  double* dpartial = nullptr;  // norms scratch
+  int device = 0;
+};
+
+namespace {
+
+constexpr int kNormBlocks = 1024;
+
+int max_m(int d) { return d == 1 ? 7 : (d == 2 ? 5 : 3); }
+
+// Build every table of the plan into host FP64 memory (packed as the kernels
+// read it, hl_layout.hpp).
+hl_status build_tables(hl_plan_s* pl, std::vector<double>& tab) {
+  const int d = pl->d, m = pl->m, MP = m + 1, N2 = 2 * m + 2;
+  const hl::KernelSet& ks = pl->ks;
+  tab.assign(ks.table_words, 0.0);
+  const std::vector<double> H = hermite_matrix(m);  // [s][L.., R..]
+  // pass tables: G[b][l] = H[b][R_l] (kind 0), (b+1)/h_k H[b+1][R_l] (kind 1+k)
+  for (int b = 0; b < N2; ++b)
+    for (int l = 0; l < MP; ++l) tab[b * MP + l] = H[b * N2 + MP + l];
+  for (int k = 0; k < d; ++k)
+    for (int b = 0; b + 1 < N2; ++b)
+      for (int l = 0; l < MP; ++l)
+        tab[(1 + k) * ks.pass_words + b * MP + l] = (b + 1) * H[(b + 1) * N2 + MP + l] / pl->h[k];
+
+  // Last-dimension pass in left/right form: Glr[b][e][l], e = 0 left, 1 right.
+  // The pass uses sigma_l (R + L) when b + l + flip is even, delta_l (R - L)
+  // otherwise; check that H has exactly that symmetry.
+  auto glr = [&](int b, int e, int l, bool dH) -> double {
+    const int k = d - 1;
+    double g;
+    if (!dH)
+      g = H[b * N2 + MP + l];
+    else
+      g = (b + 1 < N2) ? (b + 1) * H[(b + 1) * N2 + MP + l] / pl->h[k] : 0.0;
+    const int flip = dH ? 1 : 0;
+    if (e == 1) return g;
+    return ((b + l + flip) & 1) ? -g : g;
+  };
+  for (int b = 0; b < N2; ++b)
+    for (int l = 0; l < MP; ++l) {
+      const double L = H[b * N2 + l], R = H[b * N2 + MP + l];
+      const double want = ((b + l) & 1) ? -R : R;
+      if (L != want) return fail(HL_ERR_ARG, "internal: interpolation matrix lacks the +-1/2 symmetry");
+    }
+
+  PolyOps P;
+  P.d = d;
+  P.N2 = N2;
+  P.size = 1;
+  for (int k = 0; k < d; ++k) P.size *= N2;
+  for (int k = 0; k < 3; ++k) P.h[k] = pl->h[k];
+  int NC = 1, NB = 1;
+  for (int k = 0; k < d; ++k) NC *= MP;
+  for (int k = 0; k + 1 < d; ++k) NB *= N2;
+  const int stride_last = (d == 1) ? 1 : (d == 2 ? N2 : N2 * N2);
+
+  // Pack a merged table: M[eL][l][s][b] = sum_bL W[s][b + bL*stride] Glr[bL][eL][l]
+  // over the structurally nonzero (s, b); verify the rest is zero.
+  auto pack = [&](const std::vector<double>& W, int deriv_dim, bool dH_last, int off) -> hl_status {
+    int t = off;
+    for (int eL = 0; eL < 2; ++eL)
+      for (int l = 0; l < MP; ++l)
+        for (int s = 0; s < NC; ++s)
+          for (int b = 0; b < NB; ++b) {
+            double v = 0.0;
+            for (int bL = 0; bL < N2; ++bL) v += W[(size_t)s * P.size + b + bL * stride_last] * glr(bL, eL, l, dH_last);
+            bool valid = true;
+            for (int k = 0; k + 1 < d; ++k) {
+              const int sk = (s / (k == 0 ? 1 : MP)) % MP;
+              const int bk = (b / (k == 0 ? 1 : N2)) % N2;
+              const int r = bk - sk - (deriv_dim == k ? 1 : 0);
+              if (r < 0 || (r & 1)) valid = false;
+            }
+            if (valid)
+              tab[t++] = v;
+            else if (v != 0.0)
+              return fail(HL_ERR_ARG, "internal: merged table has a nonzero outside its pattern");
+          }
+    return HL_OK;
+  };
+  const std::vector<double> Wp = weight_operator(P, m, pl->dt, pl->kappa, 1, -1);
+  hl_status st;
+  if (d > 1 && (st = pack(Wp, -1, false, ks.p_a_off)) != HL_OK) return st;
+  if ((st = pack(Wp, -1, true, ks.p_b_off)) != HL_OK) return st;
+  for (int i = 0; i < d; ++i) {
+    const std::vector<double> Wu = weight_operator(P, m, pl->dt, pl->kappa, 0, i);
+    if ((st = pack(Wu, i, false, ks.u_off[i])) != HL_OK) return st;
+  }
+  return HL_OK;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// host layout offset of (node j, coefficient a) -> device offset
+struct LayoutMap {
+  int d, MP, nc;
+  int64_t K[3], nodes;
+  template <typename F>
+  void for_each(F&& f) const {
+    // host: ((j1 K2 + j2) K3 + j3) * nc + ((a1 MP + a2) MP + a3)
+    // device: c * nodes + n, n = j1 + K1 (j2 + K2 j3), c = a1 + MP (a2 + MP a3)
+    const int64_t K1 = K[0], K2 = d > 1 ? K[1] : 1, K3 = d > 2 ? K[2] : 1;
+    const int nthreads = (int)std::max<unsigned>(1, std::min<unsigned>(16, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int w = 0; w < nthreads; ++w)
+      th.emplace_back([&, w]() {
+        for (int64_t j1 = w; j1 < K1; j1 += nthreads)
+          for (int64_t j2 = 0; j2 < K2; ++j2)
+            for (int64_t j3 = 0; j3 < K3; ++j3) {
+              const int64_t hbase = ((j1 * K2 + j2) * K3 + j3) * nc;
+              const int64_t n = j1 + K1 * (j2 + K2 * j3);
+              for (int ha = 0; ha < nc; ++ha) {
+                // host coefficient index ha = (a1 MP + a2) MP + a3 (a1 slowest)
+                int a[3] = {0, 0, 0}, r = ha;
+                for (int k = d - 1; k >= 0; --k) {
+                  a[k] = r % MP;
+                  r /= MP;
+                }
+                const int c = a[0] + MP * (a[1] + MP * a[2]);
+                f(hbase + ha, (int64_t)c * nodes + n);
+              }
+            }
+      });
+    for (auto& t : th) t.join();
+  }
+};
+
+LayoutMap layout_of(const hl_plan_s* pl) {
+  LayoutMap L;
+  L.d = pl->d;
+  L.MP = pl->m + 1;
+  L.nc = pl->nc;
+  for (int k = 0; k < 3; ++k) L.K[k] = pl->grid.K[k];
+  L.nodes = pl->grid.nodes;
+  return L;
+}
+
+template <typename T>
+hl_status upload_field(const hl_plan_s* pl, const double* host, int ncomp, void* dev, hipStream_t s) {
+  const LayoutMap L = layout_of(pl);
+  const int64_t fw = (int64_t)pl->nc * pl->grid.nodes;
+  std::vector<T> buf;
+  try {
+    buf.resize((size_t)fw);
+  } catch (const std::bad_alloc&) {
+    return fail(HL_ERR_NOMEM, "hl_init: host staging allocation failed");
+  }
+  for (int i = 0; i < ncomp; ++i) {
+    const double* src = host ? host + (size_t)i * fw : nullptr;
+    if (src)
+      L.for_each([&](int64_t h, int64_t dv) { buf[dv] = (T)src[h]; });
+    else
+      std::fill(buf.begin(), buf.end(), T(0));
+    hipError_t e = hipMemcpyAsync((T*)dev + (size_t)i * fw, buf.data(), (size_t)fw * sizeof(T), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hl_init: copy to device");
+  }
+  return HL_OK;
+}
+
+template <typename T>
+hl_status download_field(const hl_plan_s* pl, const void* dev, int ncomp, double* host, hipStream_t s) {
+  const LayoutMap L = layout_of(pl);
+  const int64_t fw = (int64_t)pl->nc * pl->grid.nodes;
+  std::vector<T> buf;
+  try {
+    buf.resize((size_t)fw);
+  } catch (const std::bad_alloc&) {
+    return fail(HL_ERR_NOMEM, "hl_export: host staging allocation failed");
+  }
+  for (int i = 0; i < ncomp; ++i) {
+    hipError_t e = hipMemcpyAsync(buf.data(), (const T*)dev + (size_t)i * fw, (size_t)fw * sizeof(T), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hl_export: copy to host");
+    double* dst = host + (size_t)i * fw;
+    L.for_each([&](int64_t h, int64_t dv) { dst[h] = (double)buf[dv]; });
+  }
+  return HL_OK;
+}
+
+hl::PlanView view(const hl_plan_s* pl) {
+  hl::PlanView v;
+  v.grid = pl->grid;
+  v.tab = pl->dtab;
+  v.d = pl->d;
+  v.m = pl->m;
+  v.precision = pl->precision;
+  return v;
+}
+
+hl_status check_plan(const hl_plan_s* pl, const char* who) {
+  if (!pl) return fail(HL_ERR_ARG, std::string(who) + ": plan is NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl->device)
+    return fail(HL_ERR_DEVICE, std::string(who) + ": current HIP device differs from the plan's device");
+  return HL_OK;
+}
+
+// FP64 sum of squares, per-block partials (deterministic order on the host).
+template <typename T>
+__global__ void sumsq_kernel(const T* __restrict__ x, int64_t n, double* __restrict__ partial) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = (double)x[i];
+    acc = fma(v, v, acc);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+template <typename T>
+hl_status sumsq(const hl_plan_s* pl, const void* x, int64_t n, double* out) {
+  hipLaunchKernelGGL(sumsq_kernel<T>, dim3(kNormBlocks), dim3(256), 0, 0, (const T*)x, n, pl->dpartial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "hl_norms: launch");
+  std::vector<double> part(kNormBlocks);
+  e = hipMemcpy(part.data(), pl->dpartial, kNormBlocks * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hl_norms: copy");
+  double s = 0.0;
+  for (double v : part) s += v;
+  *out = s;
+  return HL_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* hl_last_error(void) { return g_last_error.c_str(); }
+
+hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
+  g_last_error.clear();
+  if (!prob || !out) return fail(HL_ERR_ARG, "hl_plan: NULL argument");
+  const hl_problem& p = *prob;
+  if (p.reserved != 0) return fail(HL_ERR_ARG, "hl_plan: reserved field must be 0");
+  if (p.d < 1 || p.d > 3) return fail(HL_ERR_ARG, "hl_plan: d must be 1, 2 or 3");
+  if (p.m < 0) return fail(HL_ERR_ARG, "hl_plan: m must be >= 0");
+  if (p.m > max_m(p.d)) return fail(HL_ERR_UNSUPPORTED, "hl_plan: m too large for this dimension");
+  if (p.precision != HL_FP64 && p.precision != HL_FP32) return fail(HL_ERR_ARG, "hl_plan: unknown precision");
+  if (!finite_pos(p.c)) return fail(HL_ERR_ARG, "hl_plan: c must be finite and > 0");
+  double hmin = INFINITY;
+  int64_t nodes = 1;
+  for (int k = 0; k < p.d; ++k) {
+    if (p.cells[k] < 2 || p.cells[k] > (int64_t)INT32_MAX) return fail(HL_ERR_ARG, "hl_plan: cells must be in [2, 2^31)");
+    if (!finite_pos(p.length[k])) return fail(HL_ERR_ARG, "hl_plan: length must be finite and > 0");
+    hmin = std::min(hmin, p.length[k] / (double)p.cells[k]);
+    nodes *= p.cells[k];
+  }
+  if (p.d > 1 && p.cells[1] > 4 * 65535LL) return fail(HL_ERR_UNSUPPORTED, "hl_plan: cells[1] too large for the launch grid");
+  if (p.d > 2 && p.cells[2] > 65535LL) return fail(HL_ERR_UNSUPPORTED, "hl_plan: cells[2] too large for the launch grid");
+  double dt = p.dt;
+  if (!std::isfinite(dt) || dt < 0.0) return fail(HL_ERR_ARG, "hl_plan: dt must be finite and >= 0");
+  if (dt == 0.0) {
+    if (!std::isfinite(p.cfl) || !(p.cfl > 0.0 && p.cfl < 1.0))
+      return fail(HL_ERR_CFL, "hl_plan: cfl must be in (0, 1) when dt == 0");
+    dt = p.cfl * hmin / p.c;
+  }
+  const double nu = p.c * dt / hmin;
+  if (!(nu > 0.0 && nu < 1.0)) return fail(HL_ERR_CFL, "hl_plan: c dt / min h must be in (0, 1)");
+
+  hl_plan_s* pl = new (std::nothrow) hl_plan_s();
+  if (!pl) return fail(HL_ERR_NOMEM, "hl_plan: out of host memory");
+  pl->prob = p;
+  pl->d = p.d;
+  pl->m = p.m;
+  pl->precision = p.precision;
+  pl->word_bytes = p.precision == HL_FP64 ? 8 : 4;
+  pl->dt = dt;
+  pl->nu = nu;
+  pl->kappa = p.c * p.c;
+  pl->nc = 1;
+  for (int k = 0; k < p.d; ++k) pl->nc *= (p.m + 1);
+  for (int k = 0; k < 3; ++k) {
+    pl->h[k] = k < p.d ? p.length[k] / (double)p.cells[k] : 1.0;
+    pl->grid.K[k] = k < p.d ? (int32_t)p.cells[k] : 1;
+  }
+  pl->grid.nodes = nodes;
+  bool ok = p.d == 1 ? hl::kernels_d1(p.m, p.precision, &pl->ks)
+                     : (p.d == 2 ? hl::kernels_d2(p.m, p.precision, &pl->ks) : hl::kernels_d3(p.m, p.precision, &pl->ks));
+  if (!ok) {
+    delete pl;
+    return fail(HL_ERR_UNSUPPORTED, "hl_plan: (d, m, precision) not built");
+  }
+  std::vector<double> tab;
+  hl_status st = build_tables(pl, tab);
+  if (st != HL_OK) {
+    delete pl;
+    return st;
+  }
+  hipError_t e = hipGetDevice(&pl->device);
+  if (e != hipSuccess) {
+    delete pl;
+    return hip_fail(e, "hl_plan: hipGetDevice");
+  }
+  const size_t bytes = tab.size() * pl->word_bytes;
+  e = hipMalloc(&pl->dtab, std::max<size_t>(bytes, 16));
+  if (e == hipSuccess) e = hipMalloc((void**)&pl->dpartial, kNormBlocks * sizeof(double));
+  if (e != hipSuccess) {
+    if (pl->dtab) (void)hipFree(pl->dtab);
+    delete pl;
+    return fail(HL_ERR_NOMEM, std::string("hl_plan: device allocation: ") + hipGetErrorString(e));
+  }
+  if (pl->precision == HL_FP64) {
+    e = hipMemcpy(pl->dtab, tab.data(), bytes, hipMemcpyHostToDevice);
+  } else {
+    std::vector<float> tf(tab.begin(), tab.end());
+    e = hipMemcpy(pl->dtab, tf.data(), bytes, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    (void)hipFree(pl->dtab);
+    (void)hipFree(pl->dpartial);
+    delete pl;
+    return hip_fail(e, "hl_plan: table upload");
+  }
+  *out = pl;
+  return HL_OK;
+}
+
+hl_status hl_plan_destroy(hl_plan_t plan) {
+  g_last_error.clear();
+  if (!plan) return HL_OK;
+  if (plan->dtab) (void)hipFree(plan->dtab);
+  if (plan->dpartial) (void)hipFree(plan->dpartial);
+  delete plan;
+  return HL_OK;
+}
+
+hl_status hl_plan_info(hl_plan_t plan, hl_info* out) {
+  g_last_error.clear();
+  if (!plan || !out) return fail(HL_ERR_ARG, "hl_plan_info: NULL argument");
+  out->dt = plan->dt;
+  out->nu = plan->nu;
+  out->nodes = plan->grid.nodes;
+  out->nc = plan->nc;
+  out->word_bytes = plan->word_bytes;
+  out->p_words = (int64_t)plan->nc * plan->grid.nodes;
+  out->u_words = (int64_t)plan->d * plan->nc * plan->grid.nodes;
+  return HL_OK;
+}
+
+hl_status hl_init(hl_plan_t plan, const double* p0, const double* u0, uint32_t flags, void* p, void* u,
+                  void* stream) {
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_init");
+  if (st != HL_OK) return st;
+  if (!p0 || !p || !u) return fail(HL_ERR_ARG, "hl_init: p0, p and u must be non-NULL");
+  if (flags & ~HL_INIT_STARTUP) return fail(HL_ERR_ARG, "hl_init: unknown flags");
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->precision == HL_FP64) {
+    if ((st = upload_field<double>(plan, p0, 1, p, s)) != HL_OK) return st;
+    if ((st = upload_field<double>(plan, u0, plan->d, u, s)) != HL_OK) return st;
+  } else {
+    if ((st = upload_field<float>(plan, p0, 1, p, s)) != HL_OK) return st;
+    if ((st = upload_field<float>(plan, u0, plan->d, u, s)) != HL_OK) return st;
+  }
+  if (flags & HL_INIT_STARTUP) {
+    hipError_t e = plan->ks.u_half(view(plan), u, p, 0.5, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hl_init: start-up half-step");
+  }
+  return HL_OK;
+}
+
+hl_status hl_export(hl_plan_t plan, const void* p, const void* u, double* p_out, double* u_out, void* stream) {
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_export");
+  if (st != HL_OK) return st;
+  if ((p_out && !p) || (u_out && !u)) return fail(HL_ERR_ARG, "hl_export: NULL device buffer");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hl_export: pending work failed");
+  if (plan->precision == HL_FP64) {
+    if (p_out && (st = download_field<double>(plan, p, 1, p_out, s)) != HL_OK) return st;
+    if (u_out && (st = download_field<double>(plan, u, plan->d, u_out, s)) != HL_OK) return st;
+  } else {
+    if (p_out && (st = download_field<float>(plan, p, 1, p_out, s)) != HL_OK) return st;
+    if (u_out && (st = download_field<float>(plan, u, plan->d, u_out, s)) != HL_OK) return st;
+  }
+  return HL_OK;
+}
+
+hl_status hl_p_half(hl_plan_t plan, void* p, const void* u, void* stream) {
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_p_half");
+  if (st != HL_OK) return st;
+  if (!p || !u || p == u) return fail(HL_ERR_ARG, "hl_p_half: p and u must be distinct non-NULL buffers");
+  hipError_t e = plan->ks.p_half(view(plan), p, u, (hipStream_t)stream);
+  return e == hipSuccess ? HL_OK : hip_fail(e, "hl_p_half: launch");
+}
+
+hl_status hl_u_half(hl_plan_t plan, void* u, const void* p, double weight_scale, void* stream) {
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_u_half");
+  if (st != HL_OK) return st;
+  if (!p || !u || p == u) return fail(HL_ERR_ARG, "hl_u_half: p and u must be distinct non-NULL buffers");
+  if (!std::isfinite(weight_scale)) return fail(HL_ERR_ARG, "hl_u_half: weight_scale must be finite");
+  hipError_t e = plan->ks.u_half(view(plan), u, p, weight_scale, (hipStream_t)stream);
+  return e == hipSuccess ? HL_OK : hip_fail(e, "hl_u_half: launch");
+}
+
+hl_status hl_step(hl_plan_t plan, void* p, void* u, int64_t nsteps, void* stream) {
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_step");
+  if (st != HL_OK) return st;
+  if (!p || !u || p == u) return fail(HL_ERR_ARG, "hl_step: p and u must be distinct non-NULL buffers");
+  if (nsteps < 0) return fail(HL_ERR_ARG, "hl_step: nsteps must be >= 0");
+  const hl::PlanView v = view(plan);
+  hipStream_t s = (hipStream_t)stream;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    hipError_t e = plan->ks.p_half(v, p, u, s);
+    if (e == hipSuccess) e = plan->ks.u_half(v, u, p, 1.0, s);
+    if (e != hipSuccess) return hip_fail(e, "hl_step: launch");
+  }
+  return HL_OK;
+}
+
+hl_status hl_norms(hl_plan_t plan, const void* p, const void* u, double* out) {
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_norms");
+  if (st != HL_OK) return st;
+  if (!p || !u || !out) return fail(HL_ERR_ARG, "hl_norms: NULL argument");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hl_norms: pending work failed");
+  const int64_t pw = (int64_t)plan->nc * plan->grid.nodes;
+  if (plan->precision == HL_FP64) {
+    if ((st = sumsq<double>(plan, p, pw, &out[0])) != HL_OK) return st;
+    if ((st = sumsq<double>(plan, u, pw * plan->d, &out[1])) != HL_OK) return st;
+  } else {
+    if ((st = sumsq<float>(plan, p, pw, &out[0])) != HL_OK) return st;
+    if ((st = sumsq<float>(plan, u, pw * plan->d, &out[1])) != HL_OK) return st;
+  }
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1])) return fail(HL_ERR_NONFINITE, "hl_norms: non-finite state");
+  return HL_OK;
+}
+
+hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* p, const void* u,
+                          void* grad_kappa, int64_t nsteps, void* stream) {
+  (void)plan, (void)p_bar, (void)u_bar, (void)p, (void)u, (void)grad_kappa, (void)nsteps, (void)stream;
+  return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: the adjoint is not built");
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// hl_internal.hpp - plan object and kernel registry shared by the C ABI
+// (hl_api.cpp) and the per-dimension kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hl.h"
+#include "hl_kernels.hpp"
+
+namespace hl {
+
+// What a launcher needs from a plan.
+struct PlanView {
+  Grid grid;
+  const void* tab;      // packed operator tables in the plan precision
+  int d, m, precision;
+};
+
+typedef hipError_t (*PHalfFn)(const PlanView&, void* p, const void* u, hipStream_t);
+typedef hipError_t (*UHalfFn)(const PlanView&, void* u, const void* p, double wscale, hipStream_t);
+
+struct KernelSet {
+  PHalfFn p_half;
+  UHalfFn u_half;
+  int table_words;       // TableLayout<D, M>::TOTAL
+  int p_a_off, p_b_off;  // offsets of the pressure merged tables
+  int u_off[3];          // offsets of the velocity merged tables
+  int pass_words;        // one pass table
+};
+
+// Registries implemented by hl_kernels_d{1,2,3}.hip; return false when
+// (m, precision) is not built for that dimension.
+bool kernels_d1(int m, int precision, KernelSet* out);
+bool kernels_d2(int m, int precision, KernelSet* out);
+bool kernels_d3(int m, int precision, KernelSet* out);
+
+// Table layout queries for a (d, m) the registry supports.
+template <int D, int M>
+inline void fill_layout(KernelSet* ks) {
+  using TL = TableLayout<D, M>;
+  ks->table_words = TL::TOTAL;
+  ks->p_a_off = TL::P_A_OFF;
+  ks->p_b_off = TL::P_B_OFF;
+  for (int i = 0; i < 3; ++i) ks->u_off[i] = (i < D) ? TL::u_off(i) : -1;
+  ks->pass_words = TL::PASS;
+}
+
+template <int D>
+inline dim3 block_shape() {
+  return D == 1 ? dim3(256, 1, 1) : dim3(64, 4, 1);
+}
+
+template <int D>
+inline dim3 grid_shape(const Grid& g) {
+  const dim3 b = block_shape<D>();
+  return dim3((unsigned)((g.K[0] + b.x - 1) / b.x), (unsigned)((g.K[1] + b.y - 1) / b.y),
+              (unsigned)(D > 2 ? g.K[2] : 1));
+}
+
+template <int D, int M, typename T>
+hipError_t launch_p_generic(const PlanView& pv, void* p, const void* u, hipStream_t s) {
+  hipLaunchKernelGGL((p_half_kernel<D, M, T>), grid_shape<D>(pv.grid), block_shape<D>(), 0, s, (T*)p,
+                     (const T*)u, (const T*)pv.tab, pv.grid);
+  return hipGetLastError();
+}
+
+template <int D, int M, typename T>
+hipError_t launch_u_generic(const PlanView& pv, void* u, const void* p, double wscale, hipStream_t s) {
+  hipLaunchKernelGGL((u_half_kernel<D, M, T>), grid_shape<D>(pv.grid), block_shape<D>(), 0, s, (T*)u,
+                     (const T*)p, (const T*)pv.tab, pv.grid, (T)wscale);
+  return hipGetLastError();
+}
+
+template <int D, int M>
+inline bool make_set(int precision, KernelSet* out) {
+  fill_layout<D, M>(out);
+  if (precision == HL_FP64) {
+    out->p_half = &launch_p_generic<D, M, double>;
+    out->u_half = &launch_u_generic<D, M, double>;
+  } else {
+    out->p_half = &launch_p_generic<D, M, float>;
+    out->u_half = &launch_u_generic<D, M, float>;
+  }
+  return true;
+}
+
+}  // namespace hl

@@ -1,0 +1,209 @@
+"""Thin ctypes binding of libhermite_lf.so (C ABI in include/hl.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch provides device memory and streams.  Importing this module
+raises if the library has not been built (there is no CPU fallback).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhermite_lf.so")
+
+HL_OK, HL_ERR_ARG, HL_ERR_CFL, HL_ERR_UNSUPPORTED, HL_ERR_DEVICE, HL_ERR_NOMEM, HL_ERR_NONFINITE = range(7)
+HL_FP64, HL_FP32 = 0, 1
+HL_INIT_STARTUP = 1
+
+STATUS_NAMES = {0: "HL_OK", 1: "HL_ERR_ARG", 2: "HL_ERR_CFL", 3: "HL_ERR_UNSUPPORTED",
+                4: "HL_ERR_DEVICE", 5: "HL_ERR_NOMEM", 6: "HL_ERR_NONFINITE"}
+
+# Every symbol include/hl.h declares.
+EXPORTS = ("hl_plan", "hl_plan_destroy", "hl_plan_info", "hl_init", "hl_export", "hl_step",
+           "hl_p_half", "hl_u_half", "hl_norms", "hl_adjoint_step", "hl_last_error")
+
+
+class HLProblem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("m", ctypes.c_int32), ("cells", ctypes.c_int64 * 3),
+                ("length", ctypes.c_double * 3), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("c", ctypes.c_double), ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class HLInfo(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("nu", ctypes.c_double), ("nodes", ctypes.c_int64),
+                ("nc", ctypes.c_int32), ("word_bytes", ctypes.c_int32), ("p_words", ctypes.c_int64),
+                ("u_words", ctypes.c_int64)]
+
+
+class HLError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() "
+                          "(python -m paper_1808_10481_amd.build)")
+    lib = ctypes.CDLL(path)
+    vp, i64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "hl_plan": ([ctypes.POINTER(HLProblem), ctypes.POINTER(vp)]),
+        "hl_plan_destroy": ([vp]),
+        "hl_plan_info": ([vp, ctypes.POINTER(HLInfo)]),
+        "hl_init": ([vp, vp, vp, ctypes.c_uint32, vp, vp, vp]),
+        "hl_export": ([vp, vp, vp, vp, vp, vp]),
+        "hl_step": ([vp, vp, vp, i64, vp]),
+        "hl_p_half": ([vp, vp, vp, vp]),
+        "hl_u_half": ([vp, vp, vp, dbl, vp]),
+        "hl_norms": ([vp, vp, vp, ctypes.POINTER(dbl)]),
+        "hl_adjoint_step": ([vp, vp, vp, vp, vp, vp, i64, vp]),
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.hl_last_error.argtypes = []
+    lib.hl_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def _check(status: int):
+    if status != HL_OK:
+        raise HLError(status, lib().hl_last_error().decode())
+
+
+def make_problem(d, m, cells, length=None, dt=0.0, cfl=0.5, c=1.0, precision="fp64") -> HLProblem:
+    cells = tuple(int(k) for k in cells)
+    length = tuple(float(v) for v in (length if length is not None else (1.0,) * d))
+    pr = HLProblem()
+    pr.d, pr.m = int(d), int(m)
+    for k in range(3):
+        pr.cells[k] = cells[k] if k < len(cells) else 1
+        pr.length[k] = length[k] if k < len(length) else 1.0
+    pr.dt, pr.cfl, pr.c = float(dt), float(cfl), float(c)
+    pr.precision = {"fp64": HL_FP64, "fp32": HL_FP32}[precision]
+    pr.reserved = 0
+    return pr
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A plan for one periodic problem; owns the library handle."""
+
+    def __init__(self, d, m, cells, length=None, dt=0.0, cfl=0.5, c=1.0, precision="fp64"):
+        self.problem = make_problem(d, m, cells, length, dt, cfl, c, precision)
+        self.d, self.m, self.precision = int(d), int(m), precision
+        self.cells = tuple(int(k) for k in cells)
+        h = ctypes.c_void_p()
+        _check(lib().hl_plan(ctypes.byref(self.problem), ctypes.byref(h)))
+        self._h = h
+        info = HLInfo()
+        _check(lib().hl_plan_info(self._h, ctypes.byref(info)))
+        self.info = info
+
+    @property
+    def dt(self):
+        return self.info.dt
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hl_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- device state ------------------------------------------------------
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def alloc(self, device="cuda"):
+        import torch
+        p = torch.empty(self.info.p_words, dtype=self.torch_dtype(), device=device)
+        u = torch.empty(self.info.u_words, dtype=self.torch_dtype(), device=device)
+        return p, u
+
+    def host_shapes(self):
+        pshape = self.cells + (self.m + 1,) * self.d
+        return pshape, (self.d,) + pshape
+
+    def init(self, p, u, p0, u0=None, startup=False, stream=None):
+        """p0, u0: FP64 host arrays in host layout (C order [j..][a..])."""
+        ps, us = self.host_shapes()
+        p0 = np.ascontiguousarray(p0, dtype=np.float64)
+        assert p0.shape == ps, (p0.shape, ps)
+        u0p = None
+        if u0 is not None:
+            u0 = np.ascontiguousarray(u0, dtype=np.float64)
+            assert u0.shape == us, (u0.shape, us)
+            u0p = u0.ctypes.data_as(ctypes.c_void_p)
+        self._check_buf(p, u)
+        _check(lib().hl_init(self._h, p0.ctypes.data_as(ctypes.c_void_p), u0p,
+                             HL_INIT_STARTUP if startup else 0, ctypes.c_void_p(p.data_ptr()),
+                             ctypes.c_void_p(u.data_ptr()), _stream_ptr(stream)))
+
+    def export(self, p, u, stream=None):
+        ps, us = self.host_shapes()
+        P = np.empty(ps, dtype=np.float64)
+        U = np.empty(us, dtype=np.float64)
+        self._check_buf(p, u)
+        _check(lib().hl_export(self._h, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                               P.ctypes.data_as(ctypes.c_void_p), U.ctypes.data_as(ctypes.c_void_p),
+                               _stream_ptr(stream)))
+        return P, U
+
+    def step(self, p, u, nsteps=1, stream=None):
+        self._check_buf(p, u)
+        _check(lib().hl_step(self._h, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                             int(nsteps), _stream_ptr(stream)))
+
+    def p_half(self, p, u, stream=None):
+        self._check_buf(p, u)
+        _check(lib().hl_p_half(self._h, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                               _stream_ptr(stream)))
+
+    def u_half(self, u, p, weight_scale=1.0, stream=None):
+        self._check_buf(p, u)
+        _check(lib().hl_u_half(self._h, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(p.data_ptr()),
+                               float(weight_scale), _stream_ptr(stream)))
+
+    def norms(self, p, u):
+        out = (ctypes.c_double * 2)()
+        self._check_buf(p, u)
+        _check(lib().hl_norms(self._h, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(u.data_ptr()), out))
+        return out[0], out[1]
+
+    def _check_buf(self, p, u):
+        if not (p.is_cuda and u.is_cuda):
+            raise ValueError("state buffers must be device tensors")
+        if p.dtype != self.torch_dtype() or u.dtype != self.torch_dtype():
+            raise ValueError("state dtype does not match the plan precision")
+        if p.numel() < self.info.p_words or u.numel() < self.info.u_words:
+            raise ValueError("state buffers are smaller than the plan's state")
+        if not (p.is_contiguous() and u.is_contiguous()):
+            raise ValueError("state buffers must be contiguous")
