@@ -199,34 +199,21 @@ hl_status build_tables(hl_plan_s* pl, std::vector<double>& tab) {
   const hl::KernelSet& ks = pl->ks;
   tab.assign(ks.table_words, 0.0);
   const std::vector<double> H = hermite_matrix(m);  // [s][L.., R..]
-  // pass tables: G[b][l] = H[b][R_l] (kind 0), (b+1)/h_k H[b+1][R_l] (kind 1+k)
-  for (int b = 0; b < N2; ++b)
-    for (int l = 0; l < MP; ++l) tab[b * MP + l] = H[b * N2 + MP + l];
-  for (int k = 0; k < d; ++k)
-    for (int b = 0; b + 1 < N2; ++b)
-      for (int l = 0; l < MP; ++l)
-        tab[(1 + k) * ks.pass_words + b * MP + l] = (b + 1) * H[(b + 1) * N2 + MP + l] / pl->h[k];
-
-  // Last-dimension pass in left/right form: Glr[b][e][l], e = 0 left, 1 right.
-  // The pass uses sigma_l (R + L) when b + l + flip is even, delta_l (R - L)
-  // otherwise; check that H has exactly that symmetry.
-  auto glr = [&](int b, int e, int l, bool dH) -> double {
-    const int k = d - 1;
-    double g;
-    if (!dH)
-      g = H[b * N2 + MP + l];
-    else
-      g = (b + 1 < N2) ? (b + 1) * H[(b + 1) * N2 + MP + l] / pl->h[k] : 0.0;
-    const int flip = dH ? 1 : 0;
-    if (e == 1) return g;
-    return ((b + l + flip) & 1) ? -g : g;
-  };
+  // The kernels rely on the +-1/2 symmetry H[b][L_l] = (-1)^{b+l} H[b][R_l]
+  // (sigma/delta form of every pass); check it exactly.
   for (int b = 0; b < N2; ++b)
     for (int l = 0; l < MP; ++l) {
       const double L = H[b * N2 + l], R = H[b * N2 + MP + l];
       const double want = ((b + l) & 1) ? -R : R;
       if (L != want) return fail(HL_ERR_ARG, "internal: interpolation matrix lacks the +-1/2 symmetry");
     }
+  // Last-dimension pass coefficient on sigma_l / delta_l: H[b][R_l], or for the
+  // derivative pass (b + 1) H[b + 1][R_l] / h_last.
+  const int kL = d - 1;
+  auto glast = [&](int b, int l, bool dH) -> double {
+    if (!dH) return H[b * N2 + MP + l];
+    return (b + 1 < N2) ? (b + 1) * H[(b + 1) * N2 + MP + l] / pl->h[kL] : 0.0;
+  };
 
   PolyOps P;
   P.d = d;
@@ -239,37 +226,50 @@ hl_status build_tables(hl_plan_s* pl, std::vector<double>& tab) {
   for (int k = 0; k + 1 < d; ++k) NB *= N2;
   const int stride_last = (d == 1) ? 1 : (d == 2 ? N2 : N2 * N2);
 
-  // Pack a merged table: M[eL][l][s][b] = sum_bL W[s][b + bL*stride] Glr[bL][eL][l]
-  // over the structurally nonzero (s, b); verify the rest is zero.
-  auto pack = [&](const std::vector<double>& W, int deriv_dim, bool dH_last, int off) -> hl_status {
+  // Pack a merged table (sigma/delta form):
+  //   M[l][s][b] = scale * sum_bL W[s][b + bL * stride] glast(bL, l)
+  // over the structurally nonzero (s, b); verify the rest is zero and that
+  // every contributing bL has the sigma/delta selector the kernel assumes.
+  auto pack = [&](const std::vector<double>& W, int deriv_dim, bool dH_last, double scale, int off) -> hl_status {
     int t = off;
-    for (int eL = 0; eL < 2; ++eL)
-      for (int l = 0; l < MP; ++l)
-        for (int s = 0; s < NC; ++s)
-          for (int b = 0; b < NB; ++b) {
-            double v = 0.0;
-            for (int bL = 0; bL < N2; ++bL) v += W[(size_t)s * P.size + b + bL * stride_last] * glr(bL, eL, l, dH_last);
-            bool valid = true;
-            for (int k = 0; k + 1 < d; ++k) {
-              const int sk = (s / (k == 0 ? 1 : MP)) % MP;
-              const int bk = (b / (k == 0 ? 1 : N2)) % N2;
-              const int r = bk - sk - (deriv_dim == k ? 1 : 0);
-              if (r < 0 || (r & 1)) valid = false;
-            }
-            if (valid)
-              tab[t++] = v;
-            else if (v != 0.0)
-              return fail(HL_ERR_ARG, "internal: merged table has a nonzero outside its pattern");
+    const int flip = dH_last ? 1 : 0;
+    for (int l = 0; l < MP; ++l)
+      for (int s = 0; s < NC; ++s) {
+        const int sL = (s / (kL == 0 ? 1 : (kL == 1 ? MP : MP * MP))) % MP;
+        const int sel = (sL + (deriv_dim == kL ? 1 : 0) + l + flip) & 1;
+        for (int b = 0; b < NB; ++b) {
+          double v = 0.0;
+          for (int bL = 0; bL < N2; ++bL) {
+            const double w = W[(size_t)s * P.size + b + bL * stride_last];
+            if (w == 0.0) continue;
+            if (((bL + l + flip) & 1) != sel)
+              return fail(HL_ERR_ARG, "internal: merged table mixes sigma and delta terms");
+            v += w * glast(bL, l, dH_last);
           }
+          v *= scale;
+          bool valid = true;
+          for (int k = 0; k + 1 < d; ++k) {
+            const int sk = (s / (k == 0 ? 1 : MP)) % MP;
+            const int bk = (b / (k == 0 ? 1 : N2)) % N2;
+            const int r = bk - sk - (deriv_dim == k ? 1 : 0);
+            if (r < 0 || (r & 1)) valid = false;
+          }
+          if (valid)
+            tab[t++] = v;
+          else if (v != 0.0)
+            return fail(HL_ERR_ARG, "internal: merged table has a nonzero outside its pattern");
+        }
+      }
     return HL_OK;
   };
   const std::vector<double> Wp = weight_operator(P, m, pl->dt, pl->kappa, 1, -1);
   hl_status st;
-  if (d > 1 && (st = pack(Wp, -1, false, ks.p_a_off)) != HL_OK) return st;
-  if ((st = pack(Wp, -1, true, ks.p_b_off)) != HL_OK) return st;
+  // group A: the slice passes give the x-derivative in units of 1/h_x
+  if (d > 1 && (st = pack(Wp, -1, false, 1.0 / pl->h[0], ks.p_a_off)) != HL_OK) return st;
+  if ((st = pack(Wp, -1, true, 1.0, ks.p_b_off)) != HL_OK) return st;
   for (int i = 0; i < d; ++i) {
     const std::vector<double> Wu = weight_operator(P, m, pl->dt, pl->kappa, 0, i);
-    if ((st = pack(Wu, i, false, ks.u_off[i])) != HL_OK) return st;
+    if ((st = pack(Wu, i, false, 1.0, ks.u_off[i])) != HL_OK) return st;
   }
   return HL_OK;
 }
@@ -370,6 +370,7 @@ hl::PlanView view(const hl_plan_s* pl) {
   v.d = pl->d;
   v.m = pl->m;
   v.precision = pl->precision;
+  v.r01 = pl->d > 1 ? pl->h[0] / pl->h[1] : 1.0;
   return v;
 }
 
@@ -440,8 +441,6 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
     hmin = std::min(hmin, p.length[k] / (double)p.cells[k]);
     nodes *= p.cells[k];
   }
-  if (p.d > 1 && p.cells[1] > 4 * 65535LL) return fail(HL_ERR_UNSUPPORTED, "hl_plan: cells[1] too large for the launch grid");
-  if (p.d > 2 && p.cells[2] > 65535LL) return fail(HL_ERR_UNSUPPORTED, "hl_plan: cells[2] too large for the launch grid");
   double dt = p.dt;
   if (!std::isfinite(dt) || dt < 0.0) return fail(HL_ERR_ARG, "hl_plan: dt must be finite and >= 0");
   if (dt == 0.0) {
@@ -469,11 +468,28 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
     pl->grid.K[k] = k < p.d ? (int32_t)p.cells[k] : 1;
   }
   pl->grid.nodes = nodes;
+  if ((double)nodes * pl->word_bytes >= 4294967296.0) {
+    delete pl;
+    return fail(HL_ERR_UNSUPPORTED, "hl_plan: one coefficient plane must stay below 4 GiB");
+  }
   bool ok = p.d == 1 ? hl::kernels_d1(p.m, p.precision, &pl->ks)
                      : (p.d == 2 ? hl::kernels_d2(p.m, p.precision, &pl->ks) : hl::kernels_d3(p.m, p.precision, &pl->ks));
   if (!ok) {
     delete pl;
     return fail(HL_ERR_UNSUPPORTED, "hl_plan: (d, m, precision) not built");
+  }
+  {
+    const int tx = pl->ks.tile[0], ty = pl->ks.tile[1];
+    pl->grid.nt[0] = (pl->grid.K[0] + tx - 1) / tx;
+    pl->grid.nt[1] = (pl->grid.K[1] + ty - 1) / ty;
+    pl->grid.nt[2] = pl->grid.K[2];
+    const int64_t tiles = (int64_t)pl->grid.nt[0] * pl->grid.nt[1] * pl->grid.nt[2];
+    if (tiles > (int64_t)INT32_MAX / 2) {
+      delete pl;
+      return fail(HL_ERR_UNSUPPORTED, "hl_plan: grid too large for the launch");
+    }
+    pl->grid.tiles = (int32_t)tiles;
+    pl->grid.per_xcd = (int32_t)((tiles + hl::kXcds - 1) / hl::kXcds);
   }
   std::vector<double> tab;
   hl_status st = build_tables(pl, tab);

@@ -15,6 +15,7 @@ struct PlanView {
   Grid grid;
   const void* tab;      // packed operator tables in the plan precision
   int d, m, precision;
+  double r01;           // h_x / h_y (3D pressure half-step)
 };
 
 typedef hipError_t (*PHalfFn)(const PlanView&, void* p, const void* u, hipStream_t);
@@ -26,7 +27,7 @@ struct KernelSet {
   int table_words;       // TableLayout<D, M>::TOTAL
   int p_a_off, p_b_off;  // offsets of the pressure merged tables
   int u_off[3];          // offsets of the velocity merged tables
-  int pass_words;        // one pass table
+  int tile[2];           // tile extent in x and y (z extent 1)
 };
 
 // Registries implemented by hl_kernels_d{1,2,3}.hip; return false when
@@ -43,31 +44,27 @@ inline void fill_layout(KernelSet* ks) {
   ks->p_a_off = TL::P_A_OFF;
   ks->p_b_off = TL::P_B_OFF;
   for (int i = 0; i < 3; ++i) ks->u_off[i] = (i < D) ? TL::u_off(i) : -1;
-  ks->pass_words = TL::PASS;
+  ks->tile[0] = TileShape<D>::X;
+  ks->tile[1] = TileShape<D>::Y;
 }
 
 template <int D>
 inline dim3 block_shape() {
-  return D == 1 ? dim3(256, 1, 1) : dim3(64, 4, 1);
+  return dim3(TileShape<D>::X, TileShape<D>::Y, 1);
 }
 
-template <int D>
-inline dim3 grid_shape(const Grid& g) {
-  const dim3 b = block_shape<D>();
-  return dim3((unsigned)((g.K[0] + b.x - 1) / b.x), (unsigned)((g.K[1] + b.y - 1) / b.y),
-              (unsigned)(D > 2 ? g.K[2] : 1));
-}
+inline dim3 grid_shape(const Grid& g) { return dim3((unsigned)(g.per_xcd * kXcds), 1, 1); }
 
 template <int D, int M, typename T>
 hipError_t launch_p_generic(const PlanView& pv, void* p, const void* u, hipStream_t s) {
-  hipLaunchKernelGGL((p_half_kernel<D, M, T>), grid_shape<D>(pv.grid), block_shape<D>(), 0, s, (T*)p,
-                     (const T*)u, (const T*)pv.tab, pv.grid);
+  hipLaunchKernelGGL((p_half_kernel<D, M, T>), grid_shape(pv.grid), block_shape<D>(), 0, s, (T*)p,
+                     (const T*)u, (const T*)pv.tab, pv.grid, (T)pv.r01);
   return hipGetLastError();
 }
 
 template <int D, int M, typename T>
 hipError_t launch_u_generic(const PlanView& pv, void* u, const void* p, double wscale, hipStream_t s) {
-  hipLaunchKernelGGL((u_half_kernel<D, M, T>), grid_shape<D>(pv.grid), block_shape<D>(), 0, s, (T*)u,
+  hipLaunchKernelGGL((u_half_kernel<D, M, T>), grid_shape(pv.grid), block_shape<D>(), 0, s, (T*)u,
                      (const T*)p, (const T*)pv.tab, pv.grid, (T)wscale);
   return hipGetLastError();
 }

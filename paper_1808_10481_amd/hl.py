@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhermite_lf.so")
+# HL_LIBRARY overrides the library path (e.g. a differently tuned build).
+LIB_PATH = os.environ.get("HL_LIBRARY", os.path.join(_HERE, "libhermite_lf.so"))
 
 HL_OK, HL_ERR_ARG, HL_ERR_CFL, HL_ERR_UNSUPPORTED, HL_ERR_DEVICE, HL_ERR_NOMEM, HL_ERR_NONFINITE = range(7)
 HL_FP64, HL_FP32 = 0, 1
