@@ -26,8 +26,8 @@
  *     valid until the next call on the same thread).
  *   - Arguments are validated on the host before anything is launched.
  *   - Device pointers (p, u, ...) are caller-owned device memory of
- *     hl_state_words() words of hl_info.word_bytes bytes each, in the
- *     library's device layout (below).  The caller owns the stream; a NULL
+ *     hl_info.p_words / hl_info.u_words words of hl_info.word_bytes bytes
+ *     each (hl_plan_info), in the library's device layout (below).  The caller owns the stream; a NULL
  *     stream is the default stream.  hl_step, hl_p_half and hl_u_half are
  *     asynchronous on that stream; hl_init and hl_export are synchronous.
  *   - The plan owns its operator tables and scratch; it must outlive the
@@ -42,6 +42,8 @@
  * Device layout (opaque to callers, fixed per plan): coefficient-major
  * planes, p[c][n] and u[i][c][n], with node n = j_1 + K_1 (j_2 + K_2 j_3)
  * and coefficient c = a_1 + (m+1)(a_2 + (m+1) a_3), in the plan precision.
+ * Size limit (HL_ERR_UNSUPPORTED beyond it): one coefficient plane below
+ * 4 GiB, i.e. fewer than 2^30 nodes in FP32 and 2^29 in FP64.
  */
 #ifndef HL_H
 #define HL_H
@@ -125,7 +127,11 @@ hl_status hl_export(hl_plan_t plan, const void* p, const void* u,
 
 /* Advance (P^n, U^{n+1/2}) to (P^{n+nsteps}, U^{n+nsteps+1/2}) in place:
  * nsteps times a pressure half-step (Sec. 3.1.2, eq. (pdup)) followed by a
- * velocity half-step (eq. (vdup)).  nsteps >= 0.  Asynchronous. */
+ * velocity half-step (eq. (vdup)).  nsteps >= 0.  Asynchronous.
+ * For nsteps >= 16 the steps are replayed from a HIP graph of 16 steps that
+ * the plan captures (on a stream of its own) for the last (p, u) pair it was
+ * given; a new pair re-captures.  A plan is not safe to use from several
+ * host threads at once. */
 hl_status hl_step(hl_plan_t plan, void* p, void* u, int64_t nsteps, void* stream);
 
 /* One pressure half-step P <- P - sum_k w_k kappa^{k+1} Lap^k div I(U).

@@ -141,35 +141,6 @@ bool all_zero(const std::vector<double>& v) {
   return true;
 }
 
-// W[s][beta] for s in {0..m}^d (index s_1 + MP (s_2 + MP s_3)) and beta in
-// {0..2m+1}^d: the coefficient of xi^s in  sum_k c_k Lap^k (D_i) xi^beta,
-// c_k = w_k kappa^{k + kshift} * scale.  deriv = -1: no D_i.
-std::vector<double> weight_operator(const PolyOps& P, int m, double dt, double kappa, int kshift, int deriv) {
-  const int MP = m + 1;
-  int NC = 1;
-  for (int k = 0; k < P.d; ++k) NC *= MP;
-  std::vector<double> W((size_t)NC * P.size, 0.0);
-  for (int beta = 0; beta < P.size; ++beta) {
-    std::vector<double> term(P.size, 0.0), acc(P.size, 0.0);
-    term[beta] = 1.0;
-    if (deriv >= 0) term = P.deriv(term, deriv);
-    double fact = 1.0;  // (2k+1)!
-    for (int k = 0; !all_zero(term); ++k) {
-      if (k > 0) fact *= (double)(2 * k) * (double)(2 * k + 1);
-      const double wk = 2.0 * std::pow(dt / 2.0, 2 * k + 1) / fact;
-      const double ck = wk * std::pow(kappa, k + kshift);
-      for (int b = 0; b < P.size; ++b) acc[b] += ck * term[b];
-      term = P.lap(term);
-    }
-    for (int s = 0; s < NC; ++s) {
-      int b = 0;
-      for (int k = 0; k < P.d; ++k) b += ((s / (k == 0 ? 1 : (k == 1 ? MP : MP * MP))) % MP) * P.stride(k);
-      W[(size_t)s * P.size + beta] = acc[b];
-    }
-  }
-  return W;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -184,11 +155,52 @@ struct hl_plan_s {
   void* dtab = nullptr;
   double* dpartial = nullptr;  // norms scratch
   int device = 0;
+  // hl_step replays a captured graph of kGraphChunk steps for the last
+  // (p, u) pair it saw; the capture runs on a plan-owned stream and the graph
+  // is launched on the caller's stream.
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void* gp = nullptr;
+  const void* gu = nullptr;
 };
 
 namespace {
 
 constexpr int kNormBlocks = 1024;
+constexpr int64_t kGraphChunk = 16;   // steps per captured graph (32 kernel nodes)
+
+void drop_graph(hl_plan_s* pl) {
+  if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
+  pl->gexec = nullptr;
+  pl->gp = pl->gu = nullptr;
+}
+
+// Capture kGraphChunk steps for buffers (p, u) into pl->gexec.
+hipError_t capture_steps(hl_plan_s* pl, const hl::PlanView& v, void* p, void* u) {
+  hipError_t e = hipSuccess;
+  if (!pl->cap_stream) e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  drop_graph(pl);
+  e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t le = hipSuccess;
+  for (int64_t n = 0; n < kGraphChunk && le == hipSuccess; ++n) {
+    le = pl->ks.p_half(v, p, u, pl->cap_stream);
+    if (le == hipSuccess) le = pl->ks.u_half(v, u, p, 1.0, pl->cap_stream);
+  }
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(pl->cap_stream, &graph);
+  if (le != hipSuccess) e = le;
+  if (e == hipSuccess) e = hipGraphInstantiate(&pl->gexec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e == hipSuccess) {
+    pl->gp = p;
+    pl->gu = u;
+  } else {
+    pl->gexec = nullptr;
+  }
+  return e;
+}
 
 int max_m(int d) { return d == 1 ? 7 : (d == 2 ? 5 : 3); }
 
@@ -226,21 +238,48 @@ hl_status build_tables(hl_plan_s* pl, std::vector<double>& tab) {
   for (int k = 0; k + 1 < d; ++k) NB *= N2;
   const int stride_last = (d == 1) ? 1 : (d == 2 ? N2 : N2 * N2);
 
+  // Output sets: pressure s in {0..m}^d (digits base m+1); velocity: the set
+  // G of Q (digits in {0..m+1}, at most one equal to m+1, not all zero).
+  std::vector<std::vector<int>> out_p, out_g;
+  {
+    int total = 1;
+    for (int k = 0; k < d; ++k) total *= (m + 2);
+    for (int s = 0; s < NC; ++s) {
+      std::vector<int> dg(d);
+      for (int k = 0, r = s; k < d; ++k, r /= MP) dg[k] = r % MP;
+      out_p.push_back(dg);
+    }
+    for (int x = 0; x < total; ++x) {
+      std::vector<int> dg(d);
+      int top = 0, nz = 0;
+      for (int k = 0, r = x; k < d; ++k, r /= (m + 2)) {
+        dg[k] = r % (m + 2);
+        top += dg[k] == m + 1;
+        nz += dg[k] != 0;
+      }
+      if (top <= 1 && nz > 0) out_g.push_back(dg);
+    }
+  }
+  if ((int)out_g.size() != ks.ng) return fail(HL_ERR_ARG, "internal: velocity output set size mismatch");
+
   // Pack a merged table (sigma/delta form):
-  //   M[l][s][b] = scale * sum_bL W[s][b + bL * stride] glast(bL, l)
-  // over the structurally nonzero (s, b); verify the rest is zero and that
+  //   M[l][o][b] = scale * sum_bL W(o, (b, bL)) glast(bL, l)
+  // over the structurally nonzero (o, b); verify the rest is zero and that
   // every contributing bL has the sigma/delta selector the kernel assumes.
-  auto pack = [&](const std::vector<double>& W, int deriv_dim, bool dH_last, double scale, int off) -> hl_status {
+  // W(o, beta) = coefficient of xi^o in sum_k c_k Lap^k xi^beta.
+  auto pack = [&](const std::vector<double>& W, const std::vector<std::vector<int>>& outs, bool dH_last,
+                  double scale, int off) -> hl_status {
     int t = off;
     const int flip = dH_last ? 1 : 0;
     for (int l = 0; l < MP; ++l)
-      for (int s = 0; s < NC; ++s) {
-        const int sL = (s / (kL == 0 ? 1 : (kL == 1 ? MP : MP * MP))) % MP;
-        const int sel = (sL + (deriv_dim == kL ? 1 : 0) + l + flip) & 1;
+      for (size_t o = 0; o < outs.size(); ++o) {
+        const int sel = (outs[o][kL] + l + flip) & 1;
+        int orow = 0;  // row of W: o as an index in {0..2m+1}^d
+        for (int k = d - 1; k >= 0; --k) orow = orow * N2 + outs[o][k];
         for (int b = 0; b < NB; ++b) {
           double v = 0.0;
           for (int bL = 0; bL < N2; ++bL) {
-            const double w = W[(size_t)s * P.size + b + bL * stride_last];
+            const double w = W[(size_t)orow * P.size + b + bL * stride_last];
             if (w == 0.0) continue;
             if (((bL + l + flip) & 1) != sel)
               return fail(HL_ERR_ARG, "internal: merged table mixes sigma and delta terms");
@@ -249,9 +288,8 @@ hl_status build_tables(hl_plan_s* pl, std::vector<double>& tab) {
           v *= scale;
           bool valid = true;
           for (int k = 0; k + 1 < d; ++k) {
-            const int sk = (s / (k == 0 ? 1 : MP)) % MP;
             const int bk = (b / (k == 0 ? 1 : N2)) % N2;
-            const int r = bk - sk - (deriv_dim == k ? 1 : 0);
+            const int r = bk - outs[o][k];
             if (r < 0 || (r & 1)) valid = false;
           }
           if (valid)
@@ -262,15 +300,76 @@ hl_status build_tables(hl_plan_s* pl, std::vector<double>& tab) {
       }
     return HL_OK;
   };
-  const std::vector<double> Wp = weight_operator(P, m, pl->dt, pl->kappa, 1, -1);
+  // W as a full (2m+2)^d x (2m+2)^d operator, rows = output coefficient.
+  auto full_operator = [&](int kshift) {
+    std::vector<double> W((size_t)P.size * P.size, 0.0);
+    for (int beta = 0; beta < P.size; ++beta) {
+      std::vector<double> term(P.size, 0.0), acc(P.size, 0.0);
+      term[beta] = 1.0;
+      double fact = 1.0;
+      for (int k = 0; !all_zero(term); ++k) {
+        if (k > 0) fact *= (double)(2 * k) * (double)(2 * k + 1);
+        const double ck = 2.0 * std::pow(pl->dt / 2.0, 2 * k + 1) / fact * std::pow(pl->kappa, k + kshift);
+        for (int b = 0; b < P.size; ++b) acc[b] += ck * term[b];
+        term = P.lap(term);
+      }
+      for (int b = 0; b < P.size; ++b) W[(size_t)b * P.size + beta] = acc[b];
+    }
+    return W;
+  };
+  const std::vector<double> Wp = full_operator(1);   // sum_k w_k kappa^{k+1} Lap^k
+  const std::vector<double> Wq = full_operator(0);   // sum_k w_k kappa^k Lap^k
   hl_status st;
-  // group A: the slice passes give the x-derivative in units of 1/h_x
-  if (d > 1 && (st = pack(Wp, -1, false, 1.0 / pl->h[0], ks.p_a_off)) != HL_OK) return st;
-  if ((st = pack(Wp, -1, true, 1.0, ks.p_b_off)) != HL_OK) return st;
-  for (int i = 0; i < d; ++i) {
-    const std::vector<double> Wu = weight_operator(P, m, pl->dt, pl->kappa, 0, i);
-    if ((st = pack(Wu, i, false, 1.0, ks.u_off[i])) != HL_OK) return st;
+  if (d == 3) {
+    // 3D: explicit x pass, y and z merged into the table:
+    //   M[a_y, a_z][o][b_x] = scale * sum_{b_y, b_z} W(o, b) gy(b_y, a_y) gz(b_z, a_z)
+    // with gy / gz the sigma/delta pass coefficients (derivative pass for the
+    // component along that dimension).
+    auto gdim = [&](int k, int b, int a, int dH) -> double {
+      if (!dH) return H[b * N2 + MP + a];
+      return (b + 1 < N2) ? (b + 1) * H[(b + 1) * N2 + MP + a] / pl->h[k] : 0.0;
+    };
+    int t_end = 0;
+    auto pack3 = [&](const std::vector<double>& W, const std::vector<std::vector<int>>& outs, int fy, int fz,
+                     double scale, int off) -> hl_status {
+      int t = off;
+      for (int az = 0; az < MP; ++az)
+        for (int ay = 0; ay < MP; ++ay)
+          for (size_t o = 0; o < outs.size(); ++o) {
+            const int ox = outs[o][0], oy = outs[o][1], oz = outs[o][2];
+            const int orow = ox + N2 * (oy + N2 * oz);
+            const int ky = (oy + ay + fy) & 1, kz = (oz + az + fz) & 1;
+            for (int bx = 0; bx < N2; ++bx) {
+              double v = 0.0;
+              for (int bz = 0; bz < N2; ++bz)
+                for (int by = 0; by < N2; ++by) {
+                  const double w = W[(size_t)orow * P.size + bx + N2 * (by + N2 * bz)];
+                  if (w == 0.0) continue;
+                  if (((by + ay + fy) & 1) != ky || ((bz + az + fz) & 1) != kz)
+                    return fail(HL_ERR_ARG, "internal: 3D merged table mixes sigma and delta terms");
+                  v += w * gdim(1, by, ay, fy) * gdim(2, bz, az, fz);
+                }
+              v *= scale;
+              if (bx >= ox && ((bx - ox) & 1) == 0)
+                tab[t++] = v;
+              else if (v != 0.0)
+                return fail(HL_ERR_ARG, "internal: 3D merged table has a nonzero outside its pattern");
+            }
+          }
+      t_end = t;
+      return HL_OK;
+    };
+    if ((st = pack3(Wp, out_p, 0, 0, 1.0 / pl->h[0], ks.p_off[0])) != HL_OK) return st;
+    if ((st = pack3(Wp, out_p, 1, 0, 1.0, ks.p_off[1])) != HL_OK) return st;
+    if ((st = pack3(Wp, out_p, 0, 1, 1.0, ks.p_off[2])) != HL_OK) return st;
+    if ((st = pack3(Wq, out_g, 0, 0, 1.0, ks.u_off)) != HL_OK) return st;
+    if (t_end != ks.table_words) return fail(HL_ERR_ARG, "internal: 3D table size mismatch");
+    return HL_OK;
   }
+  // x-component (2D): the slice pass gives the x-derivative in units of 1/h_x
+  if (d > 1 && (st = pack(Wp, out_p, false, 1.0 / pl->h[0], ks.p_off[0])) != HL_OK) return st;
+  if ((st = pack(Wp, out_p, true, 1.0, ks.p_off[d - 1])) != HL_OK) return st;
+  if ((st = pack(Wq, out_g, false, 1.0, ks.u_off)) != HL_OK) return st;
   return HL_OK;
 }
 
@@ -370,7 +469,7 @@ hl::PlanView view(const hl_plan_s* pl) {
   v.d = pl->d;
   v.m = pl->m;
   v.precision = pl->precision;
-  v.r01 = pl->d > 1 ? pl->h[0] / pl->h[1] : 1.0;
+  for (int k = 0; k < 3; ++k) v.ih[k] = 1.0 / pl->h[k];
   return v;
 }
 
@@ -479,10 +578,10 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
     return fail(HL_ERR_UNSUPPORTED, "hl_plan: (d, m, precision) not built");
   }
   {
-    const int tx = pl->ks.tile[0], ty = pl->ks.tile[1];
+    const int tx = pl->ks.tile[0], ty = pl->ks.tile[1], tz = pl->ks.tile[2];
     pl->grid.nt[0] = (pl->grid.K[0] + tx - 1) / tx;
     pl->grid.nt[1] = (pl->grid.K[1] + ty - 1) / ty;
-    pl->grid.nt[2] = pl->grid.K[2];
+    pl->grid.nt[2] = (pl->grid.K[2] + tz - 1) / tz;
     const int64_t tiles = (int64_t)pl->grid.nt[0] * pl->grid.nt[1] * pl->grid.nt[2];
     if (tiles > (int64_t)INT32_MAX / 2) {
       delete pl;
@@ -529,6 +628,8 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
 hl_status hl_plan_destroy(hl_plan_t plan) {
   g_last_error.clear();
   if (!plan) return HL_OK;
+  drop_graph(plan);
+  if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   if (plan->dtab) (void)hipFree(plan->dtab);
   if (plan->dpartial) (void)hipFree(plan->dpartial);
   delete plan;
@@ -616,7 +717,18 @@ hl_status hl_step(hl_plan_t plan, void* p, void* u, int64_t nsteps, void* stream
   if (nsteps < 0) return fail(HL_ERR_ARG, "hl_step: nsteps must be >= 0");
   const hl::PlanView v = view(plan);
   hipStream_t s = (hipStream_t)stream;
-  for (int64_t n = 0; n < nsteps; ++n) {
+  int64_t n = 0;
+  if (nsteps >= kGraphChunk) {
+    if (!plan->gexec || plan->gp != p || plan->gu != u) {
+      hipError_t e = capture_steps(plan, v, p, u);
+      if (e != hipSuccess) return hip_fail(e, "hl_step: graph capture");
+    }
+    for (; n + kGraphChunk <= nsteps; n += kGraphChunk) {
+      hipError_t e = hipGraphLaunch(plan->gexec, s);
+      if (e != hipSuccess) return hip_fail(e, "hl_step: graph launch");
+    }
+  }
+  for (; n < nsteps; ++n) {
     hipError_t e = plan->ks.p_half(v, p, u, s);
     if (e == hipSuccess) e = plan->ks.u_half(v, u, p, 1.0, s);
     if (e != hipSuccess) return hip_fail(e, "hl_step: launch");

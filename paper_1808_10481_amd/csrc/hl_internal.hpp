@@ -15,7 +15,7 @@ struct PlanView {
   Grid grid;
   const void* tab;      // packed operator tables in the plan precision
   int d, m, precision;
-  double r01;           // h_x / h_y (3D pressure half-step)
+  double ih[3];         // 1 / h_k (velocity half-step)
 };
 
 typedef hipError_t (*PHalfFn)(const PlanView&, void* p, const void* u, hipStream_t);
@@ -25,9 +25,10 @@ struct KernelSet {
   PHalfFn p_half;
   UHalfFn u_half;
   int table_words;       // TableLayout<D, M>::TOTAL
-  int p_a_off, p_b_off;  // offsets of the pressure merged tables
-  int u_off[3];          // offsets of the velocity merged tables
-  int tile[2];           // tile extent in x and y (z extent 1)
+  int p_off[3];          // offsets of the pressure merged tables, per component
+  int u_off;             // offset of the velocity (Q) merged table
+  int ng;                // size of the velocity output set G
+  int tile[3];           // tile extent in x, y and z
 };
 
 // Registries implemented by hl_kernels_d{1,2,3}.hip; return false when
@@ -41,11 +42,12 @@ template <int D, int M>
 inline void fill_layout(KernelSet* ks) {
   using TL = TableLayout<D, M>;
   ks->table_words = TL::TOTAL;
-  ks->p_a_off = TL::P_A_OFF;
-  ks->p_b_off = TL::P_B_OFF;
-  for (int i = 0; i < 3; ++i) ks->u_off[i] = (i < D) ? TL::u_off(i) : -1;
+  for (int i = 0; i < 3; ++i) ks->p_off[i] = i < D ? TL::p_off(i) : -1;
+  ks->u_off = TL::U_OFF;
+  ks->ng = GSet<D, M>::NG;
   ks->tile[0] = TileShape<D>::X;
   ks->tile[1] = TileShape<D>::Y;
+  ks->tile[2] = TileShape<D>::Z;
 }
 
 template <int D>
@@ -57,15 +59,24 @@ inline dim3 grid_shape(const Grid& g) { return dim3((unsigned)(g.per_xcd * kXcds
 
 template <int D, int M, typename T>
 hipError_t launch_p_generic(const PlanView& pv, void* p, const void* u, hipStream_t s) {
-  hipLaunchKernelGGL((p_half_kernel<D, M, T>), grid_shape(pv.grid), block_shape<D>(), 0, s, (T*)p,
-                     (const T*)u, (const T*)pv.tab, pv.grid, (T)pv.r01);
+  if constexpr (D == 3)
+    hipLaunchKernelGGL((p_half_3d<M, T>), grid_shape(pv.grid), block_shape<D>(), 0, s, (T*)p, (const T*)u,
+                       (const T*)pv.tab, pv.grid);
+  else
+    hipLaunchKernelGGL((p_half_kernel<D, M, T>), grid_shape(pv.grid), block_shape<D>(), 0, s, (T*)p,
+                       (const T*)u, (const T*)pv.tab, pv.grid);
   return hipGetLastError();
 }
 
 template <int D, int M, typename T>
 hipError_t launch_u_generic(const PlanView& pv, void* u, const void* p, double wscale, hipStream_t s) {
-  hipLaunchKernelGGL((u_half_kernel<D, M, T>), grid_shape(pv.grid), block_shape<D>(), 0, s, (T*)u,
-                     (const T*)p, (const T*)pv.tab, pv.grid, (T)wscale);
+  if constexpr (D == 3)
+    hipLaunchKernelGGL((u_half_3d<M, T>), grid_shape(pv.grid), block_shape<D>(), 0, s, (T*)u, (const T*)p,
+                       (const T*)pv.tab, pv.grid, (T)wscale, (T)pv.ih[0], (T)pv.ih[1], (T)pv.ih[2]);
+  else
+    hipLaunchKernelGGL((u_half_kernel<D, M, T>), grid_shape(pv.grid), block_shape<D>(), 0, s, (T*)u,
+                       (const T*)p, (const T*)pv.tab, pv.grid, (T)wscale, (T)pv.ih[0], (T)pv.ih[1],
+                       (T)pv.ih[2]);
   return hipGetLastError();
 }
 

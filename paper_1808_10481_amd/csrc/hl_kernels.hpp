@@ -56,6 +56,7 @@ template <int D>
 struct TileShape {
   static constexpr int X = D == 1 ? 256 : 64;
   static constexpr int Y = D == 1 ? 1 : 4;
+  static constexpr int Z = 1;
 };
 
 // out[b] = sum_l pass_coef<M,FLIP>(b, l) * (b + l + FLIP even ? R_l + L_l : R_l - L_l)
@@ -89,13 +90,14 @@ __device__ __forceinline__ T ld(const T* __restrict__ f, int64_t plane_words, in
 }
 
 // Slice of the interpolant for last-dimension corner eL and last-dimension
-// datum l: Y[b], b in {0..2m+1}^{d-1}, from the 2^{d-1} corners with that eL.
-// FLIPk = 1 makes transverse pass k the derivative pass (units of 1/h_k).
-// cb[e]: byte offset of corner e inside a coefficient plane.
+// datum l (1D and 2D kernels): Y[b], b in {0..2m+1}^{d-1}, from the 2^{d-1}
+// corners with that eL.  FLIP0 = 1 makes the x pass the derivative pass
+// (units of 1/h_x).  cb[e]: byte offset of corner e inside a coefficient plane.
 template <int D, int M, int FLIP0, int FLIP1, typename T>
 __device__ __forceinline__ void slice(const T* __restrict__ f, int64_t nodes, const uint32_t* cb, int eL, int l,
                                       T* Y) {
-  constexpr int MP = M + 1, N2 = 2 * M + 2;
+  constexpr int MP = M + 1;
+  static_assert(D == 1 || D == 2, "3D uses the x-line kernels");
   if constexpr (D == 1) {
     Y[0] = ld(f, nodes, l, cb[eL]);
   } else if constexpr (D == 2) {
@@ -107,57 +109,50 @@ __device__ __forceinline__ void slice(const T* __restrict__ f, int64_t nodes, co
       Rv[a0] = ld(f, nodes, c, cb[1 + 2 * eL]);
     }
     pass1d<M, FLIP0>(Lv, Rv, Y);
-  } else {
-    T Z[2][MP][N2];  // [e1][a1][b0]
-#pragma unroll
-    for (int e1 = 0; e1 < 2; ++e1)
-#pragma unroll
-      for (int a1 = 0; a1 < MP; ++a1) {
-        T Lv[MP], Rv[MP];
-#pragma unroll
-        for (int a0 = 0; a0 < MP; ++a0) {
-          const int c = a0 + MP * (a1 + MP * l);
-          Lv[a0] = ld(f, nodes, c, cb[0 + 2 * e1 + 4 * eL]);
-          Rv[a0] = ld(f, nodes, c, cb[1 + 2 * e1 + 4 * eL]);
-        }
-        pass1d<M, FLIP0>(Lv, Rv, Z[e1][a1]);
-      }
-#pragma unroll
-    for (int b0 = 0; b0 < N2; ++b0) {
-      T Lv[MP], Rv[MP], out[N2];
-#pragma unroll
-      for (int a1 = 0; a1 < MP; ++a1) {
-        Lv[a1] = Z[0][a1][b0];
-        Rv[a1] = Z[1][a1][b0];
-      }
-      pass1d<M, FLIP1>(Lv, Rv, out);
-#pragma unroll
-      for (int b1 = 0; b1 < N2; ++b1) Y[b0 + N2 * b1] = out[b1];
-    }
   }
 }
 
-// acc[s] += sum_b Mt[t] * (sigma or delta)[b] over the structurally nonzero
-// (s, b) of one merged table row-block (datum l).  t is a compile-time
-// constant once the loops are unrolled.
-template <int D, int M, int DD, int FLIPL, typename T>
+// acc[o] += sum_b Mt[t] * (sigma or delta)[b] over the structurally nonzero
+// (o, b) of one merged table row-block (datum l); the walk comes from the
+// compile-time MergeSpec, so every index is a constant after unrolling.
+template <int D, int M, bool VEL, int FLIPL, typename T>
 __device__ __forceinline__ void merge(const T* __restrict__ Mt, int l, const T* S, const T* Df, T* acc) {
-  using Dm = Dims<D, M>;
+  using Sp = MergeSpec<D, M, VEL, FLIPL>;
   // Scalar table loads are consumed in chunks: without the barriers the
   // scheduler hoists every s_load of the table to the top of the kernel and
   // runs out of SGPRs (spilling them through VGPR lanes).
   constexpr int kChunk = sizeof(T) == 8 ? 16 : 32;
-  int t = 0;
 #pragma unroll
-  for (int s = 0; s < Dm::NC; ++s) {
-    const bool dl = merged_uses_delta<D, M>(DD, FLIPL, s, l);
+  for (int t = 0; t < Sp::NNZ; ++t) {
+    if (t % kChunk == 0) __builtin_amdgcn_sched_barrier(HL_SCHED_MASK);
+    const int o = kMerge<D, M, VEL, FLIPL>.o[t];
+    const int b = kMerge<D, M, VEL, FLIPL>.b[t];
+    const bool dl = kMerge<D, M, VEL, FLIPL>.base_delta[o] != ((l & 1) != 0);
+    acc[o] = fma(Mt[t], dl ? Df[b] : S[b], acc[o]);
+  }
+}
+
+// Plane form of the merge (z-march kernels): t_o = sum_b Mt * Y[b] is the
+// plane's contribution through the table; it adds to the cell for which the
+// plane is the upper corner (accR, + t) and to the cell for which it is the
+// lower corner (accL, + t for sigma entries, - t for delta entries).  The
+// table walk is ordered by output, so t_o is complete when o changes.
+template <int D, int M, bool VEL, int FLIPL, bool DO_R, bool DO_L, typename T, typename TP>
+__device__ __forceinline__ void merge_plane(TP Mt, int l, const T* Y, T* accR, T* accL) {
+  using Sp = MergeSpec<D, M, VEL, FLIPL>;
+  constexpr int kChunk = sizeof(T) == 8 ? 16 : 32;
+  T acc = T(0);
 #pragma unroll
-    for (int b = 0; b < Dm::NB; ++b)
-      if (merged_valid<D, M>(DD, s, b)) {
-        if (t % kChunk == 0) __builtin_amdgcn_sched_barrier(HL_SCHED_MASK);
-        acc[s] = fma(Mt[t], dl ? Df[b] : S[b], acc[s]);
-        ++t;
-      }
+  for (int t = 0; t < Sp::NNZ; ++t) {
+    if (t % kChunk == 0) __builtin_amdgcn_sched_barrier(HL_SCHED_MASK);
+    const int o = kMerge<D, M, VEL, FLIPL>.o[t];
+    acc = fma(Mt[t], Y[kMerge<D, M, VEL, FLIPL>.b[t]], acc);
+    if (t + 1 == Sp::NNZ || kMerge<D, M, VEL, FLIPL>.o[t + 1] != o) {
+      const bool dl = kMerge<D, M, VEL, FLIPL>.base_delta[o] != ((l & 1) != 0);
+      if (DO_R) accR[o] += acc;
+      if (DO_L) accL[o] += dl ? -acc : acc;
+      acc = T(0);
+    }
   }
 }
 
@@ -184,17 +179,15 @@ __device__ __forceinline__ uint32_t node_index(int32_t x, int32_t y, int32_t z, 
   return n;
 }
 
-// Pressure half-step at every primal node.
-// tab: packed merged tables (hl_layout.hpp TableLayout).  r01 = h_x / h_y
-// scales the y-component's slice into the units of group A, whose table
-// carries 1/h_x (3D only).
+// Pressure half-step at every primal node (1D and 2D).
+// tab: packed merged tables (hl_layout.hpp TableLayout).
 template <int D, int M, typename T>
 __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_kernel(T* __restrict__ p, const T* __restrict__ u,
-                                                      const T* __restrict__ tab, Grid g, T r01) {
+                                                                       const T* __restrict__ tab, Grid g) {
   using Dm = Dims<D, M>;
   using TL = TableLayout<D, M>;
   constexpr int MP = Dm::MP, NC = Dm::NC, NB = Dm::NB;
-  constexpr int NNZ = merged_nnz<D, M>(-1);
+  constexpr int NNZ = merged_nnz<D, M>(false);
   int32_t j[3];
   if (!node_of_thread<D>(g, j)) return;
   int32_t lo[3], hi[3];
@@ -218,31 +211,20 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_kernel(T* __restr
 #pragma unroll
   for (int l = 0; l < MP; ++l) {
     if constexpr (D > 1) {
-      // group A: components 0..d-2 with the derivative pass in their own
-      // dimension; last pass H
+      // x-component: derivative pass in x; last pass H
       T YL[NB], YR[NB];
       slice<D, M, 1, 0>(u, nodes, cb, 0, l, YL);
       slice<D, M, 1, 0>(u, nodes, cb, 1, l, YR);
-      if constexpr (D == 3) {
-        T ZL[NB], ZR[NB];
-        slice<D, M, 0, 1>(u + field, nodes, cb, 0, l, ZL);
-        slice<D, M, 0, 1>(u + field, nodes, cb, 1, l, ZR);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          YL[b] = fma(r01, ZL[b], YL[b]);
-          YR[b] = fma(r01, ZR[b], YR[b]);
-        }
-      }
       T S[NB], Df[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         S[b] = YR[b] + YL[b];
         Df[b] = YR[b] - YL[b];
       }
-      merge<D, M, -1, 0>(tab + TL::P_A_OFF + l * NNZ, l, S, Df, acc);
+      merge<D, M, false, 0>(tab + TL::P_A_OFF + l * NNZ, l, S, Df, acc);
     }
     {
-      // group B: component d-1, transverse passes H, last pass D_d H
+      // last component: interpolation pass in x, derivative in the last pass
       T YL[NB], YR[NB], S[NB], Df[NB];
       slice<D, M, 0, 0>(u + (D - 1) * field, nodes, cb, 0, l, YL);
       slice<D, M, 0, 0>(u + (D - 1) * field, nodes, cb, 1, l, YR);
@@ -251,7 +233,7 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_kernel(T* __restr
         S[b] = YR[b] + YL[b];
         Df[b] = YR[b] - YL[b];
       }
-      merge<D, M, -1, 1>(tab + TL::P_B_OFF + l * NNZ, l, S, Df, acc);
+      merge<D, M, false, 1>(tab + TL::P_B_OFF + l * NNZ, l, S, Df, acc);
     }
   }
   const uint32_t o0 = (uint32_t)sizeof(T) * node_index<D>(j[0], j[1], j[2], g);
@@ -262,13 +244,32 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_kernel(T* __restr
   }
 }
 
+// u_i[s] -= wscale * (s_i + 1) / h_i * Q[s + e_i]   (Q on the set G)
+template <int D, int M, typename T>
+__device__ __forceinline__ void finish_velocity(T* __restrict__ u, int64_t field, int64_t nodes, uint32_t o0,
+                                                const T* Q, T wscale, const T* ih) {
+  constexpr int MP = M + 1;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const T f = wscale * ih[i];
+#pragma unroll
+    for (int s = 0; s < Dims<D, M>::NC; ++s) {
+      const int si1 = digit(s, MP, i) + 1;
+      T* q = reinterpret_cast<T*>(reinterpret_cast<char*>(u + (int64_t)i * field + (int64_t)s * nodes) + o0);
+      *q = fma(-(T)si1 * f, Q[kGIndex<D, M>.g[i][s]], *q);
+    }
+  }
+}
+
 // Velocity half-step at every dual node, weights scaled by wscale.
 template <int D, int M, typename T>
 __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_kernel(T* __restrict__ u, const T* __restrict__ p,
-                                                      const T* __restrict__ tab, Grid g, T wscale) {
+                                                                       const T* __restrict__ tab, Grid g, T wscale,
+                                                                       T ih0, T ih1, T ih2) {
   using Dm = Dims<D, M>;
   using TL = TableLayout<D, M>;
-  constexpr int MP = Dm::MP, NC = Dm::NC, NB = Dm::NB;
+  constexpr int MP = Dm::MP, NB = Dm::NB;
+  constexpr int NG = GSet<D, M>::NG;
   int32_t j[3];
   if (!node_of_thread<D>(g, j)) return;
   int32_t lo[3], hi[3];
@@ -283,13 +284,12 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_kernel(T* __restr
     cb[e] = (uint32_t)sizeof(T) *
             node_index<D>((e & 1) ? hi[0] : lo[0], (e & 2) ? hi[1] : lo[1], (e & 4) ? hi[2] : lo[2], g);
 
-  T acc[D][NC];
+  T Q[NG];
 #pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int s = 0; s < NC; ++s) acc[i][s] = T(0);
+  for (int o = 0; o < NG; ++o) Q[o] = T(0);
   const int64_t nodes = g.nodes;
-  const int64_t field = (int64_t)NC * nodes;
+  const int64_t field = (int64_t)Dm::NC * nodes;
+  constexpr int NNZ = merged_nnz<D, M>(true);
 
 #pragma unroll
   for (int l = 0; l < MP; ++l) {
@@ -301,18 +301,186 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_kernel(T* __restr
       S[b] = YR[b] + YL[b];
       Df[b] = YR[b] - YL[b];
     }
-    merge<D, M, 0, 0>(tab + TL::u_off(0) + l * merged_nnz<D, M>(0), l, S, Df, acc[0]);
-    if constexpr (D > 1) merge<D, M, 1, 0>(tab + TL::u_off(1) + l * merged_nnz<D, M>(1), l, S, Df, acc[1]);
-    if constexpr (D > 2) merge<D, M, 2, 0>(tab + TL::u_off(2) + l * merged_nnz<D, M>(2), l, S, Df, acc[2]);
+    merge<D, M, true, 0>(tab + TL::U_OFF + l * NNZ, l, S, Df, Q);
   }
-  const uint32_t o0 = (uint32_t)sizeof(T) * node_index<D>(j[0], j[1], j[2], g);
+  const T ih[3] = {ih0, ih1, ih2};
+  finish_velocity<D, M>(u, field, nodes, (uint32_t)sizeof(T) * node_index<D>(j[0], j[1], j[2], g), Q, wscale, ih);
+}
+
+// ---------------------------------------------------------------------------
+// 3D kernels.  A work-item interpolates explicitly only along x: for every
+// y/z datum pair (a_y, a_z) it loads the 8 corners' x-lines, applies the x
+// pass (derivative pass for the x-component of the pressure half-step), and
+// combines the four (y, z) corners into sigma/delta in y and in z.  The y and
+// z interpolation, the Cauchy-Kowalevsky weights and (for the y- and
+// z-components) the divergence are all in the runtime table (Merge3Spec).
+// Coefficient planes are read through buffer descriptors: one per field and
+// (a_y, a_z), a 32-bit per-lane corner offset and a scalar plane offset.
+// ---------------------------------------------------------------------------
+
+// Buffer resource over n consecutive coefficient planes starting at plane c0
+// (raw dword addressing, gfx9 descriptor word 3).  Offsets past num_records
+// read as zero.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t planes_rsrc(const T* f, int64_t nodes, int c0, int n) {
+  const T* base = f + (int64_t)c0 * nodes;
+  const uint32_t bytes = (uint32_t)((int64_t)n * nodes * (int64_t)sizeof(T));
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+// X[k_y][k_z][b_x] for datum pair (a_y, a_z), whose m+1 coefficient planes
+// (a_x = 0..m) start at plane c0 of field f; cb[e], e = e_x + 2 e_y + 4 e_z,
+// are the corners' byte offsets inside a plane.  One buffer descriptor per
+// plane keeps every offset below 4 GiB for any plane below 4 GiB.
+template <int M, int FLIPX, typename T>
+__device__ __forceinline__ void xlines(const T* f, int64_t nodes, int c0, const uint32_t* cb,
+                                       T (&X)[2][2][2 * M + 2]) {
+  constexpr int MP = M + 1, N2 = 2 * M + 2;
+  // for large m keep the loads of different (a_y, a_z) blocks apart, or the
+  // scheduler clusters them and runs out of registers
+  if constexpr (M >= 3) __builtin_amdgcn_sched_barrier(0);
+  __amdgpu_buffer_rsrc_t rs[MP];
 #pragma unroll
-  for (int i = 0; i < D; ++i)
+  for (int ax = 0; ax < MP; ++ax) rs[ax] = planes_rsrc(f, nodes, c0 + ax, 1);
+  T Y[2][2][N2];  // [e_y][e_z][b_x]
 #pragma unroll
-    for (int s = 0; s < NC; ++s) {
-      T* q = reinterpret_cast<T*>(reinterpret_cast<char*>(u + (int64_t)i * field + (int64_t)s * nodes) + o0);
-      *q = fma(-wscale, acc[i][s], *q);
+  for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey) {
+      T Lv[MP], Rv[MP];
+#pragma unroll
+      for (int ax = 0; ax < MP; ++ax) {
+        Lv[ax] = bload<T>(rs[ax], cb[0 + 2 * ey + 4 * ez], 0u);
+        Rv[ax] = bload<T>(rs[ax], cb[1 + 2 * ey + 4 * ez], 0u);
+      }
+      pass1d<M, FLIPX>(Lv, Rv, Y[ey][ez]);
     }
+#pragma unroll
+  for (int b = 0; b < N2; ++b) {
+    const T s0 = Y[1][0][b] + Y[0][0][b], d0 = Y[1][0][b] - Y[0][0][b];  // z = lower
+    const T s1 = Y[1][1][b] + Y[0][1][b], d1 = Y[1][1][b] - Y[0][1][b];  // z = upper
+    X[0][0][b] = s1 + s0;
+    X[0][1][b] = s1 - s0;
+    X[1][0][b] = d1 + d0;
+    X[1][1][b] = d1 - d0;
+  }
+}
+
+template <int M, bool VEL, int FY, int FZ, typename T, typename TP>
+__device__ __forceinline__ void merge3(TP Mt, int ay, int az, const T (&X)[2][2][2 * M + 2], T* acc) {
+  constexpr int NNZ = Merge3Spec<M, VEL, FY, FZ>::NNZ;
+  constexpr int kChunk = sizeof(T) == 8 ? 16 : 32;
+#pragma unroll
+  for (int t = 0; t < NNZ; ++t) {
+    if (t % kChunk == 0) __builtin_amdgcn_sched_barrier(HL_SCHED_MASK);
+    const int o = kMerge3<M, VEL, FY, FZ>.o[t];
+    const int bx = kMerge3<M, VEL, FY, FZ>.bx[t];
+    const int ky = kMerge3<M, VEL, FY, FZ>.ky[t][ay];
+    const int kz = kMerge3<M, VEL, FY, FZ>.kz[t][az];
+    acc[o] = fma(Mt[t], X[ky][kz][bx], acc[o]);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void corners3(const Grid& g, const int32_t* lo, const int32_t* hi, uint32_t* cb) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    cb[e] = (uint32_t)sizeof(T) *
+            node_index<3>((e & 1) ? hi[0] : lo[0], (e & 2) ? hi[1] : lo[1], (e & 4) ? hi[2] : lo[2], g);
+}
+
+template <int M, typename T>
+__global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_3d(T* __restrict__ p, const T* __restrict__ u,
+                                                                   const T* __restrict__ tab, Grid g) {
+  using TL = TableLayout<3, M>;
+  constexpr int MP = M + 1, NC = Dims<3, M>::NC, N2 = 2 * M + 2;
+  constexpr int NNZ = Merge3Spec<M, false, 0, 0>::NNZ;
+  int32_t j[3];
+  if (!node_of_thread<3>(g, j)) return;
+  int32_t lo[3], hi[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = (j[k] == 0 ? g.K[k] : j[k]) - 1;  // dual q = j - 1 (wrapped)
+    hi[k] = j[k];                              // dual q = j
+  }
+  uint32_t cb[8];
+  corners3<T>(g, lo, hi, cb);
+  const int64_t nodes = g.nodes;
+  const int64_t field = (int64_t)NC * nodes;
+  T acc[NC];
+#pragma unroll
+  for (int s = 0; s < NC; ++s) acc[s] = T(0);
+#pragma unroll
+  for (int az = 0; az < MP; ++az)
+#pragma unroll
+    for (int ay = 0; ay < MP; ++ay) {
+      const int blk = ay + MP * az;
+      {
+        T X[2][2][N2];
+        xlines<M, 1>(u, nodes, MP * blk, cb, X);
+        merge3<M, false, 0, 0>(tab + TL::p_off(0) + blk * NNZ, ay, az, X, acc);
+      }
+      {
+        T X[2][2][N2];
+        xlines<M, 0>(u + field, nodes, MP * blk, cb, X);
+        merge3<M, false, 1, 0>(tab + TL::p_off(1) + blk * NNZ, ay, az, X, acc);
+      }
+      {
+        T X[2][2][N2];
+        xlines<M, 0>(u + 2 * field, nodes, MP * blk, cb, X);
+        merge3<M, false, 0, 1>(tab + TL::p_off(2) + blk * NNZ, ay, az, X, acc);
+      }
+    }
+  const uint32_t o0 = (uint32_t)sizeof(T) * node_index<3>(j[0], j[1], j[2], g);
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    T* q = reinterpret_cast<T*>(reinterpret_cast<char*>(p + (int64_t)s * nodes) + o0);
+    *q = *q - acc[s];
+  }
+}
+
+template <int M, typename T>
+__global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_3d(T* __restrict__ u, const T* __restrict__ p,
+                                                                   const T* __restrict__ tab, Grid g, T wscale,
+                                                                   T ih0, T ih1, T ih2) {
+  using TL = TableLayout<3, M>;
+  constexpr int MP = M + 1, NC = Dims<3, M>::NC, N2 = 2 * M + 2;
+  constexpr int NG = GSet<3, M>::NG;
+  constexpr int NNZ = Merge3Spec<M, true, 0, 0>::NNZ;
+  int32_t j[3];
+  if (!node_of_thread<3>(g, j)) return;
+  int32_t lo[3], hi[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = j[k];                                  // primal j = q
+    hi[k] = (j[k] + 1 == g.K[k]) ? 0 : j[k] + 1;   // primal j = q + 1 (wrapped)
+  }
+  uint32_t cb[8];
+  corners3<T>(g, lo, hi, cb);
+  const int64_t nodes = g.nodes;
+  const int64_t field = (int64_t)NC * nodes;
+  T Q[NG];
+#pragma unroll
+  for (int o = 0; o < NG; ++o) Q[o] = T(0);
+#pragma unroll
+  for (int az = 0; az < MP; ++az)
+#pragma unroll
+    for (int ay = 0; ay < MP; ++ay) {
+      const int blk = ay + MP * az;
+      T X[2][2][N2];
+      xlines<M, 0>(p, nodes, MP * blk, cb, X);
+      merge3<M, true, 0, 0>(tab + TL::U_OFF + blk * NNZ, ay, az, X, Q);
+    }
+  const T ih[3] = {ih0, ih1, ih2};
+  finish_velocity<3, M>(u, field, nodes, (uint32_t)sizeof(T) * node_index<3>(j[0], j[1], j[2], g), Q, wscale, ih);
 }
 
 }  // namespace hl

@@ -213,3 +213,36 @@ def test_gaussian_pulse_3d_full_size_sampled(prec):
     wl = inputs.gaussian_pulse_3d(seed=2, K=256, m=2)
     wl.U0 = None
     _sampled_check(wl, prec, 200, tol(prec, 3, 2))
+
+
+@pytest.mark.parametrize("d,m,K,prec", [(1, 1, (200,), "fp64"), (2, 3, (64, 32), "fp32"), (3, 2, (16, 12, 8), "fp64")])
+def test_graph_replay_matches_eager(d, m, K, prec):
+    """hl_step replays a captured graph for >= 16 steps: its results equal the
+    eager half-step launches bit for bit, on every replay, with eager work and
+    host synchronisation in between, and after the buffers change."""
+    _say(f"[parity] graph replay d={d} m={m} K={K} {prec}")
+    rng = np.random.default_rng(5)
+    P = inputs.random_data(rng, d, m, K) * 0.1
+    U = inputs.random_data(rng, d, m, K, ncomp=d) * 0.1
+    plan = hl.Plan(d, m, K, cfl=0.7, precision=prec)
+    pe, ue = plan.alloc()
+    pg, ug = plan.alloc()
+    plan.init(pe, ue, P, U)
+    plan.init(pg, ug, P, U)
+    for rep in range(3):
+        for _ in range(37):
+            plan.p_half(pe, ue)
+            plan.u_half(ue, pe)
+        plan.step(pg, ug, 37)               # 2 graph replays + 5 eager steps
+        Pe, Ue = plan.export(pe, ue)
+        Pg, Ug = plan.export(pg, ug)
+        assert np.array_equal(Pe, Pg) and np.array_equal(Ue, Ug), rep
+    # new buffers: the plan must re-capture for them
+    p2, u2 = plan.alloc()
+    plan.init(p2, u2, P, U)
+    plan.step(p2, u2, 16)
+    plan.init(pe, ue, P, U)
+    for _ in range(16):
+        plan.p_half(pe, ue)
+        plan.u_half(ue, pe)
+    assert np.array_equal(plan.export(p2, u2)[0], plan.export(pe, ue)[0])
