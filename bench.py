@@ -76,10 +76,11 @@ def _source_sha256():
     return h.hexdigest()
 
 
-def _profiled_traffic(kernel, prec):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_standing_mode_2d_m3_1024.json")
+def _profiled_traffic(kernel, prec, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this workload, or None when there is none or the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     try:
         rec = json.load(open(path))
     except OSError:
@@ -89,7 +90,7 @@ def _profiled_traffic(kernel, prec):
     return rec["kernels"].get(f"{kernel}_{prec}", {}).get("bytes_per_launch")
 
 
-def roofline(res, d, prec="fp64"):
+def roofline(res, d, prec="fp64", workload="standing_mode_2d_m3_1024"):
     """Dominant kernel: algorithmic HBM bytes per launch / average duration.
     p half-step reads u (d fields) and p, writes p: (d + 2) nc words per node;
     u half-step reads p and u, writes u: (2 d + 1) nc words per node."""
@@ -98,13 +99,58 @@ def roofline(res, d, prec="fp64"):
     name = max(per, key=lambda k: per[k][1])
     bpn, ms = per[name]
     gbs = bpn * res["nodes"] / (ms * 1e-3) / 1e9
-    traffic = _profiled_traffic(name, prec)
+    traffic = _profiled_traffic(name, prec, workload)
     out = {"kernel": name, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
            "algorithmic_bytes_per_launch": bpn * res["nodes"], "bytes_per_cell": bpn, "avg_ms": round(ms, 5)}
     if traffic:
         out["traffic_over_algorithmic"] = round(traffic / (bpn * res["nodes"]), 4)
     return out
+
+
+def run_3d(hl, torch, steps, K=256, m=2):
+    """3D m=2 256^3 Gaussian pulse (start-up from u = 0), FP32 bulk state:
+    steps timed (the workload runs 500; a shorter timed window of the same
+    per-step work keeps the bench within minutes).  Reported beside the 2D
+    headline with its own roofline (3D step: 4 (m+1)^3 words read + written per
+    half-step pair, p: 5 nc, u: 7 nc words per node)."""
+    from paper_1808_10481_amd import inputs
+    wl = inputs.gaussian_pulse_3d(seed=2, K=K, m=m, steps=steps)
+    res = {}
+    for prec in ("fp32", "fp64"):
+        log(f"[bench] 3d {prec}: {steps} steps at {K}^3")
+        plan = hl.Plan(3, m, wl.K, dt=wl.dt, c=1.0, precision=prec)
+        p, u = plan.alloc()
+        plan.init(p, u, wl.P0, None, startup=True)
+        for _ in range(3):
+            plan.p_half(p, u)
+            plan.u_half(u, p)
+        stream = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for n in range(steps):
+            plan.p_half(p, u)
+            ev[2 * n + 1].record(stream)
+            plan.u_half(u, p)
+            ev[2 * n + 2].record(stream)
+        torch.cuda.synchronize()
+        tp = float(np.mean([ev[2 * n].elapsed_time(ev[2 * n + 1]) for n in range(steps)]))
+        tu = float(np.mean([ev[2 * n + 1].elapsed_time(ev[2 * n + 2]) for n in range(steps)]))
+        total = ev[0].elapsed_time(ev[-1])
+        info = plan.info
+        r = {"nc": info.nc, "word": info.word_bytes, "nodes": info.nodes, "p_ms": tp, "u_ms": tu}
+        step_bytes = 3 * 4 * info.nc * info.word_bytes * info.nodes
+        res[prec] = {"value": wl.cells * steps / (total * 1e-3), "unit": "cell-updates/s",
+                     "ms_per_step": total / steps, "steps": steps,
+                     "step_hbm_frac": round(step_bytes / (total / steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "roofline": roofline(r, 3, prec, f"gaussian_pulse_3d_m{m}_{K}")}
+        plan.close()
+        del p, u
+        torch.cuda.empty_cache()
+    res["config"] = {"workload": f"gaussian_pulse_3d m={m} {K}^3 nu=0.5 width=0.05", "d": 3, "m": m,
+                     "cells": [K] * 3}
+    return res
 
 
 def copy_probe(torch, nbytes=1 << 30, reps=20):
@@ -160,6 +206,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--steps-3d", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the build has no "
@@ -211,6 +259,9 @@ def main():
                        "nodal_l2_vs_exact": err32,
                        "roofline": roofline(r32, 2, "fp32"), "speedup_vs_fp64": value32 / value64}
         log(f"[bench] fp32 {r32['total_ms'] / args.steps:.4f} ms/step, rel L2 vs fp64 {rel:.3e}")
+
+    if not args.no_3d:
+        out["gaussian_pulse_3d"] = run_3d(hl, torch, args.steps_3d)
 
     if not args.no_copy_probe:
         out["copy_probe"] = copy_probe(torch)
