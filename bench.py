@@ -57,12 +57,12 @@ def run_precision(hl, torch, wl, prec, steps, warmup):
     tu = [ev[2 * n + 1].elapsed_time(ev[2 * n + 2]) for n in range(steps)]
     total_ms = ev[0].elapsed_time(ev[-1])
     P, U = plan.export(p, u)
-    info = plan.info
+    info, word = plan.info, plan.coef_bytes
     plan.close()
     del p, u
     torch.cuda.empty_cache()
     return dict(total_ms=total_ms, wall_s=wall, p_ms=float(np.mean(tp)), u_ms=float(np.mean(tu)),
-                P=P, U=U, word=info.word_bytes, nodes=info.nodes, nc=info.nc)
+                P=P, U=U, word=word, nodes=info.nodes, nc=info.nc)
 
 
 def _source_sha256():
@@ -112,12 +112,15 @@ def run_3d(hl, torch, steps, K=256, m=2):
     """3D m=2 256^3 Gaussian pulse (start-up from u = 0), FP32 bulk state:
     steps timed (the workload runs 500; a shorter timed window of the same
     per-step work keeps the bench within minutes).  Reported beside the 2D
-    headline with its own roofline (3D step: 4 (m+1)^3 words read + written per
-    half-step pair, p: 5 nc, u: 7 nc words per node)."""
+    headline with its own roofline (3D step: 12 (m+1)^3 coefficients read +
+    written per half-step pair, p: 5 nc, u: 7 nc per node).  Every precision
+    runs the same start-up, 3 untimed and `steps` timed steps; the pressure
+    state is then compared with the FP64 run's."""
     from paper_1808_10481_amd import inputs
     wl = inputs.gaussian_pulse_3d(seed=2, K=K, m=m, steps=steps)
     res = {}
-    for prec in ("fp32", "fp64"):
+    finals = {}
+    for prec in ("fp64", "fp32", "fp32_comp"):
         log(f"[bench] 3d {prec}: {steps} steps at {K}^3")
         plan = hl.Plan(3, m, wl.K, dt=wl.dt, c=1.0, precision=prec)
         p, u = plan.alloc()
@@ -139,12 +142,20 @@ def run_3d(hl, torch, steps, K=256, m=2):
         tu = float(np.mean([ev[2 * n + 1].elapsed_time(ev[2 * n + 2]) for n in range(steps)]))
         total = ev[0].elapsed_time(ev[-1])
         info = plan.info
-        r = {"nc": info.nc, "word": info.word_bytes, "nodes": info.nodes, "p_ms": tp, "u_ms": tu}
-        step_bytes = 3 * 4 * info.nc * info.word_bytes * info.nodes
+        r = {"nc": info.nc, "word": plan.coef_bytes, "nodes": info.nodes, "p_ms": tp, "u_ms": tu}
+        step_bytes = 3 * 4 * info.nc * plan.coef_bytes * info.nodes
         res[prec] = {"value": wl.cells * steps / (total * 1e-3), "unit": "cell-updates/s",
                      "ms_per_step": total / steps, "steps": steps,
                      "step_hbm_frac": round(step_bytes / (total / steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "roofline": roofline(r, 3, prec, f"gaussian_pulse_3d_m{m}_{K}")}
+        finals[prec] = plan.export(p, u, want_u=False)[0]
+        if prec != "fp64":
+            ref = finals["fp64"]
+            res[prec]["rel_l2_vs_fp64_p_state"] = float(np.linalg.norm(finals[prec] - ref) / np.linalg.norm(ref))
+            res[prec]["rel_l2_vs_fp64_p_nodal_values"] = float(
+                np.linalg.norm(finals[prec][..., 0, 0, 0] - ref[..., 0, 0, 0]) / np.linalg.norm(ref[..., 0, 0, 0]))
+            res[prec]["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res[prec]["ms_per_step"]
+            del finals[prec]
         plan.close()
         del p, u
         torch.cuda.empty_cache()
@@ -205,6 +216,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-comp", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--steps-3d", type=int, default=50)
@@ -259,6 +271,22 @@ def main():
                        "nodal_l2_vs_exact": err32,
                        "roofline": roofline(r32, 2, "fp32"), "speedup_vs_fp64": value32 / value64}
         log(f"[bench] fp32 {r32['total_ms'] / args.steps:.4f} ms/step, rel L2 vs fp64 {rel:.3e}")
+
+    if not args.no_comp:
+        log(f"[bench] fp32_comp: {args.warmup} warmup + {args.steps} timed steps")
+        rc = run_precision(hl, torch, wl, "fp32_comp", args.steps, args.warmup)
+        valuec = wl.cells * args.steps / (rc["total_ms"] * 1e-3)
+        den = np.sqrt(np.sum(r64["P"] ** 2) + np.sum(r64["U"] ** 2))
+        rel = float(np.sqrt(np.sum((rc["P"] - r64["P"]) ** 2) + np.sum((rc["U"] - r64["U"]) ** 2)) / den)
+        vc = np.concatenate([rc["P"][..., 0, 0].ravel(), rc["U"][..., 0, 0].ravel()])
+        v64 = np.concatenate([r64["P"][..., 0, 0].ravel(), r64["U"][..., 0, 0].ravel()])
+        out["fp32_comp"] = {"value": valuec, "ms_per_step": rc["total_ms"] / args.steps,
+                            "storage": "FP32 hi + BF16 lo (6 B/coefficient), FP64 arithmetic",
+                            "rel_l2_vs_fp64_state": rel,
+                            "rel_l2_vs_fp64_nodal_values": float(np.linalg.norm(vc - v64) / np.linalg.norm(v64)),
+                            "nodal_l2_vs_exact": float(np.sqrt(vol * np.sum((rc["P"][..., 0, 0] - Pex[..., 0, 0]) ** 2))),
+                            "roofline": roofline(rc, 2, "fp32_comp"), "speedup_vs_fp64": valuec / value64}
+        log(f"[bench] fp32_comp {rc['total_ms'] / args.steps:.4f} ms/step, rel L2 vs fp64 {rel:.3e}")
 
     if not args.no_3d:
         out["gaussian_pulse_3d"] = run_3d(hl, torch, args.steps_3d)

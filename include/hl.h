@@ -41,9 +41,11 @@
  *
  * Device layout (opaque to callers, fixed per plan): coefficient-major
  * planes, p[c][n] and u[i][c][n], with node n = j_1 + K_1 (j_2 + K_2 j_3)
- * and coefficient c = a_1 + (m+1)(a_2 + (m+1) a_3), in the plan precision.
- * Size limit (HL_ERR_UNSUPPORTED beyond it): one coefficient plane below
- * 4 GiB, i.e. fewer than 2^30 nodes in FP32 and 2^29 in FP64.
+ * and coefficient c = a_1 + (m+1)(a_2 + (m+1) a_3), in the plan precision
+ * (HL_FP32_COMP: hi planes p[c][n] / u[i][c][n], then the lo planes in the
+ * same order).  Size limit (HL_ERR_UNSUPPORTED beyond it): one coefficient
+ * plane below 4 GiB, i.e. fewer than 2^30 nodes in FP32 and FP32_COMP and
+ * 2^29 in FP64.
  */
 #ifndef HL_H
 #define HL_H
@@ -64,7 +66,17 @@ typedef enum {
   HL_ERR_NONFINITE = 6     /* hl_norms found a NaN or Inf */
 } hl_status;
 
-typedef enum { HL_FP64 = 0, HL_FP32 = 1 } hl_precision;
+/* Storage and arithmetic type of the state.  The method is defined in exact
+ * arithmetic; these are representations of its scaled nodal data (Sec. 2).
+ *   HL_FP64       FP64 words, FP64 arithmetic.
+ *   HL_FP32       FP32 words, FP32 arithmetic (half the bytes of FP64; the
+ *                 state's rounding at every half-step is ~2^-24 relative).
+ *   HL_FP32_COMP  each coefficient stored as hi + lo, hi = FP32 rounding of
+ *                 the value, lo = BF16 rounding of the residual (6 bytes,
+ *                 ~2^-33 relative state rounding); arithmetic in FP64.
+ *                 The buffer holds every hi plane (FP32) followed by every lo
+ *                 plane (BF16), counted in 2-byte words. */
+typedef enum { HL_FP64 = 0, HL_FP32 = 1, HL_FP32_COMP = 2 } hl_precision;
 
 /* Problem statement (Sec. 4: system, CFL constant and time step; Sec. 5:
  * tensor grid with spacing h_k per dimension). */
@@ -86,9 +98,9 @@ typedef struct {
   double  nu;           /* c dt / min_k h_k, in (0, 1) */
   int64_t nodes;        /* prod_k K_k */
   int32_t nc;           /* (m+1)^d coefficients per node per field */
-  int32_t word_bytes;   /* 8 (FP64) or 4 (FP32) */
-  int64_t p_words;      /* nc * nodes */
-  int64_t u_words;      /* d * nc * nodes */
+  int32_t word_bytes;   /* 8 (FP64), 4 (FP32) or 2 (FP32_COMP) */
+  int64_t p_words;      /* nc * nodes words (FP64, FP32); 3 * nc * nodes (FP32_COMP) */
+  int64_t u_words;      /* d times p_words */
 } hl_info;
 
 typedef struct hl_plan_s* hl_plan_t;
@@ -97,8 +109,8 @@ typedef struct hl_plan_s* hl_plan_t;
  * c dt / min h is not in (0, 1) - the domain-of-dependence bound of
  * Sec. 3.1.1 - and HL_ERR_UNSUPPORTED), builds the interpolation operator of
  * Sec. 2 eq. (interp) exactly in rationals and the Cauchy-Kowalevsky weight
- * tables in FP64, casts them to the plan precision and uploads them to the
- * current HIP device.  *out receives the handle (unchanged on failure). */
+ * tables in FP64, casts them to the plan's arithmetic type and uploads them
+ * to the current HIP device.  *out receives the handle (unchanged on failure). */
 hl_status hl_plan(const hl_problem* prob, hl_plan_t* out);
 
 /* Free the plan and its device tables.  NULL is accepted. */

@@ -13,8 +13,19 @@ Data (Sec. 2 and Sec. 5): every node stores scaled Taylor data
     alpha in {0..m}^d.
 Pressure lives on the primal grid x_j = lo + j*h at integer time levels, every
 velocity component on the dual grid x_{j+1/2} at half-integer levels (Sec. 2,
-eqs. (pGrid), (dGrid); Sec. 5).  The grid is periodic; dual index q sits at
-x_{q+1/2}.
+eqs. (pGrid), (dGrid); Sec. 5).  Dual index q sits at x_{q+1/2}.
+
+Boundaries: periodic, or reflecting walls (Sec. 5, "Imposing reflective
+boundary conditions", eq. (Boundary)): p = 0 on every face of the box
+[0, L_1] x ... x [0, L_d].  Then the primal grid has K+1 nodes per dimension
+(j = 0..K, the end nodes on the walls), the dual grid K (q = 0..K-1).  Before
+the pressure half-step one layer of ghost dual nodes (q = -1 and q = K) is
+filled by mirroring the velocity polynomials across the wall: p odd across the
+wall makes grad p's normal component even and its tangential components odd,
+so by u_t = -grad p the normal velocity component is mirrored evenly and the
+tangential ones oddly.  Mirroring a scaled Taylor coefficient across a wall
+normal to x_k multiplies it by (-1)^{a_k}, times -1 for an odd mirror.  The
+velocity half-step reads primal nodes only and needs no ghosts.
 
 One step (P^n, U^{n+1/2}) -> (P^{n+1}, U^{n+3/2}) is a p half-step followed by
 a u half-step:
@@ -55,7 +66,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "hermite_matrix_exact", "hermite_matrix", "p_half", "u_half",
-    "step", "startup", "p_update_cells", "u_update_cells",
+    "step", "startup", "p_update_cells", "u_update_cells", "ghost_pad", "mirror_sign",
 ]
 
 _CHUNK = 1 << 14  # nodes per vectorised batch (bounds memory, not arithmetic)
@@ -66,9 +77,10 @@ _CHUNK = 1 << 14  # nodes per vectorised batch (bounds memory, not arithmetic)
 # ---------------------------------------------------------------------------
 @dataclass(frozen=True)
 class Problem:
-    """Periodic constant-coefficient problem: dimension d, Hermite order m,
-    cells per dimension K, period length per dimension, time step dt and
-    kappa = c^2 (system of Sec. 4 / Sec. 5 with constant coefficient)."""
+    """Constant-coefficient problem: dimension d, Hermite order m, cells per
+    dimension K, box (or period) length per dimension, time step dt,
+    kappa = c^2 (system of Sec. 4 / Sec. 5 with constant coefficient) and the
+    boundary, "periodic" or "walls" (p = 0 on the box faces)."""
 
     d: int
     m: int
@@ -76,6 +88,19 @@ class Problem:
     length: tuple
     dt: float
     kappa: float = 1.0
+    bc: str = "periodic"
+
+    @property
+    def walls(self):
+        return self.bc == "walls"
+
+    def p_nodes(self):
+        """Primal nodes per dimension."""
+        return tuple(int(k) + (1 if self.walls else 0) for k in self.K)
+
+    def u_nodes(self):
+        """Dual nodes per dimension."""
+        return tuple(int(k) for k in self.K)
 
     @property
     def h(self):
@@ -89,10 +114,10 @@ class Problem:
         return replace(self, dt=dt)
 
     def p_shape(self):
-        return tuple(self.K) + (self.m + 1,) * self.d
+        return self.p_nodes() + (self.m + 1,) * self.d
 
     def u_shape(self):
-        return (self.d,) + self.p_shape()
+        return (self.d,) + self.u_nodes() + (self.m + 1,) * self.d
 
 
 # ---------------------------------------------------------------------------
@@ -256,28 +281,68 @@ def _all_nodes(K) -> np.ndarray:
 
 
 def _gather(F: np.ndarray, nodes: np.ndarray, offset: int, d: int, K) -> np.ndarray:
-    """Corner data F[(node + offset + eps) mod K] for eps in {0,1}^d, shaped
-    (2,)*d + (n,) + coefficient axes."""
+    """Corner data F[node + offset + eps] for eps in {0,1}^d, shaped
+    (2,)*d + (n,) + coefficient axes; indices taken mod K when K is given
+    (periodic), else used as they are."""
     n = nodes.shape[0]
     out = np.empty((2,) * d + (n,) + F.shape[d:], dtype=F.dtype)
     for eps in itertools.product((0, 1), repeat=d):
-        idx = tuple((nodes[:, k] + offset + eps[k]) % K[k] for k in range(d))
+        if K is None:
+            idx = tuple(nodes[:, k] + offset + eps[k] for k in range(d))
+        else:
+            idx = tuple((nodes[:, k] + offset + eps[k]) % K[k] for k in range(d))
         out[eps] = F[idx]
     return out
 
 
+def mirror_sign(i: int, k: int) -> float:
+    """Mirror parity of velocity component i across a wall normal to x_k:
+    +1 (even) for the normal component, -1 (odd) for tangential ones."""
+    return 1.0 if i == k else -1.0
+
+
+def ghost_pad(prob: Problem, U: np.ndarray) -> np.ndarray:
+    """Velocity with one ghost layer of dual nodes on every wall (walls
+    boundary): shape (d,) + (K+2,)*d + coefficient axes, the dual node q at
+    index q + 1.  Ghost q = -1 mirrors q = 0 across x_k = 0, ghost q = K
+    mirrors q = K-1 across x_k = L_k; a coefficient with index a_k is
+    multiplied by mirror_sign * (-1)^{a_k}.  Dimensions are mirrored one after
+    the other, so an edge or corner ghost is the mirror of a mirror."""
+    d, m = prob.d, prob.m
+    K = tuple(prob.K)
+    out = np.zeros((d,) + tuple(k + 2 for k in K) + (m + 1,) * d)
+    out[(slice(None),) + tuple(slice(1, k + 1) for k in K)] = U
+    for i in range(d):
+        for k in range(d):
+            shape = [1] * (2 * d)
+            shape[d + k] = m + 1
+            flip = (mirror_sign(i, k) * (-1.0) ** np.arange(m + 1)).reshape(shape)
+            lo = [slice(None)] * d
+            src = [slice(None)] * d
+            lo[k], src[k] = 0, 1
+            out[(i,) + tuple(lo)] = flip[0] * out[(i,) + tuple(src)]
+            lo[k], src[k] = K[k] + 1, K[k]
+            out[(i,) + tuple(lo)] = flip[0] * out[(i,) + tuple(src)]
+    return out
+
+
 def p_half(prob: Problem, P: np.ndarray, U: np.ndarray, nodes=None, dt=None):
-    """Pressure half-step on the periodic grid.  P, U in natural layout.
-    Primal node j takes the dual corners q = j - 1 + eps (cell centred on x_j
-    with ends x_{j-1/2}, x_{j+1/2}).  With ``nodes`` (n, d) only those nodes
-    are computed and an (n,)+coef array is returned; else the new P."""
-    d, K = prob.d, tuple(prob.K)
+    """Pressure half-step.  P, U in natural layout.  Primal node j takes the
+    dual corners q = j - 1 + eps (cell centred on x_j with ends x_{j-1/2},
+    x_{j+1/2}); with walls, q = -1 and q = K are the ghost nodes.  With
+    ``nodes`` (n, d) only those nodes are computed and an (n,)+coef array is
+    returned; else the new P."""
+    d = prob.d
     full = nodes is None
-    nodes = _all_nodes(K) if full else np.asarray(nodes, dtype=np.int64).reshape(-1, d)
+    nodes = _all_nodes(prob.p_nodes()) if full else np.asarray(nodes, dtype=np.int64).reshape(-1, d)
+    if prob.walls:
+        Ug, off, wrap = ghost_pad(prob, U), 0, None     # padded index q + 1
+    else:
+        Ug, off, wrap = U, -1, tuple(prob.K)
     res = np.empty((nodes.shape[0],) + P.shape[d:], dtype=np.float64)
     for a in range(0, nodes.shape[0], _CHUNK):
         nd = nodes[a:a + _CHUNK]
-        uc = [_gather(U[i], nd, -1, d, K) for i in range(d)]
+        uc = [_gather(Ug[i], nd, off, d, wrap) for i in range(d)]
         pv = P[tuple(nd[:, k] for k in range(d))]
         res[a:a + _CHUNK] = p_update_cells(prob, pv, uc, dt=dt)
     return res.reshape(P.shape) if full else res
@@ -287,13 +352,14 @@ def u_half(prob: Problem, U: np.ndarray, P: np.ndarray, nodes=None, dt=None,
            weight_scale: float = 1.0):
     """Velocity half-step.  Dual node q takes the primal corners j = q + eps
     (cell centred on x_{q+1/2} with ends x_q, x_{q+1})."""
-    d, K = prob.d, tuple(prob.K)
+    d = prob.d
     full = nodes is None
-    nodes = _all_nodes(K) if full else np.asarray(nodes, dtype=np.int64).reshape(-1, d)
+    nodes = _all_nodes(prob.u_nodes()) if full else np.asarray(nodes, dtype=np.int64).reshape(-1, d)
+    wrap = None if prob.walls else tuple(prob.K)
     res = np.empty((d, nodes.shape[0]) + P.shape[d:], dtype=np.float64)
     for a in range(0, nodes.shape[0], _CHUNK):
         nd = nodes[a:a + _CHUNK]
-        pc = _gather(P, nd, 0, d, K)
+        pc = _gather(P, nd, 0, d, wrap)
         uv = np.stack([U[i][tuple(nd[:, k] for k in range(d))] for i in range(d)])
         res[:, a:a + _CHUNK] = u_update_cells(prob, uv, pc, dt=dt, weight_scale=weight_scale)
     return res.reshape(U.shape) if full else res

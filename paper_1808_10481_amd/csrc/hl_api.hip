@@ -1,8 +1,8 @@
-// hl_api.cpp - C ABI of the Hermite-leapfrog library: validation, operator
+// hl_api.hip - C ABI of the Hermite-leapfrog library: validation, operator
 // tables, host<->device layout conversion, stepping and diagnostics.
 //
-// Operator tables (built once per plan, FP64, then cast to the plan
-// precision):
+// Operator tables (built once per plan, FP64, then cast to the plan's
+// arithmetic type):
 //  * H_m = [C^L; C^R]^{-1} (Sec. 2, eq. (interp)), by exact rational
 //    Gauss-Jordan elimination; C_{ls} = binom(s, l) xi0^{s-l}, xi0 = -+1/2.
 //  * the weight operators of the leapfrog difference with Cauchy-Kowalevsky
@@ -148,12 +148,15 @@ bool all_zero(const std::vector<double>& v) {
 // ---------------------------------------------------------------------------
 struct hl_plan_s {
   hl_problem prob;
-  int d, m, precision, nc, word_bytes;
+  int d, m, precision, nc;
+  int word_bytes;      // bytes per state word
+  int words_per_coef;  // 1 (FP64, FP32) or 3 (FP32_COMP: FP32 hi + BF16 lo)
+  int tab_bytes;       // bytes per table entry (arithmetic type)
   double dt, nu, kappa, h[3];
   hl::Grid grid;
   hl::KernelSet ks;
   void* dtab = nullptr;
-  double* dpartial = nullptr;  // norms scratch
+  double* dpartial = nullptr;  // norms scratch, kNormBlocks per plane
   int device = 0;
   // hl_step replays a captured graph of kGraphChunk steps for the last
   // (p, u) pair it saw; the capture runs on a plan-owned stream and the graph
@@ -166,8 +169,12 @@ struct hl_plan_s {
 
 namespace {
 
-constexpr int kNormBlocks = 1024;
+constexpr int kNormBlocks = 256;
 constexpr int64_t kGraphChunk = 16;   // steps per captured graph (32 kernel nodes)
+#ifndef HL_3D_YGROUP
+#define HL_3D_YGROUP 2
+#endif
+constexpr int32_t kYGroup3 = HL_3D_YGROUP;
 
 void drop_graph(hl_plan_s* pl) {
   if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
@@ -419,45 +426,98 @@ LayoutMap layout_of(const hl_plan_s* pl) {
   return L;
 }
 
-template <typename T>
+// BF16 bits of x rounded to nearest even (x finite); the device side of the
+// FP32_COMP format rounds the same way.
+uint16_t bf16_rne(float x) {
+  uint32_t b;
+  std::memcpy(&b, &x, 4);
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+float bf16_value(uint16_t h) {
+  const uint32_t b = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &b, 4);
+  return f;
+}
+
+// Device image of one field component: the hi (or only) word plane set and,
+// for FP32_COMP, the lo plane set; component i of ncomp sits at
+// i * hi_bytes (hi) and ncomp * hi_bytes + i * lo_bytes (lo).
+struct FieldImage {
+  int precision;
+  int64_t fw;  // coefficients per component
+  std::vector<unsigned char> hi, lo;
+  size_t hi_bytes() const { return (size_t)fw * (precision == HL_FP64 ? 8 : 4); }
+  size_t lo_bytes() const { return precision == HL_FP32_COMP ? (size_t)fw * 2 : 0; }
+  bool alloc() {
+    try {
+      hi.resize(hi_bytes());
+      lo.resize(lo_bytes());
+    } catch (const std::bad_alloc&) {
+      return false;
+    }
+    return true;
+  }
+  void put(int64_t i, double x) {
+    switch (precision) {
+      case HL_FP64: reinterpret_cast<double*>(hi.data())[i] = x; break;
+      case HL_FP32: reinterpret_cast<float*>(hi.data())[i] = (float)x; break;
+      default: {
+        const float h = (float)x;
+        reinterpret_cast<float*>(hi.data())[i] = h;
+        reinterpret_cast<uint16_t*>(lo.data())[i] = bf16_rne((float)(x - (double)h));
+      }
+    }
+  }
+  double get(int64_t i) const {
+    switch (precision) {
+      case HL_FP64: return reinterpret_cast<const double*>(hi.data())[i];
+      case HL_FP32: return (double)reinterpret_cast<const float*>(hi.data())[i];
+      default:
+        return (double)reinterpret_cast<const float*>(hi.data())[i] +
+               (double)bf16_value(reinterpret_cast<const uint16_t*>(lo.data())[i]);
+    }
+  }
+};
+
 hl_status upload_field(const hl_plan_s* pl, const double* host, int ncomp, void* dev, hipStream_t s) {
   const LayoutMap L = layout_of(pl);
-  const int64_t fw = (int64_t)pl->nc * pl->grid.nodes;
-  std::vector<T> buf;
-  try {
-    buf.resize((size_t)fw);
-  } catch (const std::bad_alloc&) {
-    return fail(HL_ERR_NOMEM, "hl_init: host staging allocation failed");
-  }
+  FieldImage im{pl->precision, (int64_t)pl->nc * pl->grid.nodes, {}, {}};
+  if (!im.alloc()) return fail(HL_ERR_NOMEM, "hl_init: host staging allocation failed");
+  unsigned char* d = static_cast<unsigned char*>(dev);
   for (int i = 0; i < ncomp; ++i) {
-    const double* src = host ? host + (size_t)i * fw : nullptr;
-    if (src)
-      L.for_each([&](int64_t h, int64_t dv) { buf[dv] = (T)src[h]; });
-    else
-      std::fill(buf.begin(), buf.end(), T(0));
-    hipError_t e = hipMemcpyAsync((T*)dev + (size_t)i * fw, buf.data(), (size_t)fw * sizeof(T), hipMemcpyHostToDevice, s);
+    const double* src = host ? host + (size_t)i * im.fw : nullptr;
+    if (src) {
+      L.for_each([&](int64_t h, int64_t dv) { im.put(dv, src[h]); });
+    } else {
+      std::fill(im.hi.begin(), im.hi.end(), (unsigned char)0);
+      std::fill(im.lo.begin(), im.lo.end(), (unsigned char)0);
+    }
+    hipError_t e = hipMemcpyAsync(d + i * im.hi_bytes(), im.hi.data(), im.hi_bytes(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && im.lo_bytes())
+      e = hipMemcpyAsync(d + ncomp * im.hi_bytes() + i * im.lo_bytes(), im.lo.data(), im.lo_bytes(),
+                         hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hl_init: copy to device");
   }
   return HL_OK;
 }
 
-template <typename T>
 hl_status download_field(const hl_plan_s* pl, const void* dev, int ncomp, double* host, hipStream_t s) {
   const LayoutMap L = layout_of(pl);
-  const int64_t fw = (int64_t)pl->nc * pl->grid.nodes;
-  std::vector<T> buf;
-  try {
-    buf.resize((size_t)fw);
-  } catch (const std::bad_alloc&) {
-    return fail(HL_ERR_NOMEM, "hl_export: host staging allocation failed");
-  }
+  FieldImage im{pl->precision, (int64_t)pl->nc * pl->grid.nodes, {}, {}};
+  if (!im.alloc()) return fail(HL_ERR_NOMEM, "hl_export: host staging allocation failed");
+  const unsigned char* d = static_cast<const unsigned char*>(dev);
   for (int i = 0; i < ncomp; ++i) {
-    hipError_t e = hipMemcpyAsync(buf.data(), (const T*)dev + (size_t)i * fw, (size_t)fw * sizeof(T), hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(im.hi.data(), d + i * im.hi_bytes(), im.hi_bytes(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && im.lo_bytes())
+      e = hipMemcpyAsync(im.lo.data(), d + ncomp * im.hi_bytes() + i * im.lo_bytes(), im.lo_bytes(),
+                         hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hl_export: copy to host");
-    double* dst = host + (size_t)i * fw;
-    L.for_each([&](int64_t h, int64_t dv) { dst[h] = (double)buf[dv]; });
+    double* dst = host + (size_t)i * im.fw;
+    L.for_each([&](int64_t h, int64_t dv) { dst[h] = im.get(dv); });
   }
   return HL_OK;
 }
@@ -481,36 +541,48 @@ hl_status check_plan(const hl_plan_s* pl, const char* who) {
   return HL_OK;
 }
 
-// FP64 sum of squares, per-block partials (deterministic order on the host).
-template <typename T>
-__global__ void sumsq_kernel(const T* __restrict__ x, int64_t n, double* __restrict__ partial) {
+// FP64 sum of squares of every entry of a state buffer; grid (kNormBlocks,
+// planes), one partial per (block, plane), summed on the host in a fixed
+// order so the result is deterministic.
+template <class S>
+__global__ void sumsq_kernel(typename S::View v, double* __restrict__ partial) {
   __shared__ double red[256];
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = (double)x[i];
-    acc = fma(v, v, acc);
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < v.nodes; n += (int64_t)gridDim.x * blockDim.x) {
+    const double x = (double)S::load(v, (int)blockIdx.y, (uint32_t)n);
+    acc = fma(x, x, acc);
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
 }
 
-template <typename T>
-hl_status sumsq(const hl_plan_s* pl, const void* x, int64_t n, double* out) {
-  hipLaunchKernelGGL(sumsq_kernel<T>, dim3(kNormBlocks), dim3(256), 0, 0, (const T*)x, n, pl->dpartial);
+template <class S>
+hl_status sumsq_as(const hl_plan_s* pl, const void* x, int ncomp, double* out) {
+  const int planes = ncomp * pl->nc;
+  const typename S::View v = S::make(x, ncomp, pl->nc, pl->grid.nodes);
+  hipLaunchKernelGGL(sumsq_kernel<S>, dim3(kNormBlocks, (unsigned)planes), dim3(256), 0, 0, v, pl->dpartial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "hl_norms: launch");
-  std::vector<double> part(kNormBlocks);
-  e = hipMemcpy(part.data(), pl->dpartial, kNormBlocks * sizeof(double), hipMemcpyDeviceToHost);
+  std::vector<double> part((size_t)kNormBlocks * planes);
+  e = hipMemcpy(part.data(), pl->dpartial, part.size() * sizeof(double), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "hl_norms: copy");
-  double s = 0.0;
-  for (double v : part) s += v;
-  *out = s;
+  double acc = 0.0;
+  for (double t : part) acc += t;
+  *out = acc;
   return HL_OK;
+}
+
+hl_status sumsq(const hl_plan_s* pl, const void* x, int ncomp, double* out) {
+  switch (pl->precision) {
+    case HL_FP64: return sumsq_as<hl::PlainStore<double>>(pl, x, ncomp, out);
+    case HL_FP32: return sumsq_as<hl::PlainStore<float>>(pl, x, ncomp, out);
+    default: return sumsq_as<hl::SplitStore>(pl, x, ncomp, out);
+  }
 }
 
 }  // namespace
@@ -530,7 +602,8 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
   if (p.d < 1 || p.d > 3) return fail(HL_ERR_ARG, "hl_plan: d must be 1, 2 or 3");
   if (p.m < 0) return fail(HL_ERR_ARG, "hl_plan: m must be >= 0");
   if (p.m > max_m(p.d)) return fail(HL_ERR_UNSUPPORTED, "hl_plan: m too large for this dimension");
-  if (p.precision != HL_FP64 && p.precision != HL_FP32) return fail(HL_ERR_ARG, "hl_plan: unknown precision");
+  if (p.precision != HL_FP64 && p.precision != HL_FP32 && p.precision != HL_FP32_COMP)
+    return fail(HL_ERR_ARG, "hl_plan: unknown precision");
   if (!finite_pos(p.c)) return fail(HL_ERR_ARG, "hl_plan: c must be finite and > 0");
   double hmin = INFINITY;
   int64_t nodes = 1;
@@ -556,7 +629,9 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
   pl->d = p.d;
   pl->m = p.m;
   pl->precision = p.precision;
-  pl->word_bytes = p.precision == HL_FP64 ? 8 : 4;
+  pl->word_bytes = p.precision == HL_FP64 ? 8 : (p.precision == HL_FP32 ? 4 : 2);
+  pl->words_per_coef = p.precision == HL_FP32_COMP ? 3 : 1;
+  pl->tab_bytes = p.precision == HL_FP32 ? 4 : 8;
   pl->dt = dt;
   pl->nu = nu;
   pl->kappa = p.c * p.c;
@@ -567,12 +642,12 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
     pl->grid.K[k] = k < p.d ? (int32_t)p.cells[k] : 1;
   }
   pl->grid.nodes = nodes;
-  if ((double)nodes * pl->word_bytes >= 4294967296.0) {
+  // the widest plane: FP64 words, or the FP32 (hi) planes
+  if ((double)nodes * (p.precision == HL_FP64 ? 8 : 4) >= 4294967296.0) {
     delete pl;
     return fail(HL_ERR_UNSUPPORTED, "hl_plan: one coefficient plane must stay below 4 GiB");
   }
-  bool ok = p.d == 1 ? hl::kernels_d1(p.m, p.precision, &pl->ks)
-                     : (p.d == 2 ? hl::kernels_d2(p.m, p.precision, &pl->ks) : hl::kernels_d3(p.m, p.precision, &pl->ks));
+  const bool ok = hl::kernels_for(p.d, p.m, p.precision, &pl->ks);
   if (!ok) {
     delete pl;
     return fail(HL_ERR_UNSUPPORTED, "hl_plan: (d, m, precision) not built");
@@ -589,6 +664,10 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
     }
     pl->grid.tiles = (int32_t)tiles;
     pl->grid.per_xcd = (int32_t)((tiles + hl::kXcds - 1) / hl::kXcds);
+    // 3D: tile numbering x, then y in groups of kYGroup3 tile rows, then z
+    // (z-neighbour planes reused from L2); 1D/2D: plain row-major
+    pl->grid.ygroup = p.d == 3 ? std::min<int32_t>(kYGroup3, pl->grid.nt[1]) : pl->grid.nt[1];
+    pl->grid.pad = 0;
   }
   std::vector<double> tab;
   hl_status st = build_tables(pl, tab);
@@ -601,15 +680,15 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
     delete pl;
     return hip_fail(e, "hl_plan: hipGetDevice");
   }
-  const size_t bytes = tab.size() * pl->word_bytes;
+  const size_t bytes = tab.size() * pl->tab_bytes;
   e = hipMalloc(&pl->dtab, std::max<size_t>(bytes, 16));
-  if (e == hipSuccess) e = hipMalloc((void**)&pl->dpartial, kNormBlocks * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&pl->dpartial, (size_t)kNormBlocks * pl->d * pl->nc * sizeof(double));
   if (e != hipSuccess) {
     if (pl->dtab) (void)hipFree(pl->dtab);
     delete pl;
     return fail(HL_ERR_NOMEM, std::string("hl_plan: device allocation: ") + hipGetErrorString(e));
   }
-  if (pl->precision == HL_FP64) {
+  if (pl->tab_bytes == 8) {
     e = hipMemcpy(pl->dtab, tab.data(), bytes, hipMemcpyHostToDevice);
   } else {
     std::vector<float> tf(tab.begin(), tab.end());
@@ -644,8 +723,8 @@ hl_status hl_plan_info(hl_plan_t plan, hl_info* out) {
   out->nodes = plan->grid.nodes;
   out->nc = plan->nc;
   out->word_bytes = plan->word_bytes;
-  out->p_words = (int64_t)plan->nc * plan->grid.nodes;
-  out->u_words = (int64_t)plan->d * plan->nc * plan->grid.nodes;
+  out->p_words = (int64_t)plan->words_per_coef * plan->nc * plan->grid.nodes;
+  out->u_words = (int64_t)plan->d * out->p_words;
   return HL_OK;
 }
 
@@ -657,13 +736,8 @@ hl_status hl_init(hl_plan_t plan, const double* p0, const double* u0, uint32_t f
   if (!p0 || !p || !u) return fail(HL_ERR_ARG, "hl_init: p0, p and u must be non-NULL");
   if (flags & ~HL_INIT_STARTUP) return fail(HL_ERR_ARG, "hl_init: unknown flags");
   hipStream_t s = (hipStream_t)stream;
-  if (plan->precision == HL_FP64) {
-    if ((st = upload_field<double>(plan, p0, 1, p, s)) != HL_OK) return st;
-    if ((st = upload_field<double>(plan, u0, plan->d, u, s)) != HL_OK) return st;
-  } else {
-    if ((st = upload_field<float>(plan, p0, 1, p, s)) != HL_OK) return st;
-    if ((st = upload_field<float>(plan, u0, plan->d, u, s)) != HL_OK) return st;
-  }
+  if ((st = upload_field(plan, p0, 1, p, s)) != HL_OK) return st;
+  if ((st = upload_field(plan, u0, plan->d, u, s)) != HL_OK) return st;
   if (flags & HL_INIT_STARTUP) {
     hipError_t e = plan->ks.u_half(view(plan), u, p, 0.5, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -680,13 +754,8 @@ hl_status hl_export(hl_plan_t plan, const void* p, const void* u, double* p_out,
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "hl_export: pending work failed");
-  if (plan->precision == HL_FP64) {
-    if (p_out && (st = download_field<double>(plan, p, 1, p_out, s)) != HL_OK) return st;
-    if (u_out && (st = download_field<double>(plan, u, plan->d, u_out, s)) != HL_OK) return st;
-  } else {
-    if (p_out && (st = download_field<float>(plan, p, 1, p_out, s)) != HL_OK) return st;
-    if (u_out && (st = download_field<float>(plan, u, plan->d, u_out, s)) != HL_OK) return st;
-  }
+  if (p_out && (st = download_field(plan, p, 1, p_out, s)) != HL_OK) return st;
+  if (u_out && (st = download_field(plan, u, plan->d, u_out, s)) != HL_OK) return st;
   return HL_OK;
 }
 
@@ -743,14 +812,8 @@ hl_status hl_norms(hl_plan_t plan, const void* p, const void* u, double* out) {
   if (!p || !u || !out) return fail(HL_ERR_ARG, "hl_norms: NULL argument");
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hl_norms: pending work failed");
-  const int64_t pw = (int64_t)plan->nc * plan->grid.nodes;
-  if (plan->precision == HL_FP64) {
-    if ((st = sumsq<double>(plan, p, pw, &out[0])) != HL_OK) return st;
-    if ((st = sumsq<double>(plan, u, pw * plan->d, &out[1])) != HL_OK) return st;
-  } else {
-    if ((st = sumsq<float>(plan, p, pw, &out[0])) != HL_OK) return st;
-    if ((st = sumsq<float>(plan, u, pw * plan->d, &out[1])) != HL_OK) return st;
-  }
+  if ((st = sumsq(plan, p, 1, &out[0])) != HL_OK) return st;
+  if ((st = sumsq(plan, u, plan->d, &out[1])) != HL_OK) return st;
   if (!std::isfinite(out[0]) || !std::isfinite(out[1])) return fail(HL_ERR_NONFINITE, "hl_norms: non-finite state");
   return HL_OK;
 }

@@ -1,5 +1,5 @@
 // hl_internal.hpp - plan object and kernel registry shared by the C ABI
-// (hl_api.cpp) and the per-dimension kernel translation units.
+// (hl_api.hip) and the per-dimension kernel translation units.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,7 +13,7 @@ namespace hl {
 // What a launcher needs from a plan.
 struct PlanView {
   Grid grid;
-  const void* tab;      // packed operator tables in the plan precision
+  const void* tab;      // packed operator tables in the plan's arithmetic type
   int d, m, precision;
   double ih[3];         // 1 / h_k (velocity half-step)
 };
@@ -31,11 +31,27 @@ struct KernelSet {
   int tile[3];           // tile extent in x, y and z
 };
 
-// Registries implemented by hl_kernels_d{1,2,3}.hip; return false when
-// (m, precision) is not built for that dimension.
-bool kernels_d1(int m, int precision, KernelSet* out);
-bool kernels_d2(int m, int precision, KernelSet* out);
-bool kernels_d3(int m, int precision, KernelSet* out);
+// Registries, one translation unit per (dimension, storage) so the build
+// compiles them in parallel (hl_kernels_d<d>_<storage>.hip); each returns false
+// when m is not built for that dimension.
+bool kernels_d1_fp64(int m, KernelSet* out);
+bool kernels_d1_fp32(int m, KernelSet* out);
+bool kernels_d1_comp(int m, KernelSet* out);
+bool kernels_d2_fp64(int m, KernelSet* out);
+bool kernels_d2_fp32(int m, KernelSet* out);
+bool kernels_d2_comp(int m, KernelSet* out);
+bool kernels_d3_fp64(int m, KernelSet* out);
+bool kernels_d3_fp32(int m, KernelSet* out);
+bool kernels_d3_comp(int m, KernelSet* out);
+
+inline bool kernels_for(int d, int m, int precision, KernelSet* out) {
+  typedef bool (*Reg)(int, KernelSet*);
+  static const Reg reg[3][3] = {{kernels_d1_fp64, kernels_d1_fp32, kernels_d1_comp},
+                                {kernels_d2_fp64, kernels_d2_fp32, kernels_d2_comp},
+                                {kernels_d3_fp64, kernels_d3_fp32, kernels_d3_comp}};
+  if (d < 1 || d > 3 || precision < HL_FP64 || precision > HL_FP32_COMP) return false;
+  return reg[d - 1][precision](m, out);
+}
 
 // Table layout queries for a (d, m) the registry supports.
 template <int D, int M>
@@ -57,40 +73,48 @@ inline dim3 block_shape() {
 
 inline dim3 grid_shape(const Grid& g) { return dim3((unsigned)(g.per_xcd * kXcds), 1, 1); }
 
-template <int D, int M, typename T>
-hipError_t launch_p_generic(const PlanView& pv, void* p, const void* u, hipStream_t s) {
+template <int D, int M, class S>
+hipError_t launch_p(const PlanView& pv, void* p, const void* u, hipStream_t s) {
+  using T = typename S::C;
+  constexpr int NC = Dims<D, M>::NC;
+  const typename S::View vp = S::make(p, 1, NC, pv.grid.nodes);
+  const typename S::View vu = S::make(u, D, NC, pv.grid.nodes);
   if constexpr (D == 3)
-    hipLaunchKernelGGL((p_half_3d<M, T>), grid_shape(pv.grid), block_shape<D>(), 0, s, (T*)p, (const T*)u,
+    hipLaunchKernelGGL((p_half_3d<M, S>), grid_shape(pv.grid), block_shape<D>(), 0, s, vp, vu, (const T*)pv.tab,
+                       pv.grid);
+  else
+    hipLaunchKernelGGL((p_half_kernel<D, M, S>), grid_shape(pv.grid), block_shape<D>(), 0, s, vp, vu,
                        (const T*)pv.tab, pv.grid);
-  else
-    hipLaunchKernelGGL((p_half_kernel<D, M, T>), grid_shape(pv.grid), block_shape<D>(), 0, s, (T*)p,
-                       (const T*)u, (const T*)pv.tab, pv.grid);
   return hipGetLastError();
 }
 
-template <int D, int M, typename T>
-hipError_t launch_u_generic(const PlanView& pv, void* u, const void* p, double wscale, hipStream_t s) {
+template <int D, int M, class S>
+hipError_t launch_u(const PlanView& pv, void* u, const void* p, double wscale, hipStream_t s) {
+  using T = typename S::C;
+  constexpr int NC = Dims<D, M>::NC;
+  const typename S::View vu = S::make(u, D, NC, pv.grid.nodes);
+  const typename S::View vp = S::make(p, 1, NC, pv.grid.nodes);
   if constexpr (D == 3)
-    hipLaunchKernelGGL((u_half_3d<M, T>), grid_shape(pv.grid), block_shape<D>(), 0, s, (T*)u, (const T*)p,
-                       (const T*)pv.tab, pv.grid, (T)wscale, (T)pv.ih[0], (T)pv.ih[1], (T)pv.ih[2]);
+    hipLaunchKernelGGL((u_half_3d<M, S>), grid_shape(pv.grid), block_shape<D>(), 0, s, vu, vp, (const T*)pv.tab,
+                       pv.grid, (T)wscale, (T)pv.ih[0], (T)pv.ih[1], (T)pv.ih[2]);
   else
-    hipLaunchKernelGGL((u_half_kernel<D, M, T>), grid_shape(pv.grid), block_shape<D>(), 0, s, (T*)u,
-                       (const T*)p, (const T*)pv.tab, pv.grid, (T)wscale, (T)pv.ih[0], (T)pv.ih[1],
-                       (T)pv.ih[2]);
+    hipLaunchKernelGGL((u_half_kernel<D, M, S>), grid_shape(pv.grid), block_shape<D>(), 0, s, vu, vp,
+                       (const T*)pv.tab, pv.grid, (T)wscale, (T)pv.ih[0], (T)pv.ih[1], (T)pv.ih[2]);
   return hipGetLastError();
 }
 
-template <int D, int M>
-inline bool make_set(int precision, KernelSet* out) {
+template <int D, class S, int M>
+inline bool make_set(KernelSet* out) {
   fill_layout<D, M>(out);
-  if (precision == HL_FP64) {
-    out->p_half = &launch_p_generic<D, M, double>;
-    out->u_half = &launch_u_generic<D, M, double>;
-  } else {
-    out->p_half = &launch_p_generic<D, M, float>;
-    out->u_half = &launch_u_generic<D, M, float>;
-  }
+  out->p_half = &launch_p<D, M, S>;
+  out->u_half = &launch_u<D, M, S>;
   return true;
+}
+
+// Registry body: the kernel set for m, one of the compile-time orders Ms.
+template <int D, class S, int... Ms>
+inline bool make_set_for(int m, KernelSet* out) {
+  return ((m == Ms && make_set<D, S, Ms>(out)) || ...);
 }
 
 }  // namespace hl

@@ -1,0 +1,8 @@
+// hl_kernels_d2_fp64.hip - 2-dimensional half-step kernels, FP64 words.
+#include "hl_internal.hpp"
+
+namespace hl {
+
+bool kernels_d2_fp64(int m, KernelSet* out) { return make_set_for<2, PlainStore<double>, 0, 1, 2, 3, 4, 5>(m, out); }
+
+}  // namespace hl

@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HL_LIBRARY", os.path.join(_HERE, "libhermite_lf.so"))
 
 HL_OK, HL_ERR_ARG, HL_ERR_CFL, HL_ERR_UNSUPPORTED, HL_ERR_DEVICE, HL_ERR_NOMEM, HL_ERR_NONFINITE = range(7)
-HL_FP64, HL_FP32 = 0, 1
+HL_FP64, HL_FP32, HL_FP32_COMP = 0, 1, 2
+PRECISIONS = {"fp64": HL_FP64, "fp32": HL_FP32, "fp32_comp": HL_FP32_COMP}
 HL_INIT_STARTUP = 1
 
 STATUS_NAMES = {0: "HL_OK", 1: "HL_ERR_ARG", 2: "HL_ERR_CFL", 3: "HL_ERR_UNSUPPORTED",
@@ -97,7 +98,7 @@ def make_problem(d, m, cells, length=None, dt=0.0, cfl=0.5, c=1.0, precision="fp
         pr.cells[k] = cells[k] if k < len(cells) else 1
         pr.length[k] = length[k] if k < len(length) else 1.0
     pr.dt, pr.cfl, pr.c = float(dt), float(cfl), float(c)
-    pr.precision = {"fp64": HL_FP64, "fp32": HL_FP32}[precision]
+    pr.precision = PRECISIONS[precision]
     pr.reserved = 0
     return pr
 
@@ -140,8 +141,11 @@ class Plan:
 
     # -- device state ------------------------------------------------------
     def torch_dtype(self):
+        """Element type of the state buffers: one word per coefficient in FP64
+        and FP32; 16-bit words (three per coefficient: FP32 hi, BF16 lo) in
+        fp32_comp."""
         import torch
-        return torch.float64 if self.precision == "fp64" else torch.float32
+        return {"fp64": torch.float64, "fp32": torch.float32, "fp32_comp": torch.int16}[self.precision]
 
     def alloc(self, device="cuda"):
         import torch
@@ -168,15 +172,23 @@ class Plan:
                              HL_INIT_STARTUP if startup else 0, ctypes.c_void_p(p.data_ptr()),
                              ctypes.c_void_p(u.data_ptr()), _stream_ptr(stream)))
 
-    def export(self, p, u, stream=None):
+    def export(self, p, u, stream=None, want_u=True):
+        """FP64 host copies (host layout) of p and, unless want_u is False, u."""
         ps, us = self.host_shapes()
         P = np.empty(ps, dtype=np.float64)
-        U = np.empty(us, dtype=np.float64)
+        U = np.empty(us, dtype=np.float64) if want_u else None
         self._check_buf(p, u)
         _check(lib().hl_export(self._h, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(u.data_ptr()),
-                               P.ctypes.data_as(ctypes.c_void_p), U.ctypes.data_as(ctypes.c_void_p),
+                               P.ctypes.data_as(ctypes.c_void_p),
+                               U.ctypes.data_as(ctypes.c_void_p) if want_u else None,
                                _stream_ptr(stream)))
         return P, U
+
+    @property
+    def coef_bytes(self):
+        """Bytes per stored coefficient (8, 4, or 6 for fp32_comp)."""
+        i = self.info
+        return i.word_bytes * i.p_words // (i.nc * i.nodes)
 
     def step(self, p, u, nsteps=1, stream=None):
         self._check_buf(p, u)

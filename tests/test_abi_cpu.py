@@ -61,6 +61,20 @@ def test_plan_rejects_bad_problems(kw, want):
     assert not h.value
 
 
+def test_plan_rejects_unknown_precision_and_oversized_planes():
+    st, msg, h = _plan_status(d=1, m=1, cells=(8,), precision="fp64")
+    pr = hl.make_problem(1, 1, (8,))
+    pr.precision = 3
+    h = ctypes.c_void_p()
+    assert hl.lib().hl_plan(ctypes.byref(pr), ctypes.byref(h)) == hl.HL_ERR_ARG
+    # one FP32 (or FP32_COMP hi) plane of 2^30 nodes is 4 GiB: refused before any device call
+    for prec in ("fp32", "fp32_comp"):
+        st, msg, h = _plan_status(d=3, m=0, cells=(1024, 1024, 1024), precision=prec)
+        assert st == hl.HL_ERR_UNSUPPORTED and "4 GiB" in msg, (prec, st, msg)
+    st, msg, h = _plan_status(d=3, m=0, cells=(1024, 1024, 512), precision="fp64")
+    assert st == hl.HL_ERR_UNSUPPORTED and "4 GiB" in msg
+
+
 def test_plan_rejects_null_and_reserved():
     h = ctypes.c_void_p()
     assert hl.lib().hl_plan(None, ctypes.byref(h)) == hl.HL_ERR_ARG

@@ -8,6 +8,10 @@ random rounding the sum's error grows like sqrt(n) u, u = 2^-24, times the
 size of the terms, which for random (non-smooth) data exceeds the result by
 a factor up to ~16.  Bound used: relative L2 <= 16 sqrt(n) u_32 * 16 =
 256 sqrt(n) 2^-24 (about 1.2e-5 for d = 2, m = 5), max <= 4x that.
+FP32_COMP: FP64 arithmetic, then the result is stored as hi + lo with
+|x - hi| <= 2^-24 |x| and lo the BF16 rounding of x - hi (relative error
+2^-9), so every stored entry is within 2^-33 |x| of the FP64 result; bound
+used: relative L2 and max |diff| / max |ref| <= 2^-32 + 1e-12.
 """
 
 import sys
@@ -46,9 +50,14 @@ def _close(got, ref, tol_l2, tol_max):
 TOL = {"fp64": (1e-12, 1e-11), "fp32": (3e-6, 1e-5)}
 
 
+COMP_TOL = 2.0 ** -32 + 1e-12
+
+
 def tol(prec, d, m):
     if prec == "fp64":
         return TOL["fp64"]
+    if prec == "fp32_comp":
+        return (COMP_TOL, COMP_TOL)
     t = 256.0 * np.sqrt((2 * m + 2) ** d) * 2.0 ** -24
     return (t, 4 * t)
 
@@ -59,7 +68,7 @@ CASES = (
 )
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_comp"])
 @pytest.mark.parametrize("d,m,K", CASES)
 def test_half_steps_match_oracle(d, m, K, prec):
     _say(f"[parity] half-steps d={d} m={m} K={K} {prec}")
@@ -83,22 +92,52 @@ def test_half_steps_match_oracle(d, m, K, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_comp"])
 @pytest.mark.parametrize("d,m,K,n", [(1, 3, (50,), 40), (2, 3, (33, 20), 10), (3, 1, (12, 10, 9), 6),
                                      (3, 2, (10, 9, 8), 4)])
-def test_multistep_fp64(d, m, K, n):
-    _say(f"[parity] {n} steps d={d} m={m} K={K} fp64")
+def test_multistep(d, m, K, n, prec):
+    """n steps from the stored (rounded) initial data; FP32_COMP rounds the
+    state once per half-step, 2n roundings of at most 2^-33 relative each."""
+    _say(f"[parity] {n} steps d={d} m={m} K={K} {prec}")
     rng = np.random.default_rng(7 + d + m)
     P = inputs.random_data(rng, d, m, K)
     U = inputs.random_data(rng, d, m, K, ncomp=d)
-    plan = hl.Plan(d, m, K, cfl=0.9, precision="fp64")
+    plan = hl.Plan(d, m, K, cfl=0.9, precision=prec)
     prob = _prob(d, m, K, plan.dt)
     p, u = plan.alloc()
     plan.init(p, u, P, U)
+    P_in, U_in = plan.export(p, u)
     plan.step(p, u, n)
     Pg, Ug = plan.export(p, u)
-    Pr, Ur = oracle.step(prob, P, U, n)
-    _close(Pg, Pr, 1e-12 * n, 1e-11 * n)
-    _close(Ug, Ur, 1e-12 * n, 1e-11 * n)
+    Pr, Ur = oracle.step(prob, P_in, U_in, n)
+    t = 1e-12 if prec == "fp64" else COMP_TOL
+    _close(Pg, Pr, 2 * t * n, 10 * t * n)
+    _close(Ug, Ur, 2 * t * n, 10 * t * n)
+
+
+def test_comp_storage_round_trip():
+    """FP32_COMP stores x as hi + lo within 2^-33 |x| (and exactly for values
+    that fit in FP32 + BF16); exported values are exactly hi + lo."""
+    d, m, K = 2, 2, (40, 7)
+    rng = np.random.default_rng(21)
+    P = inputs.random_data(rng, d, m, K)
+    U = inputs.random_data(rng, d, m, K, ncomp=d)
+    plan = hl.Plan(d, m, K, precision="fp32_comp")
+    assert plan.info.word_bytes == 2 and plan.info.p_words == 3 * plan.info.nc * plan.info.nodes
+    p, u = plan.alloc()
+    plan.init(p, u, P, U)
+    Pg, Ug = plan.export(p, u)
+    for got, ref in ((Pg, P), (Ug, U)):
+        assert np.all(np.abs(got - ref) <= 2.0 ** -33 * np.abs(ref) + 1e-300)
+        assert rel_l2(got, ref) > 0                        # not FP64 storage
+    # values representable as FP32 + BF16 survive exactly
+    P2 = (P.astype(np.float32).astype(np.float64))
+    plan.init(p, u, P2, None)
+    assert np.array_equal(plan.export(p, u)[0], P2)
+    # norms see the stored values
+    plan.init(p, u, P, U)
+    sp, su = plan.norms(p, u)
+    assert abs(sp - np.sum(Pg * Pg)) <= 1e-12 * sp and abs(su - np.sum(Ug * Ug)) <= 1e-12 * su
 
 
 def test_standing_wave_1d_full_run():
@@ -197,7 +236,7 @@ def _sampled_check(wl, prec, nsamp, tol):
     _close(gotu, refu, *tol)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_comp"])
 def test_standing_mode_2d_full_size_sampled(prec):
     """2D m=3 1024^2 (the benchmark workload): sampled parity of one step."""
     _say(f"[parity] standing_mode_2d 1024^2 m=3 sampled {prec}")
@@ -205,7 +244,7 @@ def test_standing_mode_2d_full_size_sampled(prec):
     _sampled_check(wl, prec, 300, tol(prec, 2, 3))
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "fp32_comp"])
 def test_gaussian_pulse_3d_full_size_sampled(prec):
     """3D m=2 256^3 Gaussian pulse with the start-up: sampled parity of the
     start-up and one step at full size."""
@@ -215,7 +254,8 @@ def test_gaussian_pulse_3d_full_size_sampled(prec):
     _sampled_check(wl, prec, 200, tol(prec, 3, 2))
 
 
-@pytest.mark.parametrize("d,m,K,prec", [(1, 1, (200,), "fp64"), (2, 3, (64, 32), "fp32"), (3, 2, (16, 12, 8), "fp64")])
+@pytest.mark.parametrize("d,m,K,prec", [(1, 1, (200,), "fp64"), (2, 3, (64, 32), "fp32"), (3, 2, (16, 12, 8), "fp64"),
+                                        (2, 2, (40, 24), "fp32_comp")])
 def test_graph_replay_matches_eager(d, m, K, prec):
     """hl_step replays a captured graph for >= 16 steps: its results equal the
     eager half-step launches bit for bit, on every replay, with eager work and
