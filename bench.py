@@ -164,6 +164,38 @@ def run_3d(hl, torch, steps, K=256, m=2):
     return res
 
 
+def run_walls(hl, torch, steps, K=1024, m=3):
+    """Walled 2D m=3 1024^2 Gaussian pulse (reflecting boundary, start-up from
+    u = 0): `steps` steps timed after 3 untimed ones.  Each step is the ghost
+    refresh, the pressure and the velocity half-step."""
+    from paper_1808_10481_amd import inputs
+    wl = inputs.gaussian_pulse_walls_2d(seed=3, K=K, m=m, steps=steps)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        log(f"[bench] walls 2d {prec}: {steps} steps at {K}^2")
+        plan = hl.Plan(2, m, wl.K, length=wl.length, dt=wl.dt, c=1.0, precision=prec, boundary="walls")
+        p, u = plan.alloc()
+        plan.init(p, u, wl.P0, None, startup=True)
+        plan.step(p, u, 3)
+        stream = torch.cuda.current_stream()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record(stream)
+        plan.step(p, u, steps)
+        e.record(stream)
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / steps
+        sp, su = plan.norms(p, u)
+        res[prec] = {"value": (K + 1) ** 2 / (ms * 1e-3), "unit": "cell-updates/s", "ms_per_step": ms,
+                     "steps": steps, "energy_like_sumsq": [sp, su]}
+        plan.close()
+        del p, u
+        torch.cuda.empty_cache()
+    res["config"] = {"workload": f"gaussian_pulse_walls_2d m={m} {K}^2 box [0,2]^2 nu=0.5 width^2=0.002",
+                     "d": 2, "m": m, "cells": [K, K], "boundary": "walls"}
+    return res
+
+
 def copy_probe(torch, nbytes=1 << 30, reps=20):
     """Plain device copy y <- x of nbytes (the paper's "realistic peak"
     vector-copy measurement); GB/s counts bytes read + written."""
@@ -220,6 +252,8 @@ def main():
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--steps-3d", type=int, default=50)
+    ap.add_argument("--no-walls", action="store_true")
+    ap.add_argument("--steps-walls", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the build has no "
@@ -290,6 +324,9 @@ def main():
 
     if not args.no_3d:
         out["gaussian_pulse_3d"] = run_3d(hl, torch, args.steps_3d)
+
+    if not args.no_walls:
+        out["gaussian_pulse_walls_2d"] = run_walls(hl, torch, args.steps_walls)
 
     if not args.no_copy_probe:
         out["copy_probe"] = copy_probe(torch)

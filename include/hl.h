@@ -5,9 +5,9 @@
  *
  *     p_t = -kappa div(u),     u_t = -grad(p),     kappa = c^2 constant,
  *
- * on a periodic box with the Hermite-leapfrog method of Vargas, Hagstrom,
- * Chan and Warburton, "Leapfrog time-stepping for Hermite methods"
- * (arXiv 1808.10481):
+ * on a periodic box, or a box with reflecting walls (p = 0 on every face),
+ * with the Hermite-leapfrog method of Vargas, Hagstrom, Chan and Warburton,
+ * "Leapfrog time-stepping for Hermite methods" (arXiv 1808.10481):
  *   - data: value and first m derivatives per dimension at every node, scaled
  *     by h^a/a! (Sec. 2; Sec. 5 tensor-product form);
  *   - pressure on the primal grid x_j = j h at integer time levels, every
@@ -34,14 +34,20 @@
  *     work enqueued with it and is freed by hl_plan_destroy.
  *
  * Host layout (hl_init input, hl_export output): FP64, C order,
- *   p[j_1]...[j_d][a_1]...[a_d],  u[i][j_1]...[j_d][a_1]...[a_d],
- * node index j_k in [0, K_k), coefficient index a_k in [0, m], velocity
- * component i in [0, d).  Primal node j is at x = j h, dual node q at
- * x = (q + 1/2) h.
+ *   p[j_1]...[j_d][a_1]...[a_d],  u[i][q_1]...[q_d][a_1]...[a_d],
+ * coefficient index a_k in [0, m], velocity component i in [0, d).  Primal
+ * node j is at x = j h, dual node q at x = (q + 1/2) h.  Periodic: j_k and
+ * q_k in [0, K_k).  Walls (the box [0, length_k] per dimension): j_k in
+ * [0, K_k] (the end nodes lie on the walls), q_k in [0, K_k).
  *
  * Device layout (opaque to callers, fixed per plan): coefficient-major
- * planes, p[c][n] and u[i][c][n], with node n = j_1 + K_1 (j_2 + K_2 j_3)
- * and coefficient c = a_1 + (m+1)(a_2 + (m+1) a_3), in the plan precision
+ * planes, p[c][n] and u[i][c][n], with node n = i_1 + E_1 (i_2 + E_2 i_3)
+ * and coefficient c = a_1 + (m+1)(a_2 + (m+1) a_3), in the plan precision.
+ * Periodic: E_k = K_k for both fields.  Walls: p has E_k = K_k + 1; u is
+ * padded by one ghost node per side, E_k = K_k + 2, dual node q at index
+ * q + 1 (the ghosts are the mirror images of Sec. 5, "Imposing reflective
+ * boundary conditions", refreshed by the library before every pressure
+ * half-step)
  * (HL_FP32_COMP: hi planes p[c][n] / u[i][c][n], then the lo planes in the
  * same order).  Size limit (HL_ERR_UNSUPPORTED beyond it): one coefficient
  * plane below 4 GiB, i.e. fewer than 2^30 nodes in FP32 and FP32_COMP and
@@ -78,29 +84,38 @@ typedef enum {
  *                 plane (BF16), counted in 2-byte words. */
 typedef enum { HL_FP64 = 0, HL_FP32 = 1, HL_FP32_COMP = 2 } hl_precision;
 
+/* Boundary of the box.
+ *   HL_PERIODIC  periodic in every dimension.
+ *   HL_WALLS     reflecting walls on every face: p = 0 there (Sec. 5,
+ *                eq. (Boundary)), imposed by ghost dual nodes that mirror
+ *                the velocity polynomials (normal component even, tangential
+ *                components odd). */
+typedef enum { HL_PERIODIC = 0, HL_WALLS = 1 } hl_boundary;
+
 /* Problem statement (Sec. 4: system, CFL constant and time step; Sec. 5:
  * tensor grid with spacing h_k per dimension). */
 typedef struct {
   int32_t d;            /* space dimension, 1..3 */
   int32_t m;            /* Hermite order: value + first m derivatives;
                            supported 0..7 for d = 1, 0..5 for d = 2, 0..3 for d = 3 */
-  int64_t cells[3];     /* K_k >= 2 nodes per dimension (periodic); entries >= d ignored */
-  double  length[3];    /* period length per dimension, > 0; h_k = length_k / K_k */
+  int64_t cells[3];     /* K_k >= 2 cells per dimension; entries >= d ignored */
+  double  length[3];    /* period or box length per dimension, > 0; h_k = length_k / K_k */
   double  dt;           /* time step > 0, or 0 to derive dt = cfl * min_k h_k / c */
   double  cfl;          /* used when dt == 0 */
   double  c;            /* wave speed > 0; kappa = c^2 */
   int32_t precision;    /* hl_precision: storage and arithmetic type of the state */
-  int32_t reserved;     /* must be 0 */
+  int32_t boundary;     /* hl_boundary */
+  int32_t reserved[2];  /* must be 0 */
 } hl_problem;
 
 typedef struct {
   double  dt;           /* time step in use */
   double  nu;           /* c dt / min_k h_k, in (0, 1) */
-  int64_t nodes;        /* prod_k K_k */
+  int64_t nodes;        /* primal nodes: prod_k K_k (periodic), prod_k (K_k + 1) (walls) */
   int32_t nc;           /* (m+1)^d coefficients per node per field */
   int32_t word_bytes;   /* 8 (FP64), 4 (FP32) or 2 (FP32_COMP) */
-  int64_t p_words;      /* nc * nodes words (FP64, FP32); 3 * nc * nodes (FP32_COMP) */
-  int64_t u_words;      /* d times p_words */
+  int64_t p_words;      /* words of p: nc * (device p nodes), times 3 for FP32_COMP */
+  int64_t u_words;      /* words of u: d * nc * (device u nodes, ghosts included), times 3 for FP32_COMP */
 } hl_info;
 
 typedef struct hl_plan_s* hl_plan_t;
@@ -145,10 +160,13 @@ hl_status hl_export(hl_plan_t plan, const void* p, const void* u,
  * given; a new pair re-captures.  A plan is not safe to use from several
  * host threads at once. */
 hl_status hl_step(hl_plan_t plan, void* p, void* u, int64_t nsteps, void* stream);
+/* With HL_WALLS every pressure half-step (in hl_step and hl_p_half) is
+ * preceded by the ghost refresh of u. */
 
 /* One pressure half-step P <- P - sum_k w_k kappa^{k+1} Lap^k div I(U).
- * Asynchronous.  p and u must not alias. */
-hl_status hl_p_half(hl_plan_t plan, void* p, const void* u, void* stream);
+ * Asynchronous.  p and u must not alias.  u is not const: with HL_WALLS its
+ * ghost nodes are refreshed first (its dual nodes are not changed). */
+hl_status hl_p_half(hl_plan_t plan, void* p, void* u, void* stream);
 
 /* One velocity half-step U <- U - s * sum_k w_k kappa^k grad Lap^k I(P),
  * s = weight_scale (1 for the scheme, 0.5 for the start-up).  Asynchronous. */

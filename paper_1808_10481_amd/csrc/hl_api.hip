@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "hl.h"
+#include "hl_host_layout.hpp"
 #include "hl_internal.hpp"
 
 namespace {
@@ -153,7 +154,13 @@ struct hl_plan_s {
   int words_per_coef;  // 1 (FP64, FP32) or 3 (FP32_COMP: FP32 hi + BF16 lo)
   int tab_bytes;       // bytes per table entry (arithmetic type)
   double dt, nu, kappa, h[3];
-  hl::Grid grid;
+  bool walls = false;
+  int32_t K[3];          // cells per dimension (1 beyond d)
+  // device arrays: p with extents pext (offset 0), u with extents uext and
+  // dual node q at index q + uoff (walls: one ghost node per side)
+  int32_t pext[3], uext[3], uoff;
+  int64_t pnodes, unodes;
+  hl::Grid gp, gu;       // pressure / velocity half-step launch grids
   hl::KernelSet ks;
   void* dtab = nullptr;
   double* dpartial = nullptr;  // norms scratch, kNormBlocks per plane
@@ -163,8 +170,8 @@ struct hl_plan_s {
   // is launched on the caller's stream.
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
-  const void* gp = nullptr;
-  const void* gu = nullptr;
+  const void* graph_p = nullptr;  // buffers the graph was captured for
+  const void* graph_u = nullptr;
 };
 
 namespace {
@@ -179,7 +186,7 @@ constexpr int32_t kYGroup3 = HL_3D_YGROUP;
 void drop_graph(hl_plan_s* pl) {
   if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
   pl->gexec = nullptr;
-  pl->gp = pl->gu = nullptr;
+  pl->graph_p = pl->graph_u = nullptr;
 }
 
 // Capture kGraphChunk steps for buffers (p, u) into pl->gexec.
@@ -192,7 +199,8 @@ hipError_t capture_steps(hl_plan_s* pl, const hl::PlanView& v, void* p, void* u)
   if (e != hipSuccess) return e;
   hipError_t le = hipSuccess;
   for (int64_t n = 0; n < kGraphChunk && le == hipSuccess; ++n) {
-    le = pl->ks.p_half(v, p, u, pl->cap_stream);
+    if (pl->walls) le = pl->ks.ghost(v, u, pl->cap_stream);
+    if (le == hipSuccess) le = pl->ks.p_half(v, p, u, pl->cap_stream);
     if (le == hipSuccess) le = pl->ks.u_half(v, u, p, 1.0, pl->cap_stream);
   }
   hipGraph_t graph = nullptr;
@@ -201,8 +209,8 @@ hipError_t capture_steps(hl_plan_s* pl, const hl::PlanView& v, void* p, void* u)
   if (e == hipSuccess) e = hipGraphInstantiate(&pl->gexec, graph, nullptr, nullptr, 0);
   if (graph) (void)hipGraphDestroy(graph);
   if (e == hipSuccess) {
-    pl->gp = p;
-    pl->gu = u;
+    pl->graph_p = p;
+    pl->graph_u = u;
   } else {
     pl->gexec = nullptr;
   }
@@ -382,118 +390,28 @@ hl_status build_tables(hl_plan_s* pl, std::vector<double>& tab) {
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-// host layout offset of (node j, coefficient a) -> device offset
-struct LayoutMap {
-  int d, MP, nc;
-  int64_t K[3], nodes;
-  template <typename F>
-  void for_each(F&& f) const {
-    // host: ((j1 K2 + j2) K3 + j3) * nc + ((a1 MP + a2) MP + a3)
-    // device: c * nodes + n, n = j1 + K1 (j2 + K2 j3), c = a1 + MP (a2 + MP a3)
-    const int64_t K1 = K[0], K2 = d > 1 ? K[1] : 1, K3 = d > 2 ? K[2] : 1;
-    const int nthreads = (int)std::max<unsigned>(1, std::min<unsigned>(16, std::thread::hardware_concurrency()));
-    std::vector<std::thread> th;
-    for (int w = 0; w < nthreads; ++w)
-      th.emplace_back([&, w]() {
-        for (int64_t j1 = w; j1 < K1; j1 += nthreads)
-          for (int64_t j2 = 0; j2 < K2; ++j2)
-            for (int64_t j3 = 0; j3 < K3; ++j3) {
-              const int64_t hbase = ((j1 * K2 + j2) * K3 + j3) * nc;
-              const int64_t n = j1 + K1 * (j2 + K2 * j3);
-              for (int ha = 0; ha < nc; ++ha) {
-                // host coefficient index ha = (a1 MP + a2) MP + a3 (a1 slowest)
-                int a[3] = {0, 0, 0}, r = ha;
-                for (int k = d - 1; k >= 0; --k) {
-                  a[k] = r % MP;
-                  r /= MP;
-                }
-                const int c = a[0] + MP * (a[1] + MP * a[2]);
-                f(hbase + ha, (int64_t)c * nodes + n);
-              }
-            }
-      });
-    for (auto& t : th) t.join();
-  }
-};
+using hl_host::FieldImage;
+using hl_host::LayoutMap;
 
-LayoutMap layout_of(const hl_plan_s* pl) {
-  LayoutMap L;
-  L.d = pl->d;
-  L.MP = pl->m + 1;
-  L.nc = pl->nc;
-  for (int k = 0; k < 3; ++k) L.K[k] = pl->grid.K[k];
-  L.nodes = pl->grid.nodes;
-  return L;
+// Field 0 = p (primal), 1 = u (dual).
+LayoutMap layout_of(const hl_plan_s* pl, int field) {
+  return hl_host::field_layout(pl->d, pl->m, pl->K, pl->walls, field);
 }
 
-// BF16 bits of x rounded to nearest even (x finite); the device side of the
-// FP32_COMP format rounds the same way.
-uint16_t bf16_rne(float x) {
-  uint32_t b;
-  std::memcpy(&b, &x, 4);
-  b += 0x7fffu + ((b >> 16) & 1u);
-  return (uint16_t)(b >> 16);
-}
-float bf16_value(uint16_t h) {
-  const uint32_t b = (uint32_t)h << 16;
-  float f;
-  std::memcpy(&f, &b, 4);
-  return f;
-}
-
-// Device image of one field component: the hi (or only) word plane set and,
-// for FP32_COMP, the lo plane set; component i of ncomp sits at
-// i * hi_bytes (hi) and ncomp * hi_bytes + i * lo_bytes (lo).
-struct FieldImage {
-  int precision;
-  int64_t fw;  // coefficients per component
-  std::vector<unsigned char> hi, lo;
-  size_t hi_bytes() const { return (size_t)fw * (precision == HL_FP64 ? 8 : 4); }
-  size_t lo_bytes() const { return precision == HL_FP32_COMP ? (size_t)fw * 2 : 0; }
-  bool alloc() {
-    try {
-      hi.resize(hi_bytes());
-      lo.resize(lo_bytes());
-    } catch (const std::bad_alloc&) {
-      return false;
-    }
-    return true;
-  }
-  void put(int64_t i, double x) {
-    switch (precision) {
-      case HL_FP64: reinterpret_cast<double*>(hi.data())[i] = x; break;
-      case HL_FP32: reinterpret_cast<float*>(hi.data())[i] = (float)x; break;
-      default: {
-        const float h = (float)x;
-        reinterpret_cast<float*>(hi.data())[i] = h;
-        reinterpret_cast<uint16_t*>(lo.data())[i] = bf16_rne((float)(x - (double)h));
-      }
-    }
-  }
-  double get(int64_t i) const {
-    switch (precision) {
-      case HL_FP64: return reinterpret_cast<const double*>(hi.data())[i];
-      case HL_FP32: return (double)reinterpret_cast<const float*>(hi.data())[i];
-      default:
-        return (double)reinterpret_cast<const float*>(hi.data())[i] +
-               (double)bf16_value(reinterpret_cast<const uint16_t*>(lo.data())[i]);
-    }
-  }
-};
-
-hl_status upload_field(const hl_plan_s* pl, const double* host, int ncomp, void* dev, hipStream_t s) {
-  const LayoutMap L = layout_of(pl);
-  FieldImage im{pl->precision, (int64_t)pl->nc * pl->grid.nodes, {}, {}};
+// field 0: p (one component), field 1: u (d components).
+hl_status upload_field(const hl_plan_s* pl, const double* host, int field, void* dev, hipStream_t s) {
+  const int ncomp = field == 0 ? 1 : pl->d;
+  const LayoutMap L = layout_of(pl, field);
+  const int64_t hw = (int64_t)pl->nc * L.K[0] * L.K[1] * L.K[2];  // host words per component
+  FieldImage im{pl->precision, (int64_t)pl->nc * L.nodes, {}, {}};
   if (!im.alloc()) return fail(HL_ERR_NOMEM, "hl_init: host staging allocation failed");
   unsigned char* d = static_cast<unsigned char*>(dev);
   for (int i = 0; i < ncomp; ++i) {
-    const double* src = host ? host + (size_t)i * im.fw : nullptr;
-    if (src) {
-      L.for_each([&](int64_t h, int64_t dv) { im.put(dv, src[h]); });
-    } else {
-      std::fill(im.hi.begin(), im.hi.end(), (unsigned char)0);
-      std::fill(im.lo.begin(), im.lo.end(), (unsigned char)0);
-    }
+    const double* src = host ? host + (size_t)i * hw : nullptr;
+    // ghost nodes (walls) start at zero; the library refreshes them before use
+    std::fill(im.hi.begin(), im.hi.end(), (unsigned char)0);
+    std::fill(im.lo.begin(), im.lo.end(), (unsigned char)0);
+    if (src) L.for_each([&](int64_t h, int64_t dv) { im.put(dv, src[h]); });
     hipError_t e = hipMemcpyAsync(d + i * im.hi_bytes(), im.hi.data(), im.hi_bytes(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && im.lo_bytes())
       e = hipMemcpyAsync(d + ncomp * im.hi_bytes() + i * im.lo_bytes(), im.lo.data(), im.lo_bytes(),
@@ -504,9 +422,11 @@ hl_status upload_field(const hl_plan_s* pl, const double* host, int ncomp, void*
   return HL_OK;
 }
 
-hl_status download_field(const hl_plan_s* pl, const void* dev, int ncomp, double* host, hipStream_t s) {
-  const LayoutMap L = layout_of(pl);
-  FieldImage im{pl->precision, (int64_t)pl->nc * pl->grid.nodes, {}, {}};
+hl_status download_field(const hl_plan_s* pl, const void* dev, int field, double* host, hipStream_t s) {
+  const int ncomp = field == 0 ? 1 : pl->d;
+  const LayoutMap L = layout_of(pl, field);
+  const int64_t hw = (int64_t)pl->nc * L.K[0] * L.K[1] * L.K[2];
+  FieldImage im{pl->precision, (int64_t)pl->nc * L.nodes, {}, {}};
   if (!im.alloc()) return fail(HL_ERR_NOMEM, "hl_export: host staging allocation failed");
   const unsigned char* d = static_cast<const unsigned char*>(dev);
   for (int i = 0; i < ncomp; ++i) {
@@ -516,7 +436,7 @@ hl_status download_field(const hl_plan_s* pl, const void* dev, int ncomp, double
                          hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hl_export: copy to host");
-    double* dst = host + (size_t)i * im.fw;
+    double* dst = host + (size_t)i * hw;
     L.for_each([&](int64_t h, int64_t dv) { dst[h] = im.get(dv); });
   }
   return HL_OK;
@@ -524,7 +444,9 @@ hl_status download_field(const hl_plan_s* pl, const void* dev, int ncomp, double
 
 hl::PlanView view(const hl_plan_s* pl) {
   hl::PlanView v;
-  v.grid = pl->grid;
+  v.gp = pl->gp;
+  v.gu = pl->gu;
+  for (int k = 0; k < 3; ++k) v.uext[k] = pl->uext[k];
   v.tab = pl->dtab;
   v.d = pl->d;
   v.m = pl->m;
@@ -541,15 +463,25 @@ hl_status check_plan(const hl_plan_s* pl, const char* who) {
   return HL_OK;
 }
 
-// FP64 sum of squares of every entry of a state buffer; grid (kNormBlocks,
-// planes), one partial per (block, plane), summed on the host in a fixed
-// order so the result is deterministic.
+// FP64 sum of squares of a state buffer's nodes (ghost nodes excluded);
+// grid (kNormBlocks, planes), one partial per (block, plane), summed on the
+// host in a fixed order so the result is deterministic.  The counted nodes
+// are i + off per dimension, i in [0, K), of an array with extents E.
+struct NormBox {
+  int32_t K[3], E[3], off;
+};
+
 template <class S>
-__global__ void sumsq_kernel(typename S::View v, double* __restrict__ partial) {
+__global__ void sumsq_kernel(typename S::View v, NormBox b, double* __restrict__ partial) {
   __shared__ double red[256];
   double acc = 0.0;
-  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < v.nodes; n += (int64_t)gridDim.x * blockDim.x) {
-    const double x = (double)S::load(v, (int)blockIdx.y, (uint32_t)n);
+  const int64_t count = (int64_t)b.K[0] * b.K[1] * b.K[2];
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < count; n += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i0 = n % b.K[0], r = n / b.K[0];
+    const int64_t i1 = r % b.K[1], i2 = r / b.K[1];
+    const int64_t o1 = b.K[1] > 1 || b.E[1] > 1 ? b.off : 0, o2 = b.K[2] > 1 || b.E[2] > 1 ? b.off : 0;
+    const uint32_t node = (uint32_t)((i0 + b.off) + (int64_t)b.E[0] * ((i1 + o1) + (int64_t)b.E[1] * (i2 + o2)));
+    const double x = (double)S::load(v, (int)blockIdx.y, node);
     acc = fma(x, x, acc);
   }
   red[threadIdx.x] = acc;
@@ -562,10 +494,18 @@ __global__ void sumsq_kernel(typename S::View v, double* __restrict__ partial) {
 }
 
 template <class S>
-hl_status sumsq_as(const hl_plan_s* pl, const void* x, int ncomp, double* out) {
+hl_status sumsq_as(const hl_plan_s* pl, const void* x, int field, double* out) {
+  const int ncomp = field == 0 ? 1 : pl->d;
   const int planes = ncomp * pl->nc;
-  const typename S::View v = S::make(x, ncomp, pl->nc, pl->grid.nodes);
-  hipLaunchKernelGGL(sumsq_kernel<S>, dim3(kNormBlocks, (unsigned)planes), dim3(256), 0, 0, v, pl->dpartial);
+  const LayoutMap L = layout_of(pl, field);
+  NormBox b;
+  for (int k = 0; k < 3; ++k) {
+    b.K[k] = (int32_t)L.K[k];
+    b.E[k] = (int32_t)L.E[k];
+  }
+  b.off = (int32_t)L.off;
+  const typename S::View v = S::make(x, ncomp, pl->nc, L.nodes);
+  hipLaunchKernelGGL(sumsq_kernel<S>, dim3(kNormBlocks, (unsigned)planes), dim3(256), 0, 0, v, b, pl->dpartial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "hl_norms: launch");
   std::vector<double> part((size_t)kNormBlocks * planes);
@@ -577,12 +517,40 @@ hl_status sumsq_as(const hl_plan_s* pl, const void* x, int ncomp, double* out) {
   return HL_OK;
 }
 
-hl_status sumsq(const hl_plan_s* pl, const void* x, int ncomp, double* out) {
+hl_status sumsq(const hl_plan_s* pl, const void* x, int field, double* out) {
   switch (pl->precision) {
-    case HL_FP64: return sumsq_as<hl::PlainStore<double>>(pl, x, ncomp, out);
-    case HL_FP32: return sumsq_as<hl::PlainStore<float>>(pl, x, ncomp, out);
-    default: return sumsq_as<hl::SplitStore>(pl, x, ncomp, out);
+    case HL_FP64: return sumsq_as<hl::PlainStore<double>>(pl, x, field, out);
+    case HL_FP32: return sumsq_as<hl::PlainStore<float>>(pl, x, field, out);
+    default: return sumsq_as<hl::SplitStore>(pl, x, field, out);
   }
+}
+
+// Launch grid of one half-step: updates K[] nodes stored at index j + ooff
+// of an array with extents oext, corners from an array with extents sext
+// (lower corner at j + soff).
+bool make_grid(const hl_plan_s* pl, const int32_t* K, const int32_t* oext, int32_t ooff, const int32_t* sext,
+               int32_t soff, int64_t onodes, int64_t snodes, hl::Grid* g) {
+  const int* tile = pl->ks.tile;
+  int64_t tiles = 1;
+  for (int k = 0; k < 3; ++k) {
+    g->K[k] = K[k];
+    g->nt[k] = (K[k] + tile[k] - 1) / tile[k];
+    g->oext[k] = oext[k];
+    g->sext[k] = sext[k];
+    tiles *= g->nt[k];
+  }
+  if (tiles > (int64_t)INT32_MAX / 2) return false;
+  g->tiles = (int32_t)tiles;
+  g->per_xcd = (int32_t)((tiles + hl::kXcds - 1) / hl::kXcds);
+  // 3D: tile numbering x, then y in groups of kYGroup3 tile rows, then z
+  // (z-neighbour planes reused from L2); 1D/2D: plain row-major
+  g->ygroup = pl->d == 3 ? std::min<int32_t>(kYGroup3, g->nt[1]) : g->nt[1];
+  g->ooff = ooff;
+  g->soff = soff;
+  g->pad = 0;
+  g->onodes = onodes;
+  g->snodes = snodes;
+  return true;
 }
 
 }  // namespace
@@ -598,7 +566,8 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
   g_last_error.clear();
   if (!prob || !out) return fail(HL_ERR_ARG, "hl_plan: NULL argument");
   const hl_problem& p = *prob;
-  if (p.reserved != 0) return fail(HL_ERR_ARG, "hl_plan: reserved field must be 0");
+  if (p.reserved[0] != 0 || p.reserved[1] != 0) return fail(HL_ERR_ARG, "hl_plan: reserved fields must be 0");
+  if (p.boundary != HL_PERIODIC && p.boundary != HL_WALLS) return fail(HL_ERR_ARG, "hl_plan: unknown boundary");
   if (p.d < 1 || p.d > 3) return fail(HL_ERR_ARG, "hl_plan: d must be 1, 2 or 3");
   if (p.m < 0) return fail(HL_ERR_ARG, "hl_plan: m must be >= 0");
   if (p.m > max_m(p.d)) return fail(HL_ERR_UNSUPPORTED, "hl_plan: m too large for this dimension");
@@ -606,12 +575,12 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
     return fail(HL_ERR_ARG, "hl_plan: unknown precision");
   if (!finite_pos(p.c)) return fail(HL_ERR_ARG, "hl_plan: c must be finite and > 0");
   double hmin = INFINITY;
-  int64_t nodes = 1;
+  int64_t max_nodes = 1;  // largest device array (walls: the ghost-padded velocity)
   for (int k = 0; k < p.d; ++k) {
-    if (p.cells[k] < 2 || p.cells[k] > (int64_t)INT32_MAX) return fail(HL_ERR_ARG, "hl_plan: cells must be in [2, 2^31)");
+    if (p.cells[k] < 2 || p.cells[k] > (int64_t)INT32_MAX - 2) return fail(HL_ERR_ARG, "hl_plan: cells must be in [2, 2^31 - 2)");
     if (!finite_pos(p.length[k])) return fail(HL_ERR_ARG, "hl_plan: length must be finite and > 0");
     hmin = std::min(hmin, p.length[k] / (double)p.cells[k]);
-    nodes *= p.cells[k];
+    max_nodes *= p.cells[k] + (p.boundary == HL_WALLS ? 2 : 0);
   }
   double dt = p.dt;
   if (!std::isfinite(dt) || dt < 0.0) return fail(HL_ERR_ARG, "hl_plan: dt must be finite and >= 0");
@@ -637,13 +606,23 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
   pl->kappa = p.c * p.c;
   pl->nc = 1;
   for (int k = 0; k < p.d; ++k) pl->nc *= (p.m + 1);
+  pl->walls = p.boundary == HL_WALLS;
+  pl->uoff = pl->walls ? 1 : 0;
   for (int k = 0; k < 3; ++k) {
     pl->h[k] = k < p.d ? p.length[k] / (double)p.cells[k] : 1.0;
-    pl->grid.K[k] = k < p.d ? (int32_t)p.cells[k] : 1;
+    pl->K[k] = k < p.d ? (int32_t)p.cells[k] : 1;
   }
-  pl->grid.nodes = nodes;
+  {
+    const LayoutMap lp = layout_of(pl, 0), lu = layout_of(pl, 1);
+    for (int k = 0; k < 3; ++k) {
+      pl->pext[k] = (int32_t)lp.E[k];
+      pl->uext[k] = (int32_t)lu.E[k];
+    }
+    pl->pnodes = lp.nodes;
+    pl->unodes = lu.nodes;
+  }
   // the widest plane: FP64 words, or the FP32 (hi) planes
-  if ((double)nodes * (p.precision == HL_FP64 ? 8 : 4) >= 4294967296.0) {
+  if ((double)max_nodes * (p.precision == HL_FP64 ? 8 : 4) >= 4294967296.0) {
     delete pl;
     return fail(HL_ERR_UNSUPPORTED, "hl_plan: one coefficient plane must stay below 4 GiB");
   }
@@ -653,21 +632,20 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
     return fail(HL_ERR_UNSUPPORTED, "hl_plan: (d, m, precision) not built");
   }
   {
-    const int tx = pl->ks.tile[0], ty = pl->ks.tile[1], tz = pl->ks.tile[2];
-    pl->grid.nt[0] = (pl->grid.K[0] + tx - 1) / tx;
-    pl->grid.nt[1] = (pl->grid.K[1] + ty - 1) / ty;
-    pl->grid.nt[2] = (pl->grid.K[2] + tz - 1) / tz;
-    const int64_t tiles = (int64_t)pl->grid.nt[0] * pl->grid.nt[1] * pl->grid.nt[2];
-    if (tiles > (int64_t)INT32_MAX / 2) {
+    // p half-step: primal nodes (walls: K+1, on the walls too) from dual
+    // corners q = j - 1 + e, stored at q + uoff; u half-step: dual nodes from
+    // primal corners j = q + e
+    int32_t Kp[3], Ku[3];
+    for (int k = 0; k < 3; ++k) {
+      Kp[k] = pl->pext[k];
+      Ku[k] = pl->K[k];
+    }
+    const bool ok_p = make_grid(pl, Kp, pl->pext, 0, pl->uext, pl->uoff - 1, pl->pnodes, pl->unodes, &pl->gp);
+    const bool ok_u = make_grid(pl, Ku, pl->uext, pl->uoff, pl->pext, 0, pl->unodes, pl->pnodes, &pl->gu);
+    if (!ok_p || !ok_u) {
       delete pl;
       return fail(HL_ERR_UNSUPPORTED, "hl_plan: grid too large for the launch");
     }
-    pl->grid.tiles = (int32_t)tiles;
-    pl->grid.per_xcd = (int32_t)((tiles + hl::kXcds - 1) / hl::kXcds);
-    // 3D: tile numbering x, then y in groups of kYGroup3 tile rows, then z
-    // (z-neighbour planes reused from L2); 1D/2D: plain row-major
-    pl->grid.ygroup = p.d == 3 ? std::min<int32_t>(kYGroup3, pl->grid.nt[1]) : pl->grid.nt[1];
-    pl->grid.pad = 0;
   }
   std::vector<double> tab;
   hl_status st = build_tables(pl, tab);
@@ -720,11 +698,11 @@ hl_status hl_plan_info(hl_plan_t plan, hl_info* out) {
   if (!plan || !out) return fail(HL_ERR_ARG, "hl_plan_info: NULL argument");
   out->dt = plan->dt;
   out->nu = plan->nu;
-  out->nodes = plan->grid.nodes;
+  out->nodes = plan->pnodes;
   out->nc = plan->nc;
   out->word_bytes = plan->word_bytes;
-  out->p_words = (int64_t)plan->words_per_coef * plan->nc * plan->grid.nodes;
-  out->u_words = (int64_t)plan->d * out->p_words;
+  out->p_words = (int64_t)plan->words_per_coef * plan->nc * plan->pnodes;
+  out->u_words = (int64_t)plan->words_per_coef * plan->d * plan->nc * plan->unodes;
   return HL_OK;
 }
 
@@ -736,8 +714,8 @@ hl_status hl_init(hl_plan_t plan, const double* p0, const double* u0, uint32_t f
   if (!p0 || !p || !u) return fail(HL_ERR_ARG, "hl_init: p0, p and u must be non-NULL");
   if (flags & ~HL_INIT_STARTUP) return fail(HL_ERR_ARG, "hl_init: unknown flags");
   hipStream_t s = (hipStream_t)stream;
-  if ((st = upload_field(plan, p0, 1, p, s)) != HL_OK) return st;
-  if ((st = upload_field(plan, u0, plan->d, u, s)) != HL_OK) return st;
+  if ((st = upload_field(plan, p0, 0, p, s)) != HL_OK) return st;
+  if ((st = upload_field(plan, u0, 1, u, s)) != HL_OK) return st;
   if (flags & HL_INIT_STARTUP) {
     hipError_t e = plan->ks.u_half(view(plan), u, p, 0.5, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -754,17 +732,19 @@ hl_status hl_export(hl_plan_t plan, const void* p, const void* u, double* p_out,
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "hl_export: pending work failed");
-  if (p_out && (st = download_field(plan, p, 1, p_out, s)) != HL_OK) return st;
-  if (u_out && (st = download_field(plan, u, plan->d, u_out, s)) != HL_OK) return st;
+  if (p_out && (st = download_field(plan, p, 0, p_out, s)) != HL_OK) return st;
+  if (u_out && (st = download_field(plan, u, 1, u_out, s)) != HL_OK) return st;
   return HL_OK;
 }
 
-hl_status hl_p_half(hl_plan_t plan, void* p, const void* u, void* stream) {
+hl_status hl_p_half(hl_plan_t plan, void* p, void* u, void* stream) {
   g_last_error.clear();
   hl_status st = check_plan(plan, "hl_p_half");
   if (st != HL_OK) return st;
   if (!p || !u || p == u) return fail(HL_ERR_ARG, "hl_p_half: p and u must be distinct non-NULL buffers");
-  hipError_t e = plan->ks.p_half(view(plan), p, u, (hipStream_t)stream);
+  const hl::PlanView v = view(plan);
+  hipError_t e = plan->walls ? plan->ks.ghost(v, u, (hipStream_t)stream) : hipSuccess;
+  if (e == hipSuccess) e = plan->ks.p_half(v, p, u, (hipStream_t)stream);
   return e == hipSuccess ? HL_OK : hip_fail(e, "hl_p_half: launch");
 }
 
@@ -788,7 +768,7 @@ hl_status hl_step(hl_plan_t plan, void* p, void* u, int64_t nsteps, void* stream
   hipStream_t s = (hipStream_t)stream;
   int64_t n = 0;
   if (nsteps >= kGraphChunk) {
-    if (!plan->gexec || plan->gp != p || plan->gu != u) {
+    if (!plan->gexec || plan->graph_p != p || plan->graph_u != u) {
       hipError_t e = capture_steps(plan, v, p, u);
       if (e != hipSuccess) return hip_fail(e, "hl_step: graph capture");
     }
@@ -798,7 +778,8 @@ hl_status hl_step(hl_plan_t plan, void* p, void* u, int64_t nsteps, void* stream
     }
   }
   for (; n < nsteps; ++n) {
-    hipError_t e = plan->ks.p_half(v, p, u, s);
+    hipError_t e = plan->walls ? plan->ks.ghost(v, u, s) : hipSuccess;
+    if (e == hipSuccess) e = plan->ks.p_half(v, p, u, s);
     if (e == hipSuccess) e = plan->ks.u_half(v, u, p, 1.0, s);
     if (e != hipSuccess) return hip_fail(e, "hl_step: launch");
   }
@@ -812,8 +793,8 @@ hl_status hl_norms(hl_plan_t plan, const void* p, const void* u, double* out) {
   if (!p || !u || !out) return fail(HL_ERR_ARG, "hl_norms: NULL argument");
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hl_norms: pending work failed");
-  if ((st = sumsq(plan, p, 1, &out[0])) != HL_OK) return st;
-  if ((st = sumsq(plan, u, plan->d, &out[1])) != HL_OK) return st;
+  if ((st = sumsq(plan, p, 0, &out[0])) != HL_OK) return st;
+  if ((st = sumsq(plan, u, 1, &out[1])) != HL_OK) return st;
   if (!std::isfinite(out[0]) || !std::isfinite(out[1])) return fail(HL_ERR_NONFINITE, "hl_norms: non-finite state");
   return HL_OK;
 }

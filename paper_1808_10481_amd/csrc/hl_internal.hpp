@@ -12,7 +12,8 @@ namespace hl {
 
 // What a launcher needs from a plan.
 struct PlanView {
-  Grid grid;
+  Grid gp, gu;          // pressure / velocity half-step grids
+  int32_t uext[3];      // velocity array extents (ghost fill, walls only)
   const void* tab;      // packed operator tables in the plan's arithmetic type
   int d, m, precision;
   double ih[3];         // 1 / h_k (velocity half-step)
@@ -20,10 +21,12 @@ struct PlanView {
 
 typedef hipError_t (*PHalfFn)(const PlanView&, void* p, const void* u, hipStream_t);
 typedef hipError_t (*UHalfFn)(const PlanView&, void* u, const void* p, double wscale, hipStream_t);
+typedef hipError_t (*GhostFn)(const PlanView&, void* u, hipStream_t);
 
 struct KernelSet {
   PHalfFn p_half;
   UHalfFn u_half;
+  GhostFn ghost;         // ghost-shell refresh of a wall-bounded velocity array
   int table_words;       // TableLayout<D, M>::TOTAL
   int p_off[3];          // offsets of the pressure merged tables, per component
   int u_off;             // offset of the velocity (Q) merged table
@@ -77,14 +80,14 @@ template <int D, int M, class S>
 hipError_t launch_p(const PlanView& pv, void* p, const void* u, hipStream_t s) {
   using T = typename S::C;
   constexpr int NC = Dims<D, M>::NC;
-  const typename S::View vp = S::make(p, 1, NC, pv.grid.nodes);
-  const typename S::View vu = S::make(u, D, NC, pv.grid.nodes);
+  const Grid& g = pv.gp;
+  const typename S::View vp = S::make(p, 1, NC, g.onodes);
+  const typename S::View vu = S::make(u, D, NC, g.snodes);
   if constexpr (D == 3)
-    hipLaunchKernelGGL((p_half_3d<M, S>), grid_shape(pv.grid), block_shape<D>(), 0, s, vp, vu, (const T*)pv.tab,
-                       pv.grid);
+    hipLaunchKernelGGL((p_half_3d<M, S>), grid_shape(g), block_shape<D>(), 0, s, vp, vu, (const T*)pv.tab, g);
   else
-    hipLaunchKernelGGL((p_half_kernel<D, M, S>), grid_shape(pv.grid), block_shape<D>(), 0, s, vp, vu,
-                       (const T*)pv.tab, pv.grid);
+    hipLaunchKernelGGL((p_half_kernel<D, M, S>), grid_shape(g), block_shape<D>(), 0, s, vp, vu, (const T*)pv.tab,
+                       g);
   return hipGetLastError();
 }
 
@@ -92,14 +95,32 @@ template <int D, int M, class S>
 hipError_t launch_u(const PlanView& pv, void* u, const void* p, double wscale, hipStream_t s) {
   using T = typename S::C;
   constexpr int NC = Dims<D, M>::NC;
-  const typename S::View vu = S::make(u, D, NC, pv.grid.nodes);
-  const typename S::View vp = S::make(p, 1, NC, pv.grid.nodes);
+  const Grid& g = pv.gu;
+  const typename S::View vu = S::make(u, D, NC, g.onodes);
+  const typename S::View vp = S::make(p, 1, NC, g.snodes);
   if constexpr (D == 3)
-    hipLaunchKernelGGL((u_half_3d<M, S>), grid_shape(pv.grid), block_shape<D>(), 0, s, vu, vp, (const T*)pv.tab,
-                       pv.grid, (T)wscale, (T)pv.ih[0], (T)pv.ih[1], (T)pv.ih[2]);
+    hipLaunchKernelGGL((u_half_3d<M, S>), grid_shape(g), block_shape<D>(), 0, s, vu, vp, (const T*)pv.tab, g,
+                       (T)wscale, (T)pv.ih[0], (T)pv.ih[1], (T)pv.ih[2]);
   else
-    hipLaunchKernelGGL((u_half_kernel<D, M, S>), grid_shape(pv.grid), block_shape<D>(), 0, s, vu, vp,
-                       (const T*)pv.tab, pv.grid, (T)wscale, (T)pv.ih[0], (T)pv.ih[1], (T)pv.ih[2]);
+    hipLaunchKernelGGL((u_half_kernel<D, M, S>), grid_shape(g), block_shape<D>(), 0, s, vu, vp, (const T*)pv.tab,
+                       g, (T)wscale, (T)pv.ih[0], (T)pv.ih[1], (T)pv.ih[2]);
+  return hipGetLastError();
+}
+
+template <int D, int M, class S>
+hipError_t launch_ghost(const PlanView& pv, void* u, hipStream_t s) {
+  constexpr int NC = Dims<D, M>::NC;
+  int64_t nodes = 1, face = 0;
+  for (int k = 0; k < D; ++k) nodes *= pv.uext[k];
+  for (int k = 0; k < D; ++k) {
+    int64_t f = 2;
+    for (int j = 0; j < D; ++j)
+      if (j != k) f *= (j < k) ? (pv.uext[j] - 2) : pv.uext[j];
+    face = f > face ? f : face;
+  }
+  const typename S::View vu = S::make(u, D, NC, nodes);
+  hipLaunchKernelGGL((ghost_fill<D, M, S>), dim3((unsigned)((face + 255) / 256), D, 1), dim3(256, 1, 1), 0, s, vu,
+                     pv.uext[0], pv.uext[1], pv.uext[2]);
   return hipGetLastError();
 }
 
@@ -108,6 +129,7 @@ inline bool make_set(KernelSet* out) {
   fill_layout<D, M>(out);
   out->p_half = &launch_p<D, M, S>;
   out->u_half = &launch_u<D, M, S>;
+  out->ghost = &launch_ghost<D, M, S>;
   return true;
 }
 

@@ -15,7 +15,16 @@
 // type, S::load / S::update / S::planes / S::bload the only memory accesses
 // to the state.  Planes are coefficient-major: plane index
 // comp * (m+1)^d + c, c = a_1 + (m+1)(a_2 + (m+1) a_3), node
-// n = j_1 + K_1 (j_2 + K_2 j_3).
+// n = i_1 + E_1 (i_2 + E_2 i_3) in an array of extents E.
+//
+// Boundaries.  Periodic: both grids have K nodes per dimension, corner
+// indices wrap.  Reflecting walls: the primal grid has K+1 nodes (the end
+// nodes on the walls), the dual grid K nodes stored inside a (K+2)-node array
+// whose outer shell holds ghost nodes (filled by ghost_fill before every
+// pressure half-step); no index wraps.  A Grid describes one half-step: the
+// nodes it updates (K, stored at index j + ooff of the output array) and the
+// corner array (corner lo of node j at j + soff, hi at lo + 1, wrapped into
+// [0, sext) for periodic grids).
 //
 // Launch: tiles of TileShape nodes, one workgroup per tile.  Workgroup i runs
 // on XCD i mod 8 and takes tile number t = (i mod 8) * per_xcd + i / 8, so
@@ -53,13 +62,18 @@ namespace hl {
 constexpr int kXcds = 8;
 
 struct Grid {
-  int32_t K[3];       // nodes per dimension (1 for unused dimensions)
+  int32_t K[3];       // nodes updated per dimension (1 for unused dimensions)
   int32_t nt[3];      // tiles per dimension
   int32_t tiles;      // nt[0] * nt[1] * nt[2]
   int32_t per_xcd;    // ceil(tiles / kXcds)
   int32_t ygroup;     // tile rows per group in the tile numbering, 1..nt[1]
+  int32_t ooff;       // output node j is stored at index j + ooff (0, or 1 in a ghost-padded array)
+  int32_t oext[3];    // output array extents
+  int32_t soff;       // lower corner of node j at index j + soff (-1 or 0)
+  int32_t sext[3];    // corner (source) array extents
   int32_t pad;
-  int64_t nodes;      // K[0] * K[1] * K[2]
+  int64_t onodes;     // output array nodes (plane size)
+  int64_t snodes;     // source array nodes (plane size)
 };
 
 template <int D>
@@ -114,19 +128,38 @@ __device__ __forceinline__ bool node_of_thread(const Grid& g, int32_t* j) {
 }
 
 template <int D>
-__device__ __forceinline__ uint32_t node_index(int32_t x, int32_t y, int32_t z, const Grid& g) {
+__device__ __forceinline__ uint32_t node_index(int32_t x, int32_t y, int32_t z, const int32_t* E) {
   uint32_t n = (uint32_t)x;
-  if (D > 1) n += (uint32_t)g.K[0] * (uint32_t)y;
-  if (D > 2) n += (uint32_t)g.K[0] * (uint32_t)g.K[1] * (uint32_t)z;
+  if (D > 1) n += (uint32_t)E[0] * (uint32_t)y;
+  if (D > 2) n += (uint32_t)E[0] * (uint32_t)E[1] * (uint32_t)z;
   return n;
 }
 
-// Node indices of the 2^d cell corners e (bit k of e: upper side in dimension k).
+// Index of this work-item's output node in the output array.
 template <int D>
-__device__ __forceinline__ void corner_nodes(const Grid& g, const int32_t* lo, const int32_t* hi, uint32_t* cn) {
+__device__ __forceinline__ uint32_t out_index(const Grid& g, const int32_t* j) {
+  return node_index<D>(j[0] + g.ooff, j[1] + g.ooff, j[2] + g.ooff, g.oext);
+}
+
+// Node indices of the 2^d cell corners e (bit k of e: upper side in
+// dimension k): lo = j + soff and hi = lo + 1, wrapped into the source array.
+template <int D>
+__device__ __forceinline__ void corner_nodes(const Grid& g, const int32_t* j, uint32_t* cn) {
+  int32_t lo[3], hi[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k < D) {
+      lo[k] = j[k] + g.soff;
+      hi[k] = lo[k] + 1;
+      if (lo[k] < 0) lo[k] += g.sext[k];
+      if (hi[k] == g.sext[k]) hi[k] = 0;
+    } else {
+      lo[k] = hi[k] = 0;
+    }
+  }
 #pragma unroll
   for (int e = 0; e < (1 << D); ++e)
-    cn[e] = node_index<D>((e & 1) ? hi[0] : lo[0], (e & 2) ? hi[1] : lo[1], (e & 4) ? hi[2] : lo[2], g);
+    cn[e] = node_index<D>((e & 1) ? hi[0] : lo[0], (e & 2) ? hi[1] : lo[1], (e & 4) ? hi[2] : lo[2], g.sext);
 }
 
 // p -= acc at node n0.
@@ -232,14 +265,8 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_kernel(typename S
   constexpr int NNZ = merged_nnz<D, M>(false);
   int32_t j[3];
   if (!node_of_thread<D>(g, j)) return;
-  int32_t lo[3], hi[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    lo[k] = (j[k] == 0 ? g.K[k] : j[k]) - 1;  // dual q = j - 1 (wrapped)
-    hi[k] = j[k];                              // dual q = j
-  }
   uint32_t cn[1 << D];
-  corner_nodes<D>(g, lo, hi, cn);
+  corner_nodes<D>(g, j, cn);  // dual q = j - 1 + e (p) or primal j = q + e (u)
   T acc[NC];
 #pragma unroll
   for (int s = 0; s < NC; ++s) acc[s] = T(0);
@@ -250,7 +277,7 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_kernel(typename S
     // last component: interpolation pass in x, derivative in the merged table
     slice_pair_merge<D, M, false, 0, 1, S>(u, D - 1, cn, l, tab + TL::P_B_OFF + l * NNZ, acc);
   }
-  finish_pressure<D, M, S>(p, node_index<D>(j[0], j[1], j[2], g), acc);
+  finish_pressure<D, M, S>(p, out_index<D>(g, j), acc);
 }
 
 // Velocity half-step at every dual node (1D and 2D), weights scaled by wscale.
@@ -267,21 +294,15 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_kernel(typename S
   constexpr int NNZ = merged_nnz<D, M>(true);
   int32_t j[3];
   if (!node_of_thread<D>(g, j)) return;
-  int32_t lo[3], hi[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    lo[k] = j[k];                                  // primal j = q
-    hi[k] = (j[k] + 1 == g.K[k]) ? 0 : j[k] + 1;   // primal j = q + 1 (wrapped)
-  }
   uint32_t cn[1 << D];
-  corner_nodes<D>(g, lo, hi, cn);
+  corner_nodes<D>(g, j, cn);  // dual q = j - 1 + e (p) or primal j = q + e (u)
   T Q[NG];
 #pragma unroll
   for (int o = 0; o < NG; ++o) Q[o] = T(0);
 #pragma unroll
   for (int l = 0; l < MP; ++l) slice_pair_merge<D, M, true, 0, 0, S>(p, 0, cn, l, tab + TL::U_OFF + l * NNZ, Q);
   const T ih[3] = {ih0, ih1, ih2};
-  finish_velocity<D, M, S>(u, node_index<D>(j[0], j[1], j[2], g), Q, wscale, ih);
+  finish_velocity<D, M, S>(u, out_index<D>(g, j), Q, wscale, ih);
 }
 
 // ---------------------------------------------------------------------------
@@ -359,14 +380,8 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_3d(typename S::Vi
   constexpr int NNZ = Merge3Spec<M, false, 0, 0>::NNZ;
   int32_t j[3];
   if (!node_of_thread<3>(g, j)) return;
-  int32_t lo[3], hi[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    lo[k] = (j[k] == 0 ? g.K[k] : j[k]) - 1;  // dual q = j - 1 (wrapped)
-    hi[k] = j[k];                              // dual q = j
-  }
   uint32_t cn[8];
-  corner_nodes<3>(g, lo, hi, cn);
+  corner_nodes<3>(g, j, cn);  // dual q = j - 1 + e (p) or primal j = q + e (u)
   T acc[NC];
 #pragma unroll
   for (int s = 0; s < NC; ++s) acc[s] = T(0);
@@ -391,7 +406,7 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_3d(typename S::Vi
         merge3<M, false, 0, 1>(tab + TL::p_off(2) + blk * NNZ, ay, az, X, acc);
       }
     }
-  finish_pressure<3, M, S>(p, node_index<3>(j[0], j[1], j[2], g), acc);
+  finish_pressure<3, M, S>(p, out_index<3>(g, j), acc);
 }
 
 template <int M, class S>
@@ -406,14 +421,8 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_3d(typename S::Vi
   constexpr int NNZ = Merge3Spec<M, true, 0, 0>::NNZ;
   int32_t j[3];
   if (!node_of_thread<3>(g, j)) return;
-  int32_t lo[3], hi[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    lo[k] = j[k];                                  // primal j = q
-    hi[k] = (j[k] + 1 == g.K[k]) ? 0 : j[k] + 1;   // primal j = q + 1 (wrapped)
-  }
   uint32_t cn[8];
-  corner_nodes<3>(g, lo, hi, cn);
+  corner_nodes<3>(g, j, cn);  // dual q = j - 1 + e (p) or primal j = q + e (u)
   T Q[NG];
 #pragma unroll
   for (int o = 0; o < NG; ++o) Q[o] = T(0);
@@ -427,7 +436,68 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_3d(typename S::Vi
       merge3<M, true, 0, 0>(tab + TL::U_OFF + blk * NNZ, ay, az, X, Q);
     }
   const T ih[3] = {ih0, ih1, ih2};
-  finish_velocity<3, M, S>(u, node_index<3>(j[0], j[1], j[2], g), Q, wscale, ih);
+  finish_velocity<3, M, S>(u, out_index<3>(g, j), Q, wscale, ih);
+}
+
+// ---------------------------------------------------------------------------
+// Ghost dual nodes for reflecting walls (Sec. 5, "Imposing reflective boundary
+// conditions"): p = 0 on the walls makes p odd across each wall, so by
+// u_t = -grad p the normal velocity component is even and the tangential ones
+// odd.  The velocity array is padded by one node per side (extents E_k =
+// K_k + 2); each shell node is the mirror of the interior node reached by
+// reflecting every ghost index across its wall (0 <- 1, E-1 <- E-2).  A scaled
+// coefficient mirrored in dimension k gets (-1)^{a_k}, and -1 more for a
+// tangential component (i != k).  Edge and corner ghosts are mirrors in
+// several dimensions at once.
+//
+// Launch: grid (ceil(max face nodes / 256), D), block 256.  Face k (grid y)
+// holds the shell nodes whose first ghost index is in dimension k: index k in
+// {0, E_k - 1}, indices j < k interior, indices j > k anything; every shell
+// node is written by exactly one work-item.
+// ---------------------------------------------------------------------------
+template <int D, int M, class S>
+__global__ void __launch_bounds__(256) ghost_fill(typename S::View u, int32_t E0, int32_t E1, int32_t E2) {
+  using T = typename S::C;
+  constexpr int MP = M + 1, NC = Dims<D, M>::NC;
+  const int32_t E[3] = {E0, E1, E2};
+  const int k = blockIdx.y;
+  int64_t cnt = 2;
+  for (int j = 0; j < D; ++j)
+    if (j != k) cnt *= (j < k) ? (E[j] - 2) : E[j];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  int32_t idx[3] = {0, 0, 0};
+  int64_t r = t / 2;
+  for (int j = 0; j < D; ++j) {
+    if (j == k) {
+      idx[j] = (t % 2) ? E[j] - 1 : 0;
+    } else if (j < k) {
+      idx[j] = 1 + (int32_t)(r % (E[j] - 2));
+      r /= (E[j] - 2);
+    } else {
+      idx[j] = (int32_t)(r % E[j]);
+      r /= E[j];
+    }
+  }
+  int32_t src[3] = {0, 0, 0};
+  bool mir[3] = {false, false, false};
+  for (int j = 0; j < D; ++j) {
+    mir[j] = idx[j] == 0 || idx[j] == E[j] - 1;
+    src[j] = idx[j] == 0 ? 1 : (idx[j] == E[j] - 1 ? E[j] - 2 : idx[j]);
+  }
+  const uint32_t n_dst = node_index<D>(idx[0], idx[1], idx[2], E);
+  const uint32_t n_src = node_index<D>(src[0], src[1], src[2], E);
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      bool neg = false;
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        if (mir[j]) neg ^= ((digit(c, MP, j) & 1) != 0) != (i != j);
+      const T v = S::load(u, i * NC + c, n_src);
+      S::store(u, i * NC + c, n_dst, neg ? -v : v);
+    }
 }
 
 }  // namespace hl

@@ -53,6 +53,9 @@ struct PlainStore {
     W* q = reinterpret_cast<W*>(plane(v, pl) + node * (uint32_t)sizeof(W));
     *q = f(*q);
   }
+  __device__ static __forceinline__ void store(const View& v, int pl, uint32_t node, C x) {
+    *reinterpret_cast<W*>(plane(v, pl) + node * (uint32_t)sizeof(W)) = x;
+  }
 
   // Buffer-descriptor loads (3D kernels): one descriptor per plane.
   struct Planes {
@@ -109,6 +112,9 @@ struct SplitStore {
     const float hi = (float)val;
     *qh = hi;
     *ql = to_bf16((float)(val - (double)hi));
+  }
+  __device__ static __forceinline__ void store(const View& v, int pl, uint32_t node, C x) {
+    update(v, pl, node, [&](C) { return x; });
   }
 
   struct Planes {

@@ -19,6 +19,8 @@ LIB_PATH = os.environ.get("HL_LIBRARY", os.path.join(_HERE, "libhermite_lf.so"))
 HL_OK, HL_ERR_ARG, HL_ERR_CFL, HL_ERR_UNSUPPORTED, HL_ERR_DEVICE, HL_ERR_NOMEM, HL_ERR_NONFINITE = range(7)
 HL_FP64, HL_FP32, HL_FP32_COMP = 0, 1, 2
 PRECISIONS = {"fp64": HL_FP64, "fp32": HL_FP32, "fp32_comp": HL_FP32_COMP}
+HL_PERIODIC, HL_WALLS = 0, 1
+BOUNDARIES = {"periodic": HL_PERIODIC, "walls": HL_WALLS}
 HL_INIT_STARTUP = 1
 
 STATUS_NAMES = {0: "HL_OK", 1: "HL_ERR_ARG", 2: "HL_ERR_CFL", 3: "HL_ERR_UNSUPPORTED",
@@ -32,7 +34,8 @@ EXPORTS = ("hl_plan", "hl_plan_destroy", "hl_plan_info", "hl_init", "hl_export",
 class HLProblem(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("m", ctypes.c_int32), ("cells", ctypes.c_int64 * 3),
                 ("length", ctypes.c_double * 3), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("c", ctypes.c_double), ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("c", ctypes.c_double), ("precision", ctypes.c_int32), ("boundary", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class HLInfo(ctypes.Structure):
@@ -89,7 +92,8 @@ def _check(status: int):
         raise HLError(status, lib().hl_last_error().decode())
 
 
-def make_problem(d, m, cells, length=None, dt=0.0, cfl=0.5, c=1.0, precision="fp64") -> HLProblem:
+def make_problem(d, m, cells, length=None, dt=0.0, cfl=0.5, c=1.0, precision="fp64",
+                 boundary="periodic") -> HLProblem:
     cells = tuple(int(k) for k in cells)
     length = tuple(float(v) for v in (length if length is not None else (1.0,) * d))
     pr = HLProblem()
@@ -99,7 +103,8 @@ def make_problem(d, m, cells, length=None, dt=0.0, cfl=0.5, c=1.0, precision="fp
         pr.length[k] = length[k] if k < len(length) else 1.0
     pr.dt, pr.cfl, pr.c = float(dt), float(cfl), float(c)
     pr.precision = PRECISIONS[precision]
-    pr.reserved = 0
+    pr.boundary = BOUNDARIES[boundary]
+    pr.reserved[0] = pr.reserved[1] = 0
     return pr
 
 
@@ -113,9 +118,10 @@ def _stream_ptr(stream):
 class Plan:
     """A plan for one periodic problem; owns the library handle."""
 
-    def __init__(self, d, m, cells, length=None, dt=0.0, cfl=0.5, c=1.0, precision="fp64"):
-        self.problem = make_problem(d, m, cells, length, dt, cfl, c, precision)
-        self.d, self.m, self.precision = int(d), int(m), precision
+    def __init__(self, d, m, cells, length=None, dt=0.0, cfl=0.5, c=1.0, precision="fp64",
+                 boundary="periodic"):
+        self.problem = make_problem(d, m, cells, length, dt, cfl, c, precision, boundary)
+        self.d, self.m, self.precision, self.boundary = int(d), int(m), precision, boundary
         self.cells = tuple(int(k) for k in cells)
         h = ctypes.c_void_p()
         _check(lib().hl_plan(ctypes.byref(self.problem), ctypes.byref(h)))
@@ -154,8 +160,10 @@ class Plan:
         return p, u
 
     def host_shapes(self):
-        pshape = self.cells + (self.m + 1,) * self.d
-        return pshape, (self.d,) + pshape
+        """Host array shapes of p and u (walls: K+1 primal nodes per dimension)."""
+        extra = 1 if self.boundary == "walls" else 0
+        coef = (self.m + 1,) * self.d
+        return tuple(k + extra for k in self.cells) + coef, (self.d,) + self.cells + coef
 
     def init(self, p, u, p0, u0=None, startup=False, stream=None):
         """p0, u0: FP64 host arrays in host layout (C order [j..][a..])."""
@@ -187,8 +195,7 @@ class Plan:
     @property
     def coef_bytes(self):
         """Bytes per stored coefficient (8, 4, or 6 for fp32_comp)."""
-        i = self.info
-        return i.word_bytes * i.p_words // (i.nc * i.nodes)
+        return {"fp64": 8, "fp32": 4, "fp32_comp": 6}[self.precision]
 
     def step(self, p, u, nsteps=1, stream=None):
         self._check_buf(p, u)

@@ -9,7 +9,8 @@ path's tests and the oracle's tests take their inputs from here.
 Host layout of every array: C order, node axes (x_1..x_d) then coefficient
 axes (a_1..a_d); velocity arrays have a leading component axis.  Primal node
 j sits at x = j*h, dual node q at x = (q + 1/2)*h, on the periodic box
-[0, length).
+[0, length) (K nodes per grid), or on the walled box [0, length] (primal
+j = 0..K, dual q = 0..K-1).
 """
 
 from __future__ import annotations
@@ -81,6 +82,29 @@ def standing_mode(d, m, K, length, waves, t_p, t_u, kappa=1.0):
     return P, U
 
 
+def box_mode(d, m, K, length, waves, t_p, t_u, kappa=1.0, ghosts=False):
+    """Standing mode of the box with p = 0 on its faces:
+    p = cos(w t) prod_k sin(a_k x_k),
+    u_i = -(sin(w t)/w) a_i cos(a_i x_i) prod_{k!=i} sin(a_k x_k),
+    a_k = pi waves_k / length_k, w = sqrt(kappa) |a|.  P at t_p on the K+1
+    primal nodes, U at t_u on the K dual nodes (with ghosts: on q = -1..K,
+    the closed form evaluated at the ghost positions)."""
+    K = tuple(int(k) for k in K)
+    length = tuple(float(v) for v in length)
+    h = [length[k] / K[k] for k in range(d)]
+    a = [pi * waves[k] / length[k] for k in range(d)]
+    w = sqrt(kappa) * sqrt(sum(x * x for x in a))
+    xp = [np.arange(K[k] + 1) * h[k] for k in range(d)]
+    g = 1 if ghosts else 0
+    xd = [(np.arange(-g, K[k] + g) + 0.5) * h[k] for k in range(d)]
+    P = np.cos(w * t_p) * outer([scaled_sin(xp[k], a[k], 0.0, h[k], m) for k in range(d)])
+    U = np.empty((d,) + tuple(len(x) for x in xd) + (m + 1,) * d, dtype=np.float64)
+    for i in range(d):
+        fac = [scaled_sin(xd[k], a[k], pi / 2 if k == i else 0.0, h[k], m) for k in range(d)]
+        U[i] = -(np.sin(w * t_u) / w) * a[i] * outer(fac)
+    return P, U
+
+
 def gaussian_pulse(d, m, K, length, center, width):
     """p0 = prod_k exp(-(s_k/width)^2), s_k the minimum-image distance of x_k to
     center_k on the periodic box; returned as primal scaled data."""
@@ -103,6 +127,20 @@ def random_data(rng, d, m, K, ncomp=None):
     return rng.uniform(-1.0, 1.0, size=shape)
 
 
+def zero_on_walls(P, d):
+    """Pressure data on the K+1 primal nodes of a walled box with p = 0 on the
+    faces: at a node on the wall normal to x_k every coefficient of even order
+    a_k is zero (p odd across the wall).  Returns a copy."""
+    P = np.array(P, dtype=np.float64, copy=True)
+    for k in range(d):
+        for j in (0, P.shape[k] - 1):
+            idx = [slice(None)] * (2 * d)
+            idx[k] = j
+            idx[d + k] = slice(0, None, 2)
+            P[tuple(idx)] = 0.0
+    return P
+
+
 # ---------------------------------------------------------------------------
 # Workloads (seeded recipes)
 # ---------------------------------------------------------------------------
@@ -120,6 +158,7 @@ class Workload:
     U0: np.ndarray | None = None      # U at t0 + dt/2, or U(t0) when startup
     startup: bool = False
     exact: object = None              # callable(t) -> P at time t, or None
+    boundary: str = "periodic"        # or "walls" (p = 0 on the box faces)
 
     @property
     def h(self):
@@ -155,6 +194,28 @@ def standing_mode_2d(seed=1, K=1024, m=3, nu=0.5, steps=1000, make_data=True):
     if make_data:
         wl.P0, wl.U0 = standing_mode(2, m, wl.K, wl.length, kl, 0.0, wl.dt / 2)
         wl.exact = lambda t: standing_mode(2, m, wl.K, wl.length, kl, t, t)[0]
+    return wl
+
+
+def gaussian_pulse_walls_2d(seed=3, K=1024, m=3, nu=0.5, steps=1000, make_data=True):
+    """Gaussian pressure pulse exp(-r^2/0.002) in the walled square [0, 2]^2
+    (the [-1, 1]^2 box shifted), centre 0.3 from the centre of the box plus a
+    seeded offset of at most 0.05 per axis, u(t0) = 0 (start-up builds u at
+    dt/2).  At the walls the pulse is below 1e-100; its even coefficients on
+    the wall nodes are set to zero so the data satisfy p = 0 there exactly."""
+    rng = np.random.default_rng(seed)
+    center = tuple(1.3 + 0.05 * float(v) for v in rng.uniform(-1, 1, 2))
+    wl = Workload("gaussian_pulse_walls_2d", 2, m, (K, K), (2.0, 2.0), nu, 1.0, steps)
+    wl.center = center
+    wl.startup = True
+    wl.boundary = "walls"
+    if make_data:
+        h = 2.0 / K
+        x = np.arange(K + 1) * h
+        width = sqrt(0.002)
+        P = outer([scaled_gauss(x - center[k], width, h, m) for k in range(2)])
+        wl.P0 = zero_on_walls(P, 2)
+        wl.U0 = np.zeros((2, K, K) + (m + 1,) * 2)
     return wl
 
 

@@ -73,13 +73,19 @@ def test_plan_rejects_unknown_precision_and_oversized_planes():
         assert st == hl.HL_ERR_UNSUPPORTED and "4 GiB" in msg, (prec, st, msg)
     st, msg, h = _plan_status(d=3, m=0, cells=(1024, 1024, 512), precision="fp64")
     assert st == hl.HL_ERR_UNSUPPORTED and "4 GiB" in msg
+    # walls: the ghost-padded velocity array sets the size (1023 x 1023 x 1022 cells pad to 1025 x 1025 x 1024 >= 2^30 nodes)
+    st, msg, h = _plan_status(d=3, m=0, cells=(1023, 1023, 1022), precision="fp32", boundary="walls")
+    assert st == hl.HL_ERR_UNSUPPORTED and "4 GiB" in msg
 
 
 def test_plan_rejects_null_and_reserved():
     h = ctypes.c_void_p()
     assert hl.lib().hl_plan(None, ctypes.byref(h)) == hl.HL_ERR_ARG
     pr = hl.make_problem(1, 1, (8,))
-    pr.reserved = 1
+    pr.reserved[1] = 1
+    assert hl.lib().hl_plan(ctypes.byref(pr), ctypes.byref(h)) == hl.HL_ERR_ARG
+    pr = hl.make_problem(1, 1, (8,))
+    pr.boundary = 2
     assert hl.lib().hl_plan(ctypes.byref(pr), ctypes.byref(h)) == hl.HL_ERR_ARG
 
 

@@ -1,17 +1,5 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle,
-element by element on the same seeded inputs.
-
-Tolerances.  FP64: relative L2 <= 1e-12 and max |diff| <= 1e-11 max |ref|
-(only summation order differs).  FP32: every output is the input minus a
-sum of n ~ (2m+2)^d rounded products (tables rounded to FP32 too); with
-random rounding the sum's error grows like sqrt(n) u, u = 2^-24, times the
-size of the terms, which for random (non-smooth) data exceeds the result by
-a factor up to ~16.  Bound used: relative L2 <= 16 sqrt(n) u_32 * 16 =
-256 sqrt(n) 2^-24 (about 1.2e-5 for d = 2, m = 5), max <= 4x that.
-FP32_COMP: FP64 arithmetic, then the result is stored as hi + lo with
-|x - hi| <= 2^-24 |x| and lo the BF16 rounding of x - hi (relative error
-2^-9), so every stored entry is within 2^-33 |x| of the FP64 result; bound
-used: relative L2 and max |diff| / max |ref| <= 2^-32 + 1e-12.
+element by element on the same seeded inputs.  Tolerances: tolerances.py.
 """
 
 import sys
@@ -22,6 +10,7 @@ import pytest
 import oracle
 from oracle.diagnostics import rel_l2
 from paper_1808_10481_amd import inputs
+from tolerances import COMP_TOL, _close, tol
 
 pytestmark = pytest.mark.gpu
 
@@ -39,27 +28,6 @@ def _say(*a):
 def _prob(d, m, K, dt, kappa=1.0):
     return oracle.Problem(d, m, tuple(K), tuple(1.0 for _ in K), dt, kappa)
 
-
-def _close(got, ref, tol_l2, tol_max):
-    r = rel_l2(got, ref)
-    mx = np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300)
-    assert r <= tol_l2 and mx <= tol_max, (r, mx)
-    return r
-
-
-TOL = {"fp64": (1e-12, 1e-11), "fp32": (3e-6, 1e-5)}
-
-
-COMP_TOL = 2.0 ** -32 + 1e-12
-
-
-def tol(prec, d, m):
-    if prec == "fp64":
-        return TOL["fp64"]
-    if prec == "fp32_comp":
-        return (COMP_TOL, COMP_TOL)
-    t = 256.0 * np.sqrt((2 * m + 2) ** d) * 2.0 ** -24
-    return (t, 4 * t)
 
 CASES = (
     [(1, m, (37,)) for m in range(0, 8)] + [(1, 1, (200,)), (1, 3, (2,))]
