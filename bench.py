@@ -196,6 +196,44 @@ def run_walls(hl, torch, steps, K=1024, m=3):
     return res
 
 
+def run_adjoint(hl, torch, steps, K=512, m=2):
+    """Discrete adjoint on the shape of the gradient workload (2D, m=2, 512^2,
+    periodic, constant kappa): `steps` transposed steps alone, then `steps`
+    steps with the kappa gradient (forward state walked back by the reversed
+    step, two inner products per step).  Forward steps timed beside them."""
+    from paper_1808_10481_amd import inputs
+    res = {}
+    for prec in ("fp32", "fp64"):
+        log(f"[bench] adjoint 2d m={m} {K}^2 {prec}: {steps} steps")
+        rng = np.random.default_rng(4)
+        plan = hl.Plan(2, m, (K, K), cfl=0.5, c=1.0, precision=prec)
+        p, u = plan.alloc()
+        pb, ub = plan.alloc()
+        plan.init(p, u, inputs.random_data(rng, 2, m, (K, K)), inputs.random_data(rng, 2, m, (K, K), ncomp=2))
+        plan.init(pb, ub, inputs.random_data(rng, 2, m, (K, K)), inputs.random_data(rng, 2, m, (K, K), ncomp=2))
+        g = torch.zeros(1, dtype=torch.float64, device="cuda")
+        plan.adjoint_step(pb, ub, 2, p=p, u=u, grad_kappa=g)     # warm-up, allocates the gradient buffers
+        stream = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        plan.step(p, u, steps)
+        ev[1].record(stream)
+        plan.adjoint_step(pb, ub, steps)
+        ev[2].record(stream)
+        plan.adjoint_step(pb, ub, steps, p=p, u=u, grad_kappa=g)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        fwd, adj, grd = (ev[i].elapsed_time(ev[i + 1]) / steps for i in range(3))
+        res[prec] = {"forward_ms_per_step": fwd, "adjoint_ms_per_step": adj, "gradient_ms_per_step": grd,
+                     "adjoint_cell_updates_per_s": K * K / (adj * 1e-3), "steps": steps}
+        plan.close()
+        del p, u, pb, ub
+        torch.cuda.empty_cache()
+    res["config"] = {"workload": f"adjoint_2d m={m} {K}^2 periodic constant kappa", "d": 2, "m": m, "cells": [K, K]}
+    return res
+
+
 def copy_probe(torch, nbytes=1 << 30, reps=20):
     """Plain device copy y <- x of nbytes (the paper's "realistic peak"
     vector-copy measurement); GB/s counts bytes read + written."""
@@ -253,6 +291,8 @@ def main():
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--steps-3d", type=int, default=50)
     ap.add_argument("--no-walls", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--steps-adjoint", type=int, default=100)
     ap.add_argument("--steps-walls", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -327,6 +367,9 @@ def main():
 
     if not args.no_walls:
         out["gaussian_pulse_walls_2d"] = run_walls(hl, torch, args.steps_walls)
+
+    if not args.no_adjoint:
+        out["adjoint_2d"] = run_adjoint(hl, torch, args.steps_adjoint)
 
     if not args.no_copy_probe:
         out["copy_probe"] = copy_probe(torch)

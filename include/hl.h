@@ -178,8 +178,25 @@ hl_status hl_u_half(hl_plan_t plan, void* u, const void* p, double weight_scale,
  * finite.  Synchronous. */
 hl_status hl_norms(hl_plan_t plan, const void* p, const void* u, double* out);
 
-/* Discrete adjoint of hl_step (gradient of a misfit with respect to kappa).
- * Not built yet: always returns HL_ERR_UNSUPPORTED. */
+/* Discrete adjoint of hl_step: nsteps transposed steps applied in place to
+ * the adjoint state (p_bar, u_bar) (device buffers laid out like p and u).
+ * A step maps (P, U) to P' = P - A U, U' = U - B P'; its transpose is
+ * p_bar <- p_bar - B^T u_bar, then u_bar <- u_bar - A^T p_bar (the transposed
+ * half-steps in reverse order; each is a gather with the forward stencil).
+ * So <step^n(x), y> = <x, adjoint^n(y)> for the plain inner product of all
+ * coefficients.
+ * grad_kappa == NULL: p and u are unused (may be NULL).
+ * grad_kappa != NULL: a device pointer to one FP64 value, to which the
+ *   derivative with respect to kappa (dt held fixed) of
+ *   <p_bar, P_n> + <u_bar, U_n> (the adjoint state as passed in) is ADDED;
+ *   p, u hold the forward state (P_n, U_n) after the n steps.  The library
+ *   walks that state back step by step with the reversed step (half-steps
+ *   with -dt in reverse order; exact in exact arithmetic) in buffers of its
+ *   own, allocated on first use (p and u are not modified), and accumulates
+ *   each step's contribution in FP64.
+ * Built for periodic plans in HL_FP64 and HL_FP32 with (m+1)^d <= 27 (d = 1
+ * all m, d = 2 m <= 4, d = 3 m <= 2); HL_ERR_UNSUPPORTED otherwise.
+ * Asynchronous. */
 hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* p,
                           const void* u, void* grad_kappa, int64_t nsteps, void* stream);
 

@@ -13,6 +13,9 @@ time-stepping for Hermite methods" (arXiv 1808.10481):
   (option2), (update1)) with Cauchy-Kowalevsky exchange of time for space
   derivatives (Sec. 2, eqs. (LFloop), (final1); Sec. 3.1.2, eqs. (pdup),
   (vdup)), and the tensor-product extension (Sec. 5).
+  Reflecting walls through mirrored ghost nodes (Sec. 5, "Imposing
+  reflective boundary conditions"); the discrete adjoint of the periodic step
+  (the transpose of the forward operators).
 * ``diagnostics`` - error norms and the one-dimensional conserved quantity
   (Sec. 3.1.1, eqs. (Qdef), (Rdef), (fullcons1d)).
 
@@ -30,5 +33,12 @@ from .hermite_lf import (  # noqa: F401
     startup,
     p_update_cells,
     u_update_cells,
+    ghost_pad,
+    adjoint_step,
+    kappa_gradient,
+    p_half_adjoint,
+    u_half_adjoint,
+    p_operator_blocks,
+    u_operator_blocks,
 )
 from . import diagnostics  # noqa: F401

@@ -67,6 +67,8 @@ import numpy as np
 __all__ = [
     "Problem", "hermite_matrix_exact", "hermite_matrix", "p_half", "u_half",
     "step", "startup", "p_update_cells", "u_update_cells", "ghost_pad", "mirror_sign",
+    "p_operator_blocks", "u_operator_blocks", "p_half_adjoint", "u_half_adjoint", "adjoint_step",
+    "kappa_gradient",
 ]
 
 _CHUNK = 1 << 14  # nodes per vectorised batch (bounds memory, not arithmetic)
@@ -219,13 +221,22 @@ def _is_zero(a: np.ndarray) -> bool:
 # ---------------------------------------------------------------------------
 # Cell-level updates (batched over cells)
 # ---------------------------------------------------------------------------
-def p_update_cells(prob: Problem, p_vals: np.ndarray, u_corners, dt=None) -> np.ndarray:
+def _kw(k: int, j: int, kappa: float, dkappa: bool) -> float:
+    """kappa^j, or its derivative j kappa^(j-1) with respect to kappa."""
+    if not dkappa:
+        return kappa ** j
+    return j * kappa ** (j - 1) if j > 0 else 0.0
+
+
+def p_update_cells(prob: Problem, p_vals: np.ndarray, u_corners, dt=None, dkappa: bool = False) -> np.ndarray:
     """New pressure data at a batch of primal nodes.
 
     p_vals: (n,) + (m+1,)*d, pressure data at the nodes at time t.
     u_corners: sequence of d arrays, each (2,)*d + (n,) + (m+1,)*d: velocity
     component i at the 2^d dual corners of each node's cell, time t + dt/2.
     Returns p data at t + dt (Sec. 2, eq. (final1); Sec. 3.1.2, eq. (pdup)).
+    With ``dkappa`` every kappa^(k+1) is replaced by its kappa-derivative, so
+    the result is p_vals minus the kappa-derivative of the increment.
     """
     d, m = prob.d, prob.m
     dt = prob.dt if dt is None else dt
@@ -240,14 +251,14 @@ def p_update_cells(prob: Problem, p_vals: np.ndarray, u_corners, dt=None) -> np.
     term = r
     k = 0
     while not _is_zero(term):
-        incr = incr + _w(k, dt) * prob.kappa ** (k + 1) * term
+        incr = incr + _w(k, dt) * _kw(k, k + 1, prob.kappa, dkappa) * term
         term = _laplacian(term, h, d, 1)
         k += 1
     return p_vals - _truncate(incr, m, d, 1)
 
 
 def u_update_cells(prob: Problem, u_vals: np.ndarray, p_corners: np.ndarray,
-                   dt=None, weight_scale: float = 1.0) -> np.ndarray:
+                   dt=None, weight_scale: float = 1.0, dkappa: bool = False) -> np.ndarray:
     """New velocity data at a batch of dual nodes.
 
     u_vals: (d, n) + (m+1,)*d at time t - dt/2 (or t for the start-up).
@@ -265,7 +276,7 @@ def u_update_cells(prob: Problem, u_vals: np.ndarray, p_corners: np.ndarray,
         term = c                                   # Lap^k c
         k = 0
         while not _is_zero(term):
-            incr = incr + weight_scale * _w(k, dt) * prob.kappa ** k * _deriv(term, i, h[i], 1)
+            incr = incr + weight_scale * _w(k, dt) * _kw(k, k, prob.kappa, dkappa) * _deriv(term, i, h[i], 1)
             term = _laplacian(term, h, d, 1)
             k += 1
         out[i] = out[i] - _truncate(incr, m, d, 1)
@@ -326,7 +337,7 @@ def ghost_pad(prob: Problem, U: np.ndarray) -> np.ndarray:
     return out
 
 
-def p_half(prob: Problem, P: np.ndarray, U: np.ndarray, nodes=None, dt=None):
+def p_half(prob: Problem, P: np.ndarray, U: np.ndarray, nodes=None, dt=None, dkappa: bool = False):
     """Pressure half-step.  P, U in natural layout.  Primal node j takes the
     dual corners q = j - 1 + eps (cell centred on x_j with ends x_{j-1/2},
     x_{j+1/2}); with walls, q = -1 and q = K are the ghost nodes.  With
@@ -344,12 +355,12 @@ def p_half(prob: Problem, P: np.ndarray, U: np.ndarray, nodes=None, dt=None):
         nd = nodes[a:a + _CHUNK]
         uc = [_gather(Ug[i], nd, off, d, wrap) for i in range(d)]
         pv = P[tuple(nd[:, k] for k in range(d))]
-        res[a:a + _CHUNK] = p_update_cells(prob, pv, uc, dt=dt)
+        res[a:a + _CHUNK] = p_update_cells(prob, pv, uc, dt=dt, dkappa=dkappa)
     return res.reshape(P.shape) if full else res
 
 
 def u_half(prob: Problem, U: np.ndarray, P: np.ndarray, nodes=None, dt=None,
-           weight_scale: float = 1.0):
+           weight_scale: float = 1.0, dkappa: bool = False):
     """Velocity half-step.  Dual node q takes the primal corners j = q + eps
     (cell centred on x_{q+1/2} with ends x_q, x_{q+1})."""
     d = prob.d
@@ -361,7 +372,7 @@ def u_half(prob: Problem, U: np.ndarray, P: np.ndarray, nodes=None, dt=None,
         nd = nodes[a:a + _CHUNK]
         pc = _gather(P, nd, 0, d, wrap)
         uv = np.stack([U[i][tuple(nd[:, k] for k in range(d))] for i in range(d)])
-        res[:, a:a + _CHUNK] = u_update_cells(prob, uv, pc, dt=dt, weight_scale=weight_scale)
+        res[:, a:a + _CHUNK] = u_update_cells(prob, uv, pc, dt=dt, weight_scale=weight_scale, dkappa=dkappa)
     return res.reshape(U.shape) if full else res
 
 
@@ -381,3 +392,116 @@ def startup(prob: Problem, P0: np.ndarray, U0: np.ndarray) -> np.ndarray:
     half-step with every w_k halved; even terms are those of U^0 alone and are
     dropped (exact when U^0 = 0, the start used here)."""
     return u_half(prob, U0, P0, weight_scale=0.5)
+
+
+# ---------------------------------------------------------------------------
+# Discrete adjoint (periodic grid)
+# ---------------------------------------------------------------------------
+# One step maps (P, U) to P' = P - A U, U' = U - B P'; A and B are the linear
+# operators of the two half-steps (translation invariant on the periodic
+# grid, one dense block per cell corner).  Its transpose maps (Pb', Ub') to
+#     Pb = Pb' - B^T Ub',    Ub = Ub' - A^T Pb
+# (substitute P' into U' and transpose the block matrix), i.e. the transposed
+# half-steps in reverse order.  The blocks are read off the forward cell
+# updates applied to unit data, so the adjoint is the forward oracle's own
+# transpose.
+
+def p_operator_blocks(prob: Problem) -> np.ndarray:
+    """A[e][s][i][a]: the pressure half-step subtracts
+    sum_e sum_{i,a} A[e][s][i][a] U_i[j - 1 + e][a] from P[j][s]."""
+    d, nc = prob.d, prob.nc
+    cshape = (prob.m + 1,) * d
+    A = np.zeros((2,) * d + (nc, d, nc))
+    for e in itertools.product((0, 1), repeat=d):
+        for i in range(d):
+            for a in range(nc):
+                uc = [np.zeros((2,) * d + (1,) + cshape) for _ in range(d)]
+                uc[i][e + (0,) + np.unravel_index(a, cshape)] = 1.0
+                A[e + (slice(None), i, a)] = -p_update_cells(prob, np.zeros((1,) + cshape), uc)[0].ravel()
+    return A
+
+
+def u_operator_blocks(prob: Problem) -> np.ndarray:
+    """B[e][i][s][a]: the velocity half-step subtracts
+    sum_e sum_a B[e][i][s][a] P[q + e][a] from U_i[q][s]."""
+    d, nc = prob.d, prob.nc
+    cshape = (prob.m + 1,) * d
+    B = np.zeros((2,) * d + (d, nc, nc))
+    for e in itertools.product((0, 1), repeat=d):
+        for a in range(nc):
+            pc = np.zeros((2,) * d + (1,) + cshape)
+            pc[e + (0,) + np.unravel_index(a, cshape)] = 1.0
+            r = -u_update_cells(prob, np.zeros((d, 1) + cshape), pc)[:, 0]
+            B[e + (slice(None), slice(None), a)] = r.reshape(d, nc)
+    return B
+
+
+def p_half_adjoint(prob: Problem, Pb: np.ndarray, Ub: np.ndarray, B=None) -> np.ndarray:
+    """Pb - B^T Ub: P[j] receives sum_e B[e]^T Ub[j - e] (the dual nodes
+    q = j - 1 + e' with e' = 1 - e, the pressure half-step's corners)."""
+    d, K, nc = prob.d, tuple(prob.K), prob.nc
+    B = u_operator_blocks(prob) if B is None else B
+    Ubf = Ub.reshape((d,) + K + (nc,))
+    out = Pb.reshape(K + (nc,)).copy()
+    for e in itertools.product((0, 1), repeat=d):
+        src = np.roll(Ubf, shift=tuple(e), axis=tuple(range(1, d + 1)))      # Ub[j - e]
+        out -= np.einsum("isa,i...s->...a", B[e], src)
+    return out.reshape(Pb.shape)
+
+
+def u_half_adjoint(prob: Problem, Ub: np.ndarray, Pb: np.ndarray, A=None) -> np.ndarray:
+    """Ub - A^T Pb: U[q] receives sum_e A[e]^T Pb[q + 1 - e] (the primal
+    nodes j = q + e' with e' = 1 - e, the velocity half-step's corners)."""
+    d, K, nc = prob.d, tuple(prob.K), prob.nc
+    A = p_operator_blocks(prob) if A is None else A
+    Pbf = Pb.reshape(K + (nc,))
+    out = Ub.reshape((d,) + K + (nc,)).copy()
+    for e in itertools.product((0, 1), repeat=d):
+        src = np.roll(Pbf, shift=tuple(e[k] - 1 for k in range(d)), axis=tuple(range(d)))   # Pb[q + 1 - e]
+        out -= np.einsum("sia,...s->i...a", A[e], src)
+    return out.reshape(Ub.shape)
+
+
+def adjoint_step(prob: Problem, Pb: np.ndarray, Ub: np.ndarray, nsteps: int = 1):
+    """Transpose of `step` (periodic grid): nsteps times Pb <- Pb - B^T Ub,
+    then Ub <- Ub - A^T Pb."""
+    if prob.walls:
+        raise NotImplementedError("the adjoint is built for the periodic grid")
+    A, B = p_operator_blocks(prob), u_operator_blocks(prob)
+    Pb = np.array(Pb, dtype=np.float64, copy=True)
+    Ub = np.array(Ub, dtype=np.float64, copy=True)
+    for _ in range(int(nsteps)):
+        Pb = p_half_adjoint(prob, Pb, Ub, B)
+        Ub = u_half_adjoint(prob, Ub, Pb, A)
+    return Pb, Ub
+
+
+def kappa_gradient(prob: Problem, P0: np.ndarray, U0: np.ndarray, Pbn: np.ndarray, Ubn: np.ndarray,
+                   nsteps: int):
+    """d/dkappa of <Pbn, P_n> + <Ubn, U_n> for n steps from (P0, U0), and the
+    adjoint state (Pb_0, Ub_0) (periodic grid).
+
+    With P' = P - A U, U' = U - B P' and the adjoint lambda_{t+1} = (Pb', Ub')
+    of the state after step t, the step's kappa-derivative contributes
+        -<Pb' - B^T Ub', A_kappa U_t> - <Ub', B_kappa P'>
+    (chain rule through both half-steps), where A_kappa, B_kappa are the
+    half-step operators with every kappa power replaced by its derivative.
+    The forward trajectory is stored (no recomputation)."""
+    A, B = p_operator_blocks(prob), u_operator_blocks(prob)
+    states = [(np.array(P0, dtype=np.float64), np.array(U0, dtype=np.float64))]
+    for _ in range(int(nsteps)):
+        P, U = states[-1]
+        P1 = p_half(prob, P, U)
+        states.append((P1, u_half(prob, U, P1)))
+    Pb, Ub = np.array(Pbn, dtype=np.float64), np.array(Ubn, dtype=np.float64)
+    g = 0.0
+    for t in range(int(nsteps) - 1, -1, -1):
+        P_t, U_t = states[t]
+        P_1 = states[t + 1][0]
+        BkP = -u_half(prob, np.zeros_like(U_t), P_1, dkappa=True)                  # B_kappa P'
+        g -= np.sum(Ub * BkP)
+        Pb = p_half_adjoint(prob, Pb, Ub, B)
+        AkU = -p_half(prob, np.zeros_like(P_t), U_t, dkappa=True)                   # A_kappa U_t
+        g -= np.sum(Pb * AkU)
+        Ub = u_half_adjoint(prob, Ub, Pb, A)
+    return g, Pb, Ub

@@ -163,6 +163,18 @@ struct hl_plan_s {
   hl::Grid gp, gu;       // pressure / velocity half-step launch grids
   hl::KernelSet ks;
   void* dtab = nullptr;
+  void* dadj = nullptr;        // adjoint blocks (B^T then A^T), or NULL
+  size_t adj_u_off = 0;        // element offset of the A^T blocks in dadj
+  // kappa gradient, allocated on first use: tables with kappa-derivative
+  // weights and with -dt (one step reversed), copies of the forward state
+  // walked back step by step, scratch fields and reduction partials
+  void* tab_dk = nullptr;
+  void* tab_rev = nullptr;
+  void* fp = nullptr;
+  void* fu = nullptr;
+  void* sp = nullptr;
+  void* su = nullptr;
+  double* gpart = nullptr;
   double* dpartial = nullptr;  // norms scratch, kNormBlocks per plane
   int device = 0;
   // hl_step replays a captured graph of kGraphChunk steps for the last
@@ -219,9 +231,107 @@ hipError_t capture_steps(hl_plan_s* pl, const hl::PlanView& v, void* p, void* u)
 
 int max_m(int d) { return d == 1 ? 7 : (d == 2 ? 5 : 3); }
 
+PolyOps poly_ops(const hl_plan_s* pl) {
+  PolyOps P;
+  P.d = pl->d;
+  P.N2 = 2 * pl->m + 2;
+  P.size = 1;
+  for (int k = 0; k < pl->d; ++k) P.size *= P.N2;
+  for (int k = 0; k < 3; ++k) P.h[k] = pl->h[k];
+  return P;
+}
+
+// Weights of the operator tables: the time step (its sign reverses a step:
+// every w_k is odd in dt) and whether the kappa powers are replaced by their
+// kappa-derivatives (the operators A_kappa, B_kappa of the gradient).
+struct WeightMode {
+  double dt;
+  bool dkappa;
+};
+
+// W = sum_k w_k kappa^{k + kshift} Lap^k as a full (2m+2)^d x (2m+2)^d
+// operator on cell polynomials, rows = output coefficient, w_k =
+// 2 (dt/2)^{2k+1} / (2k+1)! (Sec. 2, eq. (update1); Sec. 3.1.2, eqs. (pdup),
+// (vdup)); the series stops where Lap^k of the basis monomial vanishes.  With
+// wm.dkappa, kappa^j becomes j kappa^{j-1}.
+std::vector<double> weight_operator(const hl_plan_s* pl, const PolyOps& P, int kshift, WeightMode wm) {
+  std::vector<double> W((size_t)P.size * P.size, 0.0);
+  for (int beta = 0; beta < P.size; ++beta) {
+    std::vector<double> term(P.size, 0.0), acc(P.size, 0.0);
+    term[beta] = 1.0;
+    double fact = 1.0;
+    for (int k = 0; !all_zero(term); ++k) {
+      if (k > 0) fact *= (double)(2 * k) * (double)(2 * k + 1);
+      const int j = k + kshift;
+      const double kp = wm.dkappa ? (j > 0 ? j * std::pow(pl->kappa, j - 1) : 0.0) : std::pow(pl->kappa, j);
+      const double ck = 2.0 * std::pow(wm.dt / 2.0, 2 * k + 1) / fact * kp;
+      for (int b = 0; b < P.size; ++b) acc[b] += ck * term[b];
+      term = P.lap(term);
+    }
+    for (int b = 0; b < P.size; ++b) W[(size_t)b * P.size + beta] = acc[b];
+  }
+  return W;
+}
+
+// Dense per-corner blocks of the transposed half-steps (periodic plans),
+// packed as the adjoint kernels read them: T[e'][io][ii][r][c].
+//   A[e][s][i][a]: the pressure half-step subtracts A[e] U_i[j - 1 + e] from P[j]:
+//     A[e][s][i][a] = sum_b Wp[s][b] (D_i I_{e,a})_b,
+//   B[e][i][s][a]: the velocity half-step subtracts B[e] P[q + e] from U_i[q]:
+//     B[e][i][s][a] = (s_i + 1) / h_i sum_b Wq[s + e_i][b] (I_{e,a})_b,
+// with I_{e,a} the interpolant of a unit datum a at corner e (Sec. 2,
+// eq. (interp), tensor product).  Pb -= B^T Ub reads Ub[j - 1 + e'] with
+// block B[1 - e']^T; Ub -= A^T Pb reads Pb[q + e'] with block A[1 - e']^T.
+void build_adjoint_tables(const hl_plan_s* pl, std::vector<double>& tp, std::vector<double>& tu) {
+  const int d = pl->d, m = pl->m, MP = m + 1, N2 = 2 * m + 2, nc = pl->nc, ne = 1 << d;
+  const PolyOps P = poly_ops(pl);
+  const std::vector<double> H = hermite_matrix(m);  // [b][L_0..L_m, R_0..R_m]
+  const WeightMode wm{pl->dt, false};
+  const std::vector<double> Wp = weight_operator(pl, P, 1, wm), Wq = weight_operator(pl, P, 0, wm);
+  auto row = [&](const int* s) {  // coefficient index of s in {0..2m+1}^d
+    int r = 0;
+    for (int k = d - 1; k >= 0; --k) r = r * N2 + s[k];
+    return r;
+  };
+  tp.assign((size_t)ne * d * nc * nc, 0.0);
+  tu.assign((size_t)ne * d * nc * nc, 0.0);
+  std::vector<double> I(P.size);
+  for (int e = 0; e < ne; ++e)
+    for (int a = 0; a < nc; ++a) {
+      int ad[3] = {0, 0, 0};
+      for (int k = 0, r = a; k < d; ++k, r /= MP) ad[k] = r % MP;
+      for (int b = 0; b < P.size; ++b) {
+        double v = 1.0;
+        for (int k = 0; k < d; ++k) v *= H[P.dig(b, k) * N2 + ((e >> k) & 1) * MP + ad[k]];
+        I[b] = v;
+      }
+      const int ep = (ne - 1) ^ e;  // e' = 1 - e
+      for (int i = 0; i < d; ++i) {
+        const std::vector<double> DI = P.deriv(I, i);
+        for (int sidx = 0; sidx < nc; ++sidx) {
+          int sd[3] = {0, 0, 0};
+          for (int k = 0, r = sidx; k < d; ++k, r /= MP) sd[k] = r % MP;
+          const int srow = row(sd);
+          double av = 0.0;
+          for (int b = 0; b < P.size; ++b) av += Wp[(size_t)srow * P.size + b] * DI[b];
+          int se[3] = {sd[0], sd[1], sd[2]};
+          se[i] += 1;
+          const int serow = row(se);
+          double bv = 0.0;
+          for (int b = 0; b < P.size; ++b) bv += Wq[(size_t)serow * P.size + b] * I[b];
+          bv *= (sd[i] + 1) / pl->h[i];
+          // Pb -= B^T Ub: out r = a (1 component), in (ii = i, c = s)
+          tp[((((size_t)ep * 1 + 0) * d + i) * nc + a) * nc + sidx] = bv;
+          // Ub -= A^T Pb: out (io = i, r = a), in (c = s)
+          tu[((((size_t)ep * d + i) * 1 + 0) * nc + a) * nc + sidx] = av;
+        }
+      }
+    }
+}
+
 // Build every table of the plan into host FP64 memory (packed as the kernels
-// read it, hl_layout.hpp).
-hl_status build_tables(hl_plan_s* pl, std::vector<double>& tab) {
+// read it, hl_layout.hpp), with the weights of wm.
+hl_status build_tables(hl_plan_s* pl, std::vector<double>& tab, WeightMode wm) {
   const int d = pl->d, m = pl->m, MP = m + 1, N2 = 2 * m + 2;
   const hl::KernelSet& ks = pl->ks;
   tab.assign(ks.table_words, 0.0);
@@ -242,12 +352,7 @@ hl_status build_tables(hl_plan_s* pl, std::vector<double>& tab) {
     return (b + 1 < N2) ? (b + 1) * H[(b + 1) * N2 + MP + l] / pl->h[kL] : 0.0;
   };
 
-  PolyOps P;
-  P.d = d;
-  P.N2 = N2;
-  P.size = 1;
-  for (int k = 0; k < d; ++k) P.size *= N2;
-  for (int k = 0; k < 3; ++k) P.h[k] = pl->h[k];
+  const PolyOps P = poly_ops(pl);
   int NC = 1, NB = 1;
   for (int k = 0; k < d; ++k) NC *= MP;
   for (int k = 0; k + 1 < d; ++k) NB *= N2;
@@ -315,25 +420,8 @@ hl_status build_tables(hl_plan_s* pl, std::vector<double>& tab) {
       }
     return HL_OK;
   };
-  // W as a full (2m+2)^d x (2m+2)^d operator, rows = output coefficient.
-  auto full_operator = [&](int kshift) {
-    std::vector<double> W((size_t)P.size * P.size, 0.0);
-    for (int beta = 0; beta < P.size; ++beta) {
-      std::vector<double> term(P.size, 0.0), acc(P.size, 0.0);
-      term[beta] = 1.0;
-      double fact = 1.0;
-      for (int k = 0; !all_zero(term); ++k) {
-        if (k > 0) fact *= (double)(2 * k) * (double)(2 * k + 1);
-        const double ck = 2.0 * std::pow(pl->dt / 2.0, 2 * k + 1) / fact * std::pow(pl->kappa, k + kshift);
-        for (int b = 0; b < P.size; ++b) acc[b] += ck * term[b];
-        term = P.lap(term);
-      }
-      for (int b = 0; b < P.size; ++b) W[(size_t)b * P.size + beta] = acc[b];
-    }
-    return W;
-  };
-  const std::vector<double> Wp = full_operator(1);   // sum_k w_k kappa^{k+1} Lap^k
-  const std::vector<double> Wq = full_operator(0);   // sum_k w_k kappa^k Lap^k
+  const std::vector<double> Wp = weight_operator(pl, P, 1, wm);   // sum_k w_k kappa^{k+1} Lap^k
+  const std::vector<double> Wq = weight_operator(pl, P, 0, wm);   // sum_k w_k kappa^k Lap^k
   hl_status st;
   if (d == 3) {
     // 3D: explicit x pass, y and z merged into the table:
@@ -448,6 +536,7 @@ hl::PlanView view(const hl_plan_s* pl) {
   v.gu = pl->gu;
   for (int k = 0; k < 3; ++k) v.uext[k] = pl->uext[k];
   v.tab = pl->dtab;
+  v.adj_tab = pl->dadj;
   v.d = pl->d;
   v.m = pl->m;
   v.precision = pl->precision;
@@ -523,6 +612,93 @@ hl_status sumsq(const hl_plan_s* pl, const void* x, int field, double* out) {
     case HL_FP32: return sumsq_as<hl::PlainStore<float>>(pl, x, field, out);
     default: return sumsq_as<hl::SplitStore>(pl, x, field, out);
   }
+}
+
+// <a, b> over `planes` coefficient planes of `nodes` entries (periodic state
+// buffers: every entry counts), FP64 accumulation; one partial per block.
+template <class S>
+__global__ void dot_kernel(typename S::View a, typename S::View b, int planes, double* __restrict__ partial) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int pl = 0; pl < planes; ++pl)
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < a.nodes; n += (int64_t)gridDim.x * blockDim.x)
+      acc = fma((double)S::load(a, pl, (uint32_t)n), (double)S::load(b, pl, (uint32_t)n), acc);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// *acc += sum of n partials, in a fixed order (one block of 256).
+__global__ void add_partials(const double* __restrict__ partial, int n, double* __restrict__ acc) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += partial[i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *acc += red[0];
+}
+
+// *acc += <a, b> for two p-shaped (field 0) or u-shaped (field 1) buffers.
+hipError_t dot_into(const hl_plan_s* pl, const void* a, const void* b, int field, double* acc, hipStream_t s) {
+  const int planes = (field == 0 ? 1 : pl->d) * pl->nc;
+  const int64_t nodes = field == 0 ? pl->pnodes : pl->unodes;
+  const int ncomp = field == 0 ? 1 : pl->d;
+  if (pl->precision == HL_FP64) {
+    using S = hl::PlainStore<double>;
+    hipLaunchKernelGGL(dot_kernel<S>, dim3(kNormBlocks), dim3(256), 0, s, S::make(a, ncomp, pl->nc, nodes),
+                       S::make(b, ncomp, pl->nc, nodes), planes, pl->gpart);
+  } else {
+    using S = hl::PlainStore<float>;
+    hipLaunchKernelGGL(dot_kernel<S>, dim3(kNormBlocks), dim3(256), 0, s, S::make(a, ncomp, pl->nc, nodes),
+                       S::make(b, ncomp, pl->nc, nodes), planes, pl->gpart);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(add_partials, dim3(1), dim3(256), 0, s, (const double*)pl->gpart, kNormBlocks, acc);
+  return hipGetLastError();
+}
+
+hipError_t upload_table(const hl_plan_s* pl, const std::vector<double>& tab, void** out) {
+  const size_t bytes = std::max<size_t>(tab.size() * pl->tab_bytes, 16);
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) return e;
+  if (pl->tab_bytes == 8) return hipMemcpy(*out, tab.data(), tab.size() * 8, hipMemcpyHostToDevice);
+  std::vector<float> f(tab.begin(), tab.end());
+  return hipMemcpy(*out, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+}
+
+// Gradient resources of a periodic plan (first use only).
+hl_status ensure_gradient(hl_plan_s* pl) {
+  if (pl->tab_dk) return HL_OK;
+  std::vector<double> tdk, trev;
+  hl_status st = build_tables(pl, tdk, WeightMode{pl->dt, true});
+  if (st == HL_OK) st = build_tables(pl, trev, WeightMode{-pl->dt, false});
+  if (st != HL_OK) return st;
+  const size_t pbytes = (size_t)pl->nc * pl->pnodes * pl->tab_bytes;
+  const size_t ubytes = (size_t)pl->d * pl->nc * pl->unodes * pl->tab_bytes;
+  hipError_t e = upload_table(pl, tdk, &pl->tab_dk);
+  if (e == hipSuccess) e = upload_table(pl, trev, &pl->tab_rev);
+  if (e == hipSuccess) e = hipMalloc(&pl->fp, pbytes);
+  if (e == hipSuccess) e = hipMalloc(&pl->fu, ubytes);
+  if (e == hipSuccess) e = hipMalloc(&pl->sp, pbytes);
+  if (e == hipSuccess) e = hipMalloc(&pl->su, ubytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&pl->gpart, kNormBlocks * sizeof(double));
+  if (e != hipSuccess) {
+    for (void** q : {&pl->tab_dk, &pl->tab_rev, &pl->fp, &pl->fu, &pl->sp, &pl->su, (void**)&pl->gpart}) {
+      if (*q) (void)hipFree(*q);
+      *q = nullptr;
+    }
+    return fail(HL_ERR_NOMEM, std::string("hl_adjoint_step: gradient buffers: ") + hipGetErrorString(e));
+  }
+  return HL_OK;
 }
 
 // Launch grid of one half-step: updates K[] nodes stored at index j + ooff
@@ -648,7 +824,7 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
     }
   }
   std::vector<double> tab;
-  hl_status st = build_tables(pl, tab);
+  hl_status st = build_tables(pl, tab, WeightMode{pl->dt, false});
   if (st != HL_OK) {
     delete pl;
     return st;
@@ -678,6 +854,30 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
     delete pl;
     return hip_fail(e, "hl_plan: table upload");
   }
+  if (pl->ks.adj_p && !pl->walls) {
+    std::vector<double> tp, tu;
+    build_adjoint_tables(pl, tp, tu);
+    pl->adj_u_off = tp.size();
+    const size_t n = tp.size() + tu.size();
+    e = hipMalloc(&pl->dadj, n * pl->tab_bytes);
+    if (e == hipSuccess) {
+      std::vector<double> all(tp);
+      all.insert(all.end(), tu.begin(), tu.end());
+      if (pl->tab_bytes == 8) {
+        e = hipMemcpy(pl->dadj, all.data(), n * 8, hipMemcpyHostToDevice);
+      } else {
+        std::vector<float> f(all.begin(), all.end());
+        e = hipMemcpy(pl->dadj, f.data(), n * 4, hipMemcpyHostToDevice);
+      }
+    }
+    if (e != hipSuccess) {
+      if (pl->dadj) (void)hipFree(pl->dadj);
+      (void)hipFree(pl->dtab);
+      (void)hipFree(pl->dpartial);
+      delete pl;
+      return hip_fail(e, "hl_plan: adjoint table upload");
+    }
+  }
   *out = pl;
   return HL_OK;
 }
@@ -688,6 +888,9 @@ hl_status hl_plan_destroy(hl_plan_t plan) {
   drop_graph(plan);
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   if (plan->dtab) (void)hipFree(plan->dtab);
+  if (plan->dadj) (void)hipFree(plan->dadj);
+  for (void* q : {plan->tab_dk, plan->tab_rev, plan->fp, plan->fu, plan->sp, plan->su, (void*)plan->gpart})
+    if (q) (void)hipFree(q);
   if (plan->dpartial) (void)hipFree(plan->dpartial);
   delete plan;
   return HL_OK;
@@ -801,8 +1004,57 @@ hl_status hl_norms(hl_plan_t plan, const void* p, const void* u, double* out) {
 
 hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* p, const void* u,
                           void* grad_kappa, int64_t nsteps, void* stream) {
-  (void)plan, (void)p_bar, (void)u_bar, (void)p, (void)u, (void)grad_kappa, (void)nsteps, (void)stream;
-  return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: the adjoint is not built");
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_adjoint_step");
+  if (st != HL_OK) return st;
+  if (plan->walls) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: built for periodic plans only");
+  if (grad_kappa && (!p || !u)) return fail(HL_ERR_ARG, "hl_adjoint_step: the gradient needs the forward state p, u");
+  if (!plan->dadj) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: not built for this (d, m, precision)");
+  if (!p_bar || !u_bar || p_bar == u_bar)
+    return fail(HL_ERR_ARG, "hl_adjoint_step: p_bar and u_bar must be distinct non-NULL buffers");
+  if (nsteps < 0) return fail(HL_ERR_ARG, "hl_adjoint_step: nsteps must be >= 0");
+  hl::PlanView v = view(plan);
+  hipStream_t s = (hipStream_t)stream;
+  const char* tab = static_cast<const char*>(plan->dadj);
+  hl::PlanView vb = v, va = v;
+  vb.adj_tab = tab;                                            // B^T blocks
+  va.adj_tab = tab + plan->adj_u_off * (size_t)plan->tab_bytes;  // A^T blocks
+  if (!grad_kappa) {
+    for (int64_t n = 0; n < nsteps; ++n) {
+      hipError_t e = plan->ks.adj_p(vb, p_bar, u_bar, s);      // Pb -= B^T Ub
+      if (e == hipSuccess) e = plan->ks.adj_u(va, u_bar, p_bar, s);  // Ub -= A^T Pb
+      if (e != hipSuccess) return hip_fail(e, "hl_adjoint_step: launch");
+    }
+    return HL_OK;
+  }
+  // Gradient: walk the forward state back one step at a time (the step is
+  // reversed exactly, in exact arithmetic, by the half-steps with -dt in
+  // reverse order) and add each step's contribution
+  //   -<Pb' - B^T Ub', A_kappa U_t> - <Ub', B_kappa P'>
+  // (the chain rule through P' = P - A U, U' = U - B P').
+  if ((st = ensure_gradient(plan)) != HL_OK) return st;
+  hl::PlanView vdk = v, vrev = v;
+  vdk.tab = plan->tab_dk;
+  vrev.tab = plan->tab_rev;
+  const size_t pbytes = (size_t)plan->nc * plan->pnodes * plan->tab_bytes;
+  const size_t ubytes = (size_t)plan->d * plan->nc * plan->unodes * plan->tab_bytes;
+  double* g = static_cast<double*>(grad_kappa);
+  hipError_t e = hipMemcpyAsync(plan->fp, p, pbytes, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(plan->fu, u, ubytes, hipMemcpyDeviceToDevice, s);
+  for (int64_t n = 0; n < nsteps && e == hipSuccess; ++n) {
+    // (fp, fu) = (P', U') after the step being undone; (p_bar, u_bar) its adjoint
+    e = hipMemsetAsync(plan->su, 0, ubytes, s);
+    if (e == hipSuccess) e = plan->ks.u_half(vdk, plan->su, plan->fp, 1.0, s);       // su = -B_kappa P'
+    if (e == hipSuccess) e = dot_into(plan, u_bar, plan->su, 1, g, s);
+    if (e == hipSuccess) e = plan->ks.u_half(v, plan->fu, plan->fp, -1.0, s);       // fu = U_t
+    if (e == hipSuccess) e = plan->ks.adj_p(vb, p_bar, u_bar, s);                    // Pb -= B^T Ub
+    if (e == hipSuccess) e = hipMemsetAsync(plan->sp, 0, pbytes, s);
+    if (e == hipSuccess) e = plan->ks.p_half(vdk, plan->sp, plan->fu, s);             // sp = -A_kappa U_t
+    if (e == hipSuccess) e = dot_into(plan, p_bar, plan->sp, 0, g, s);
+    if (e == hipSuccess) e = plan->ks.p_half(vrev, plan->fp, plan->fu, s);            // fp = P_t
+    if (e == hipSuccess) e = plan->ks.adj_u(va, u_bar, p_bar, s);                    // Ub -= A^T Pb
+  }
+  return e == hipSuccess ? HL_OK : hip_fail(e, "hl_adjoint_step: gradient launch");
 }
 
 }  // extern "C"

@@ -13,6 +13,7 @@ namespace hl {
 // What a launcher needs from a plan.
 struct PlanView {
   Grid gp, gu;          // pressure / velocity half-step grids
+  const void* adj_tab;  // transposed half-step blocks (periodic plans with an adjoint), or NULL
   int32_t uext[3];      // velocity array extents (ghost fill, walls only)
   const void* tab;      // packed operator tables in the plan's arithmetic type
   int d, m, precision;
@@ -22,11 +23,14 @@ struct PlanView {
 typedef hipError_t (*PHalfFn)(const PlanView&, void* p, const void* u, hipStream_t);
 typedef hipError_t (*UHalfFn)(const PlanView&, void* u, const void* p, double wscale, hipStream_t);
 typedef hipError_t (*GhostFn)(const PlanView&, void* u, hipStream_t);
+// Transposed half-steps: pb -= B^T ub (AdjFn p), ub -= A^T pb (AdjFn u).
+typedef hipError_t (*AdjFn)(const PlanView&, void* out, const void* in, hipStream_t);
 
 struct KernelSet {
   PHalfFn p_half;
   UHalfFn u_half;
   GhostFn ghost;         // ghost-shell refresh of a wall-bounded velocity array
+  AdjFn adj_p, adj_u;    // transposed half-steps, NULL where not built
   int table_words;       // TableLayout<D, M>::TOTAL
   int p_off[3];          // offsets of the pressure merged tables, per component
   int u_off;             // offset of the velocity (Q) merged table
@@ -124,12 +128,36 @@ hipError_t launch_ghost(const PlanView& pv, void* u, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int D, int M, class S, bool PTYPE>
+hipError_t launch_adjoint(const PlanView& pv, void* out, const void* in, hipStream_t s) {
+  using T = typename S::C;
+  constexpr int NC = Dims<D, M>::NC;
+  const Grid& g = PTYPE ? pv.gp : pv.gu;
+  const typename S::View vo = S::make(out, PTYPE ? 1 : D, NC, g.onodes);
+  const typename S::View vi = S::make(in, PTYPE ? D : 1, NC, g.snodes);
+  hipLaunchKernelGGL((adjoint_half<D, M, S, PTYPE>), grid_shape(g), block_shape<D>(), 0, s, vo, vi,
+                     (const T*)pv.adj_tab, g);
+  return hipGetLastError();
+}
+
+template <class S>
+constexpr bool kPlain = false;
+template <typename W>
+constexpr bool kPlain<PlainStore<W>> = true;
+
 template <int D, class S, int M>
 inline bool make_set(KernelSet* out) {
   fill_layout<D, M>(out);
   out->p_half = &launch_p<D, M, S>;
   out->u_half = &launch_u<D, M, S>;
   out->ghost = &launch_ghost<D, M, S>;
+  out->adj_p = nullptr;
+  out->adj_u = nullptr;
+  // adjoint: FP64 and FP32 storage, nc <= 27 (1D all m, 2D m <= 4, 3D m <= 2)
+  if constexpr (kPlain<S> && Dims<D, M>::NC <= kAdjointMaxNC) {
+    out->adj_p = &launch_adjoint<D, M, S, true>;
+    out->adj_u = &launch_adjoint<D, M, S, false>;
+  }
   return true;
 }
 

@@ -500,4 +500,58 @@ __global__ void __launch_bounds__(256) ghost_fill(typename S::View u, int32_t E0
     }
 }
 
+// ---------------------------------------------------------------------------
+// Discrete adjoint (periodic grids).  A step maps (P, U) to P' = P - A U,
+// U' = U - B P'; its transpose is Pb <- Pb - B^T Ub, then Ub <- Ub - A^T Pb:
+// the transposed half-steps in reverse order.  On the periodic grid each
+// transposed half-step is again a gather with the forward stencil: B^T Ub at
+// primal node j reads the dual nodes q = j - 1 + e' (the pressure half-step's
+// corners) and A^T Pb at dual node q reads the primal nodes j = q + e' (the
+// velocity half-step's), so no atomics are needed.  The operators are dense
+// per corner: T[e'][io][ii][r][c] (nc x nc blocks for output component io and
+// input component ii), built on the host from the same interpolation and
+// weight operators as the forward tables.
+//   PTYPE = true:  out = Pb (1 component), in = Ub (D components)
+//   PTYPE = false: out = Ub (D components), in = Pb (1 component)
+// ---------------------------------------------------------------------------
+constexpr int kAdjointMaxNC = 27;  // register budget: nc inputs + nc accumulators
+
+template <int D, int M, class S, bool PTYPE>
+__global__ void __launch_bounds__(256) adjoint_half(typename S::View out, typename S::View in,
+                                                    const typename S::C* __restrict__ tab, Grid g) {
+  using T = typename S::C;
+  constexpr int NC = Dims<D, M>::NC, NO = PTYPE ? 1 : D, NI = PTYPE ? D : 1;
+  static_assert(NC <= kAdjointMaxNC, "adjoint kernels are built for nc <= 27");
+  int32_t j[3];
+  if (!node_of_thread<D>(g, j)) return;
+  uint32_t cn[1 << D];
+  corner_nodes<D>(g, j, cn);
+  const uint32_t n0 = out_index<D>(g, j);
+#pragma unroll 1
+  for (int io = 0; io < NO; ++io) {
+    T acc[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) acc[r] = T(0);
+#pragma unroll
+    for (int e = 0; e < (1 << D); ++e) {
+#pragma unroll 1
+      for (int ii = 0; ii < NI; ++ii) {
+        T src[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) src[c] = S::load(in, ii * NC + c, cn[e]);
+        const T* __restrict__ Tb = tab + ((int64_t)((e * NO + io) * NI + ii) * NC) * NC;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+          // keep the scalar table loads of one row together (SGPR pressure)
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[r] = fma(Tb[r * NC + c], src[c], acc[r]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NC; ++r) S::update(out, io * NC + r, n0, [&](T x) { return x - acc[r]; });
+  }
+}
+
 }  // namespace hl

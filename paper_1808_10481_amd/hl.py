@@ -121,6 +121,7 @@ class Plan:
     def __init__(self, d, m, cells, length=None, dt=0.0, cfl=0.5, c=1.0, precision="fp64",
                  boundary="periodic"):
         self.problem = make_problem(d, m, cells, length, dt, cfl, c, precision, boundary)
+        self.kappa = float(c) ** 2
         self.d, self.m, self.precision, self.boundary = int(d), int(m), precision, boundary
         self.cells = tuple(int(k) for k in cells)
         h = ctypes.c_void_p()
@@ -211,6 +212,22 @@ class Plan:
         self._check_buf(p, u)
         _check(lib().hl_u_half(self._h, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(p.data_ptr()),
                                float(weight_scale), _stream_ptr(stream)))
+
+    def adjoint_step(self, p_bar, u_bar, nsteps=1, p=None, u=None, grad_kappa=None, stream=None):
+        """nsteps transposed steps on the adjoint state, in place (hl_adjoint_step).
+        With grad_kappa (a one-element FP64 device tensor) the kappa-derivative
+        of <p_bar, P_n> + <u_bar, U_n> is added to it; p, u are then the forward
+        state (P_n, U_n) after the n steps (not modified)."""
+        self._check_buf(p_bar, u_bar)
+        pp = uu = gg = None
+        if grad_kappa is not None:
+            self._check_buf(p, u)
+            if grad_kappa.dtype.itemsize != 8 or not grad_kappa.is_cuda or grad_kappa.numel() < 1:
+                raise ValueError("grad_kappa must be a float64 device tensor")
+            pp, uu = ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(u.data_ptr())
+            gg = ctypes.c_void_p(grad_kappa.data_ptr())
+        _check(lib().hl_adjoint_step(self._h, ctypes.c_void_p(p_bar.data_ptr()), ctypes.c_void_p(u_bar.data_ptr()),
+                                     pp, uu, gg, int(nsteps), _stream_ptr(stream)))
 
     def norms(self, p, u):
         out = (ctypes.c_double * 2)()

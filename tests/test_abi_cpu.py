@@ -89,9 +89,9 @@ def test_plan_rejects_null_and_reserved():
     assert hl.lib().hl_plan(ctypes.byref(pr), ctypes.byref(h)) == hl.HL_ERR_ARG
 
 
-def test_adjoint_is_reported_unsupported():
+def test_adjoint_rejects_null_plan():
     st = hl.lib().hl_adjoint_step(None, None, None, None, None, None, 1, None)
-    assert st == hl.HL_ERR_UNSUPPORTED
+    assert st == hl.HL_ERR_ARG
 
 
 def test_null_plan_arguments():
