@@ -36,6 +36,10 @@ from .hermite_lf import (  # noqa: F401
     ghost_pad,
     adjoint_step,
     kappa_gradient,
+    kmax_var,
+    p_half_var,
+    u_half_var,
+    step_var,
     p_half_adjoint,
     u_half_adjoint,
     p_operator_blocks,

@@ -68,7 +68,8 @@ __all__ = [
     "Problem", "hermite_matrix_exact", "hermite_matrix", "p_half", "u_half",
     "step", "startup", "p_update_cells", "u_update_cells", "ghost_pad", "mirror_sign",
     "p_operator_blocks", "u_operator_blocks", "p_half_adjoint", "u_half_adjoint", "adjoint_step",
-    "kappa_gradient",
+    "kappa_gradient", "kmax_var", "p_update_cells_var", "u_update_cells_var", "p_half_var", "u_half_var",
+    "step_var",
 ]
 
 _CHUNK = 1 << 14  # nodes per vectorised batch (bounds memory, not arithmetic)
@@ -505,3 +506,113 @@ def kappa_gradient(prob: Problem, P0: np.ndarray, U0: np.ndarray, Pbn: np.ndarra
         g -= np.sum(Pb * AkU)
         Ub = u_half_adjoint(prob, Ub, Pb, A)
     return g, Pb, Ub
+
+
+# ---------------------------------------------------------------------------
+# Variable coefficient kappa(x) (periodic grid)
+# ---------------------------------------------------------------------------
+# The paper expands the coefficient about every grid node in a local Taylor
+# polynomial of degree 2m+1 (Sec. 4, "Smoothly varying wave speed"):
+#     kappa~_b = prod_k h_k^{b_k} / b_k!  d^b kappa (node),  b in {0..2m+1}^d,
+# and runs the Cauchy-Kowalevsky recurrence with it.  From p_t = -kappa div u,
+# u_t = -grad p:  d_t^{2k+1} p = -(kappa Lap)^k (kappa div u) and
+# d_t^{2k+1} u = -grad (kappa Lap)^k p.  Reading taken (the printed formula
+# is garbled): every product is a product of cell polynomials truncated to
+# degree 2m+1 per variable, T[.]; kappa is expanded about the cell centre,
+# i.e. about the primal node for the pressure half-step and the dual node for
+# the velocity half-step; the series runs over k = 0..kmax with
+# kmax = floor(d (2m+1) / 2), the last k at which Lap^k of a degree-(2m+1)
+# cell polynomial can be nonzero (so constant kappa data reproduce the
+# constant-coefficient step exactly):
+#     P <- P - sum_k w_k r_k,  r_0 = T[kappa div c],  r_k = T[kappa Lap r_{k-1}],
+#     U_i <- U_i - sum_k w_k D_i g_k,  g_0 = c,  g_k = T[kappa Lap g_{k-1}].
+
+def kmax_var(d: int, m: int) -> int:
+    return (d * (2 * m + 1)) // 2
+
+
+def _tmul(a: np.ndarray, b: np.ndarray, d: int, ns: int) -> np.ndarray:
+    """T[a b]: product of batched cell polynomials (ns batch axes, then d
+    coefficient axes of length 2m+2), truncated to the same degrees."""
+    n = a.shape[ns]
+    out = np.zeros(np.broadcast_shapes(a.shape, b.shape))
+    for s in itertools.product(range(n), repeat=d):
+        bs = a[(slice(None),) * ns + s]
+        dst = (slice(None),) * ns + tuple(slice(sk, n) for sk in s)
+        src = (slice(None),) * ns + tuple(slice(0, n - sk) for sk in s)
+        out[dst] += bs.reshape(bs.shape + (1,) * d) * b[src]
+    return out
+
+
+def p_update_cells_var(prob: Problem, p_vals, u_corners, kap, dt=None):
+    """Pressure update with kappa Taylor data kap, (n,) + (2m+2,)*d, about
+    each node (see the block comment above)."""
+    d, m = prob.d, prob.m
+    dt = prob.dt if dt is None else dt
+    h = prob.h
+    H = hermite_matrix(m)
+    div = None
+    for i in range(d):
+        di = _deriv(_interpolate(np.asarray(u_corners[i], dtype=np.float64), H, d, 1), i, h[i], 1)
+        div = di if div is None else div + di
+    r = _tmul(kap, div, d, 1)
+    incr = _w(0, dt) * r
+    for k in range(1, kmax_var(d, m) + 1):
+        r = _tmul(kap, _laplacian(r, h, d, 1), d, 1)
+        incr = incr + _w(k, dt) * r
+    return p_vals - _truncate(incr, m, d, 1)
+
+
+def u_update_cells_var(prob: Problem, u_vals, p_corners, kap, dt=None, weight_scale: float = 1.0):
+    """Velocity update with kappa Taylor data kap about each dual node."""
+    d, m = prob.d, prob.m
+    dt = prob.dt if dt is None else dt
+    h = prob.h
+    g = _interpolate(np.asarray(p_corners, dtype=np.float64), hermite_matrix(m), d, 1)
+    q = _w(0, dt) * g
+    for k in range(1, kmax_var(d, m) + 1):
+        g = _tmul(kap, _laplacian(g, h, d, 1), d, 1)
+        q = q + _w(k, dt) * g
+    out = np.array(u_vals, dtype=np.float64, copy=True)
+    for i in range(d):
+        out[i] = out[i] - weight_scale * _truncate(_deriv(q, i, h[i], 1), m, d, 1)
+    return out
+
+
+def p_half_var(prob: Problem, P, U, Kp, nodes=None, dt=None):
+    """Pressure half-step with kappa data Kp, (K,)*d + (2m+2,)*d on the primal
+    nodes (periodic)."""
+    d, K = prob.d, tuple(prob.K)
+    full = nodes is None
+    nodes = _all_nodes(K) if full else np.asarray(nodes, dtype=np.int64).reshape(-1, d)
+    res = np.empty((nodes.shape[0],) + P.shape[d:], dtype=np.float64)
+    for a in range(0, nodes.shape[0], _CHUNK):
+        nd = nodes[a:a + _CHUNK]
+        idx = tuple(nd[:, k] for k in range(d))
+        uc = [_gather(U[i], nd, -1, d, K) for i in range(d)]
+        res[a:a + _CHUNK] = p_update_cells_var(prob, P[idx], uc, Kp[idx], dt=dt)
+    return res.reshape(P.shape) if full else res
+
+
+def u_half_var(prob: Problem, U, P, Ku, nodes=None, dt=None, weight_scale: float = 1.0):
+    """Velocity half-step with kappa data Ku on the dual nodes (periodic)."""
+    d, K = prob.d, tuple(prob.K)
+    full = nodes is None
+    nodes = _all_nodes(K) if full else np.asarray(nodes, dtype=np.int64).reshape(-1, d)
+    res = np.empty((d, nodes.shape[0]) + P.shape[d:], dtype=np.float64)
+    for a in range(0, nodes.shape[0], _CHUNK):
+        nd = nodes[a:a + _CHUNK]
+        idx = tuple(nd[:, k] for k in range(d))
+        pc = _gather(P, nd, 0, d, K)
+        uv = np.stack([U[i][idx] for i in range(d)])
+        res[:, a:a + _CHUNK] = u_update_cells_var(prob, uv, pc, Ku[idx], dt=dt, weight_scale=weight_scale)
+    return res.reshape(U.shape) if full else res
+
+
+def step_var(prob: Problem, P, U, Kp, Ku, nsteps: int = 1):
+    P = np.array(P, dtype=np.float64, copy=True)
+    U = np.array(U, dtype=np.float64, copy=True)
+    for _ in range(int(nsteps)):
+        P = p_half_var(prob, P, U, Kp)
+        U = u_half_var(prob, U, P, Ku)
+    return P, U

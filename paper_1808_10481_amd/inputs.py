@@ -119,6 +119,30 @@ def gaussian_pulse(d, m, K, length, center, width):
     return outer(fac)
 
 
+def kappa_sines(d, m, K, length, amps, waves, grid="primal"):
+    """Taylor data of kappa(x) = 1 + sum_k amps_k sin(2 pi waves_k x_k / length_k)
+    (periodic, smooth, positive for sum |amps| < 1) to degree 2m+1 per
+    variable, about the primal (x = j h) or dual (x = (q + 1/2) h) nodes:
+    (K,)*d + (2m+2,)*d, kappa~_b = prod_k h_k^{b_k}/b_k! d^b kappa (node)."""
+    K = tuple(int(k) for k in K)
+    n = 2 * m + 2
+    h = [float(length[k]) / K[k] for k in range(d)]
+    off = 0.0 if grid == "primal" else 0.5
+    out = np.zeros(K + (n,) * d)
+    out[(Ellipsis,) + (0,) * d] = 1.0
+    for k in range(d):
+        x = (np.arange(K[k]) + off) * h[k]
+        a = 2 * pi * waves[k] / float(length[k])
+        f = amps[k] * scaled_sin(x, a, 0.0, h[k], 2 * m + 1)          # (K_k, n)
+        shape = [1] * (2 * d)
+        shape[k] = K[k]
+        shape[d + k] = n
+        sl = [slice(None)] * d + [0] * d
+        sl[d + k] = slice(None)
+        out[tuple(sl)] += f.reshape([K[k] if j == k else 1 for j in range(d)] + [n])
+    return out
+
+
 def random_data(rng, d, m, K, ncomp=None):
     """Uniform[-1,1] scaled data (any data is valid input to the linear scheme)."""
     shape = tuple(int(k) for k in K) + (m + 1,) * d

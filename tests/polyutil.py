@@ -185,3 +185,43 @@ def leapfrog_difference_exact(p_mid, u_mid, h, kappa, dt):
         for i in range(d):
             du[i] = rpoly_add(du[i], U[j][i], f)
     return dp, du
+
+
+def mul_affine(c, k0, kgrad):
+    """(k0 + sum_k kgrad_k x_k) * q for a dense monomial tensor q, grown by
+    one in every axis that kgrad touches (padded shape: +1 per axis)."""
+    d = c.ndim
+    out = np.zeros(tuple(n + 1 for n in c.shape))
+    out[tuple(slice(0, n) for n in c.shape)] += k0 * c
+    for k in range(d):
+        if kgrad[k] != 0.0:
+            sl = [slice(0, n) for n in c.shape]
+            sl[k] = slice(1, c.shape[k] + 1)
+            out[tuple(sl)] += kgrad[k] * c
+    return out
+
+
+def time_series_affine(p0, u0, k0, kgrad, nmax=64):
+    """Time derivatives at t = 0 of the exact solution of
+    p_t = -kappa div u, u_t = -grad p with kappa = k0 + kgrad . x, from the
+    PDE's own recurrence on monomials; terminates when the data have total
+    degree low enough (every kappa-multiplication is followed by derivatives
+    that lower the total degree)."""
+    d = p0.ndim
+    size = p0.shape[0] + nmax
+
+    def pad(c):
+        out = np.zeros((size,) * d)
+        out[tuple(slice(0, n) for n in c.shape)] = c
+        return out
+
+    P, U = [pad(p0)], [[pad(u) for u in u0]]
+    for _ in range(nmax):
+        div = sum(pder(U[-1][i], i) for i in range(d))
+        Pn = -mul_affine(div, k0, kgrad)[tuple(slice(0, size) for _ in range(d))]
+        Un = [-pder(P[-1], i) for i in range(d)]
+        if not np.any(Pn) and not any(np.any(x) for x in Un):
+            return P, U
+        P.append(Pn)
+        U.append(Un)
+    raise RuntimeError("series did not terminate")
