@@ -196,6 +196,47 @@ def run_walls(hl, torch, steps, K=1024, m=3):
     return res
 
 
+def run_varkappa(hl, torch, steps, K=1024, m=3):
+    """Variable coefficient (per-node Taylor data of kappa), 2D m=3 FP32 on
+    the largest grid of the batched-shot configuration (1024^2), smooth
+    kappa = 1 + 0.35 sin(4 pi x) + 0.25 sin(6 pi y), standing-mode data:
+    `steps` steps timed after 3 untimed ones; FP64 beside it."""
+    from paper_1808_10481_amd import inputs
+    res = {}
+    L = (1.0, 1.0)
+    kp = inputs.kappa_sines(2, m, (K, K), L, (0.35, 0.25), (2, 3), "primal")
+    ku = inputs.kappa_sines(2, m, (K, K), L, (0.35, 0.25), (2, 3), "dual")
+    for prec in ("fp32", "fp64"):
+        log(f"[bench] variable kappa 2d m={m} {K}^2 {prec}: {steps} steps")
+        plan = hl.Plan(2, m, (K, K), cfl=0.5, c=float(np.sqrt(1.6)), precision=prec)
+        plan.set_kappa(kp, ku)
+        P0, U0 = inputs.standing_mode(2, m, (K, K), L, (3, 2), 0.0, plan.dt / 2)
+        p, u = plan.alloc()
+        plan.init(p, u, P0, U0)
+        plan.step(p, u, 3)
+        stream = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for n in range(steps):
+            plan.p_half(p, u)
+            ev[2 * n + 1].record(stream)
+            plan.u_half(u, p)
+            ev[2 * n + 2].record(stream)
+        torch.cuda.synchronize()
+        total = ev[0].elapsed_time(ev[-1])
+        tp = float(np.mean([ev[2 * n].elapsed_time(ev[2 * n + 1]) for n in range(steps)]))
+        tu = float(np.mean([ev[2 * n + 1].elapsed_time(ev[2 * n + 2]) for n in range(steps)]))
+        res[prec] = {"value": K * K * steps / (total * 1e-3), "unit": "cell-updates/s", "ms_per_step": total / steps,
+                     "p_half_ms": tp, "u_half_ms": tu, "steps": steps}
+        plan.close()
+        del p, u
+        torch.cuda.empty_cache()
+    res["config"] = {"workload": f"variable_kappa_2d m={m} {K}^2 kappa=1+0.35sin(4pi x)+0.25sin(6pi y) (one shot; "
+                                 "batched persistent launch not built)", "d": 2, "m": m, "cells": [K, K]}
+    return res
+
+
 def run_adjoint(hl, torch, steps, K=512, m=2):
     """Discrete adjoint on the shape of the gradient workload (2D, m=2, 512^2,
     periodic, constant kappa): `steps` transposed steps alone, then `steps`
@@ -292,6 +333,8 @@ def main():
     ap.add_argument("--steps-3d", type=int, default=50)
     ap.add_argument("--no-walls", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-varkappa", action="store_true")
+    ap.add_argument("--steps-varkappa", type=int, default=50)
     ap.add_argument("--steps-adjoint", type=int, default=100)
     ap.add_argument("--steps-walls", type=int, default=200)
     args = ap.parse_args()
@@ -367,6 +410,9 @@ def main():
 
     if not args.no_walls:
         out["gaussian_pulse_walls_2d"] = run_walls(hl, torch, args.steps_walls)
+
+    if not args.no_varkappa:
+        out["variable_kappa_2d"] = run_varkappa(hl, torch, args.steps_varkappa)
 
     if not args.no_adjoint:
         out["adjoint_2d"] = run_adjoint(hl, torch, args.steps_adjoint)

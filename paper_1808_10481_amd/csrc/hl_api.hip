@@ -168,6 +168,10 @@ struct hl_plan_s {
   // kappa gradient, allocated on first use: tables with kappa-derivative
   // weights and with -dt (one step reversed), copies of the forward state
   // walked back step by step, scratch fields and reduction partials
+  // variable kappa (hl_set_kappa): Taylor data on the primal / dual nodes
+  bool var_kappa = false;
+  void* dkap_p = nullptr;
+  void* dkap_u = nullptr;
   void* tab_dk = nullptr;
   void* tab_rev = nullptr;
   void* fp = nullptr;
@@ -201,6 +205,10 @@ void drop_graph(hl_plan_s* pl) {
   pl->graph_p = pl->graph_u = nullptr;
 }
 
+// Half-step launchers of the plan: constant or variable kappa.
+hl::PHalfFn p_fn(const hl_plan_s* pl) { return pl->var_kappa ? pl->ks.p_half_var : pl->ks.p_half; }
+hl::UHalfFn u_fn(const hl_plan_s* pl) { return pl->var_kappa ? pl->ks.u_half_var : pl->ks.u_half; }
+
 // Capture kGraphChunk steps for buffers (p, u) into pl->gexec.
 hipError_t capture_steps(hl_plan_s* pl, const hl::PlanView& v, void* p, void* u) {
   hipError_t e = hipSuccess;
@@ -212,8 +220,8 @@ hipError_t capture_steps(hl_plan_s* pl, const hl::PlanView& v, void* p, void* u)
   hipError_t le = hipSuccess;
   for (int64_t n = 0; n < kGraphChunk && le == hipSuccess; ++n) {
     if (pl->walls) le = pl->ks.ghost(v, u, pl->cap_stream);
-    if (le == hipSuccess) le = pl->ks.p_half(v, p, u, pl->cap_stream);
-    if (le == hipSuccess) le = pl->ks.u_half(v, u, p, 1.0, pl->cap_stream);
+    if (le == hipSuccess) le = p_fn(pl)(v, p, u, pl->cap_stream);
+    if (le == hipSuccess) le = u_fn(pl)(v, u, p, 1.0, pl->cap_stream);
   }
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(pl->cap_stream, &graph);
@@ -537,6 +545,9 @@ hl::PlanView view(const hl_plan_s* pl) {
   for (int k = 0; k < 3; ++k) v.uext[k] = pl->uext[k];
   v.tab = pl->dtab;
   v.adj_tab = pl->dadj;
+  v.kap_p = pl->dkap_p;
+  v.kap_u = pl->dkap_u;
+  v.dt = pl->dt;
   v.d = pl->d;
   v.m = pl->m;
   v.precision = pl->precision;
@@ -889,7 +900,8 @@ hl_status hl_plan_destroy(hl_plan_t plan) {
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   if (plan->dtab) (void)hipFree(plan->dtab);
   if (plan->dadj) (void)hipFree(plan->dadj);
-  for (void* q : {plan->tab_dk, plan->tab_rev, plan->fp, plan->fu, plan->sp, plan->su, (void*)plan->gpart})
+  for (void* q : {plan->dkap_p, plan->dkap_u, plan->tab_dk, plan->tab_rev, plan->fp, plan->fu, plan->sp, plan->su,
+                  (void*)plan->gpart})
     if (q) (void)hipFree(q);
   if (plan->dpartial) (void)hipFree(plan->dpartial);
   delete plan;
@@ -920,7 +932,7 @@ hl_status hl_init(hl_plan_t plan, const double* p0, const double* u0, uint32_t f
   if ((st = upload_field(plan, p0, 0, p, s)) != HL_OK) return st;
   if ((st = upload_field(plan, u0, 1, u, s)) != HL_OK) return st;
   if (flags & HL_INIT_STARTUP) {
-    hipError_t e = plan->ks.u_half(view(plan), u, p, 0.5, s);
+    hipError_t e = u_fn(plan)(view(plan), u, p, 0.5, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hl_init: start-up half-step");
   }
@@ -947,7 +959,7 @@ hl_status hl_p_half(hl_plan_t plan, void* p, void* u, void* stream) {
   if (!p || !u || p == u) return fail(HL_ERR_ARG, "hl_p_half: p and u must be distinct non-NULL buffers");
   const hl::PlanView v = view(plan);
   hipError_t e = plan->walls ? plan->ks.ghost(v, u, (hipStream_t)stream) : hipSuccess;
-  if (e == hipSuccess) e = plan->ks.p_half(v, p, u, (hipStream_t)stream);
+  if (e == hipSuccess) e = p_fn(plan)(v, p, u, (hipStream_t)stream);
   return e == hipSuccess ? HL_OK : hip_fail(e, "hl_p_half: launch");
 }
 
@@ -957,7 +969,7 @@ hl_status hl_u_half(hl_plan_t plan, void* u, const void* p, double weight_scale,
   if (st != HL_OK) return st;
   if (!p || !u || p == u) return fail(HL_ERR_ARG, "hl_u_half: p and u must be distinct non-NULL buffers");
   if (!std::isfinite(weight_scale)) return fail(HL_ERR_ARG, "hl_u_half: weight_scale must be finite");
-  hipError_t e = plan->ks.u_half(view(plan), u, p, weight_scale, (hipStream_t)stream);
+  hipError_t e = u_fn(plan)(view(plan), u, p, weight_scale, (hipStream_t)stream);
   return e == hipSuccess ? HL_OK : hip_fail(e, "hl_u_half: launch");
 }
 
@@ -982,10 +994,51 @@ hl_status hl_step(hl_plan_t plan, void* p, void* u, int64_t nsteps, void* stream
   }
   for (; n < nsteps; ++n) {
     hipError_t e = plan->walls ? plan->ks.ghost(v, u, s) : hipSuccess;
-    if (e == hipSuccess) e = plan->ks.p_half(v, p, u, s);
-    if (e == hipSuccess) e = plan->ks.u_half(v, u, p, 1.0, s);
+    if (e == hipSuccess) e = p_fn(plan)(v, p, u, s);
+    if (e == hipSuccess) e = u_fn(plan)(v, u, p, 1.0, s);
     if (e != hipSuccess) return hip_fail(e, "hl_step: launch");
   }
+  return HL_OK;
+}
+
+hl_status hl_set_kappa(hl_plan_t plan, const double* kappa_p, const double* kappa_u) {
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_set_kappa");
+  if (st != HL_OK) return st;
+  if (!kappa_p != !kappa_u) return fail(HL_ERR_ARG, "hl_set_kappa: give both kappa arrays or neither");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hl_set_kappa: pending work failed");
+  drop_graph(plan);
+  if (!kappa_p) {  // back to the constant kappa of the plan
+    plan->var_kappa = false;
+    for (void** q : {&plan->dkap_p, &plan->dkap_u}) {
+      if (*q) (void)hipFree(*q);
+      *q = nullptr;
+    }
+    return HL_OK;
+  }
+  if (plan->walls || !plan->ks.p_half_var)
+    return fail(HL_ERR_UNSUPPORTED, "hl_set_kappa: variable kappa is built for periodic plans, d = 1, or d = 2 "
+                                    "with m <= 3, in HL_FP64 or HL_FP32");
+  // host layout [nodes][b_1..b_d], b_k in 0..2m+1: the field layout of order 2m+1
+  const LayoutMap L = hl_host::field_layout(plan->d, 2 * plan->m + 1, plan->K, false, 0);
+  const int64_t hw = (int64_t)L.nc * L.K[0] * L.K[1] * L.K[2];
+  for (const double* src : {kappa_p, kappa_u})
+    for (int64_t i = 0; i < hw; ++i)
+      if (!std::isfinite(src[i])) return fail(HL_ERR_ARG, "hl_set_kappa: kappa data must be finite");
+  FieldImage im{plan->precision, (int64_t)L.nc * L.nodes, {}, {}};
+  if (!im.alloc()) return fail(HL_ERR_NOMEM, "hl_set_kappa: host staging allocation failed");
+  for (void** q : {&plan->dkap_p, &plan->dkap_u})
+    if (!*q && (e = hipMalloc(q, im.hi_bytes())) != hipSuccess)
+      return fail(HL_ERR_NOMEM, std::string("hl_set_kappa: device allocation: ") + hipGetErrorString(e));
+  const double* srcs[2] = {kappa_p, kappa_u};
+  void* dsts[2] = {plan->dkap_p, plan->dkap_u};
+  for (int f = 0; f < 2; ++f) {
+    L.for_each([&](int64_t h, int64_t dv) { im.put(dv, srcs[f][h]); });
+    e = hipMemcpy(dsts[f], im.hi.data(), im.hi_bytes(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hl_set_kappa: copy to device");
+  }
+  plan->var_kappa = true;
   return HL_OK;
 }
 
@@ -1008,6 +1061,7 @@ hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* 
   hl_status st = check_plan(plan, "hl_adjoint_step");
   if (st != HL_OK) return st;
   if (plan->walls) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: built for periodic plans only");
+  if (plan->var_kappa) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: built for constant kappa only");
   if (grad_kappa && (!p || !u)) return fail(HL_ERR_ARG, "hl_adjoint_step: the gradient needs the forward state p, u");
   if (!plan->dadj) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: not built for this (d, m, precision)");
   if (!p_bar || !u_bar || p_bar == u_bar)

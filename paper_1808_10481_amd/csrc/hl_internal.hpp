@@ -14,6 +14,9 @@ namespace hl {
 struct PlanView {
   Grid gp, gu;          // pressure / velocity half-step grids
   const void* adj_tab;  // transposed half-step blocks (periodic plans with an adjoint), or NULL
+  const void* kap_p;    // variable kappa: Taylor data on the primal / dual nodes, or NULL
+  const void* kap_u;
+  double dt;            // time step (variable-kappa kernels)
   int32_t uext[3];      // velocity array extents (ghost fill, walls only)
   const void* tab;      // packed operator tables in the plan's arithmetic type
   int d, m, precision;
@@ -31,6 +34,8 @@ struct KernelSet {
   UHalfFn u_half;
   GhostFn ghost;         // ghost-shell refresh of a wall-bounded velocity array
   AdjFn adj_p, adj_u;    // transposed half-steps, NULL where not built
+  PHalfFn p_half_var;    // variable-kappa half-steps, NULL where not built
+  UHalfFn u_half_var;
   int table_words;       // TableLayout<D, M>::TOTAL
   int p_off[3];          // offsets of the pressure merged tables, per component
   int u_off;             // offset of the velocity (Q) merged table
@@ -141,6 +146,36 @@ hipError_t launch_adjoint(const PlanView& pv, void* out, const void* in, hipStre
 }
 
 template <class S>
+VarArgs<typename S::C> var_args(const PlanView& pv) {
+  VarArgs<typename S::C> va;
+  va.w0 = (typename S::C)pv.dt;
+  va.ratio[0] = 0;
+  for (int k = 1; k < 9; ++k) va.ratio[k] = (typename S::C)(0.25 * pv.dt * pv.dt / ((2.0 * k) * (2.0 * k + 1.0)));
+  for (int k = 0; k < 3; ++k) va.ih[k] = (typename S::C)pv.ih[k];
+  return va;
+}
+
+template <int D, int M, class S>
+hipError_t launch_p_var(const PlanView& pv, void* p, const void* u, hipStream_t s) {
+  constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
+  const Grid& g = pv.gp;
+  hipLaunchKernelGGL((p_half_var<D, M, S>), grid_shape(g), block_shape<D>(), 0, s, S::make(p, 1, NC, g.onodes),
+                     S::make(u, D, NC, g.snodes), S::make(pv.kap_p, 1, NP, g.onodes), g, var_args<S>(pv));
+  return hipGetLastError();
+}
+
+template <int D, int M, class S>
+hipError_t launch_u_var(const PlanView& pv, void* u, const void* p, double wscale, hipStream_t s) {
+  using T = typename S::C;
+  constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
+  const Grid& g = pv.gu;
+  hipLaunchKernelGGL((u_half_var<D, M, S>), grid_shape(g), block_shape<D>(), 0, s, S::make(u, D, NC, g.onodes),
+                     S::make(p, 1, NC, g.snodes), S::make(pv.kap_u, 1, NP, g.onodes), g, var_args<S>(pv),
+                     (T)wscale);
+  return hipGetLastError();
+}
+
+template <class S>
 constexpr bool kPlain = false;
 template <typename W>
 constexpr bool kPlain<PlainStore<W>> = true;
@@ -157,6 +192,13 @@ inline bool make_set(KernelSet* out) {
   if constexpr (kPlain<S> && Dims<D, M>::NC <= kAdjointMaxNC) {
     out->adj_p = &launch_adjoint<D, M, S, true>;
     out->adj_u = &launch_adjoint<D, M, S, false>;
+  }
+  out->p_half_var = nullptr;
+  out->u_half_var = nullptr;
+  // variable kappa: FP64 and FP32 storage, d = 1 (all m) and d = 2 (m <= 3)
+  if constexpr (kPlain<S> && (D == 1 || (D == 2 && M <= 3))) {
+    out->p_half_var = &launch_p_var<D, M, S>;
+    out->u_half_var = &launch_u_var<D, M, S>;
   }
   return true;
 }

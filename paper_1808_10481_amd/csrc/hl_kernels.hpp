@@ -554,4 +554,202 @@ __global__ void __launch_bounds__(256) adjoint_half(typename S::View out, typena
   }
 }
 
+// ---------------------------------------------------------------------------
+// Variable coefficient kappa(x) (Sec. 4, "Smoothly varying wave speed"):
+// kappa is given per node as a Taylor polynomial of degree 2m+1 per variable
+// (scaled like the data), about the primal nodes for the pressure half-step
+// and the dual nodes for the velocity half-step.  From p_t = -kappa div u and
+// u_t = -grad p the odd time derivatives are
+//   d_t^{2k+1} p = -(kappa Lap)^k (kappa div u),   d_t^{2k+1} u = -grad (kappa Lap)^k p,
+// evaluated on the cell polynomials with every product truncated to degree
+// 2m+1 per variable, k = 0..kmax, kmax = floor(d (2m+1) / 2) (the last k at
+// which Lap^k of a cell polynomial can be nonzero):
+//   P <- P - sum_k w_k r_k,   r_0 = T[kappa div c],  r_k = T[kappa Lap r_{k-1}]
+//   U_i <- U_i - sum_k w_k D_i g_k,   g_0 = c,  g_k = T[kappa Lap g_{k-1}].
+// No operator can be merged into a constant table here (kappa differs per
+// cell), so the kernels build the full (2m+2)^d interpolant in registers;
+// built for d = 1 (all m) and d = 2 (m <= 3).
+// ---------------------------------------------------------------------------
+template <int D, int M>
+struct VK {
+  static constexpr int N2 = 2 * M + 2, MP = M + 1;
+  static constexpr int NP = ipow(N2, D);            // cell polynomial coefficients
+  static constexpr int KMAX = (D * (2 * M + 1)) / 2;
+};
+
+// The series is accumulated as t_k = w_k r_k with t_k = (w_k / w_{k-1})
+// T[kappa Lap t_{k-1}]: the ratio (dt/2)^2 / (2k (2k+1)) cancels the 1/h^2 of
+// each Laplacian, so every term stays O(1) (r_k alone grows like h^{-2k} and
+// overflows FP32 for large m).
+template <typename T>
+struct VarArgs {
+  T w0;        // w_0 = dt
+  T ratio[9];  // w_k / w_{k-1} = (dt/2)^2 / (2k (2k+1)), k = 1..kmax (kmax <= 8)
+  T ih[3];     // 1 / h_k
+};
+
+// Full interpolant c[b_x + N2 b_y] of one component from its 2^D corner blocks.
+template <int D, int M, class S>
+__device__ __forceinline__ void interp_full(const typename S::View& f, int comp, const uint32_t* cn,
+                                            typename S::C* c) {
+  using T = typename S::C;
+  constexpr int MP = M + 1, N2 = 2 * M + 2, NC = Dims<D, M>::NC;
+  static_assert(D == 1 || D == 2, "variable kappa is built for d <= 2");
+  if constexpr (D == 1) {
+    T L[MP], R[MP];
+#pragma unroll
+    for (int a = 0; a < MP; ++a) {
+      L[a] = S::load(f, comp * NC + a, cn[0]);
+      R[a] = S::load(f, comp * NC + a, cn[1]);
+    }
+    pass1d<M, 0>(L, R, c);
+  } else {
+    T Yl[MP][N2], Yh[MP][N2];  // x pass at the lower / upper y corners, per a_y
+#pragma unroll
+    for (int ay = 0; ay < MP; ++ay) {
+      T L[MP], R[MP];
+#pragma unroll
+      for (int ax = 0; ax < MP; ++ax) {
+        L[ax] = S::load(f, comp * NC + ax + MP * ay, cn[0]);
+        R[ax] = S::load(f, comp * NC + ax + MP * ay, cn[1]);
+      }
+      pass1d<M, 0>(L, R, Yl[ay]);
+#pragma unroll
+      for (int ax = 0; ax < MP; ++ax) {
+        L[ax] = S::load(f, comp * NC + ax + MP * ay, cn[2]);
+        R[ax] = S::load(f, comp * NC + ax + MP * ay, cn[3]);
+      }
+      pass1d<M, 0>(L, R, Yh[ay]);
+    }
+#pragma unroll
+    for (int bx = 0; bx < N2; ++bx) {
+      T L[MP], R[MP], out[N2];
+#pragma unroll
+      for (int ay = 0; ay < MP; ++ay) {
+        L[ay] = Yl[ay][bx];
+        R[ay] = Yh[ay][bx];
+      }
+      pass1d<M, 0>(L, R, out);
+#pragma unroll
+      for (int by = 0; by < N2; ++by) c[bx + N2 * by] = out[by];
+    }
+  }
+}
+
+// out = T[kappa f]: out_b = sum_{a <= b} kappa_a f_{b-a} (per variable),
+// kappa_a read from plane a of the kappa array at node n0.
+template <int D, int M, class S>
+__device__ __forceinline__ void tprod(const typename S::View& kv, uint32_t n0, const typename S::C* f,
+                                      typename S::C* out) {
+  using T = typename S::C;
+  constexpr int N2 = 2 * M + 2, NP = VK<D, M>::NP;
+#pragma unroll
+  for (int b = 0; b < NP; ++b) out[b] = T(0);
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    const T ka = S::load(kv, a, n0);
+    const int ax = a % N2, ay = a / N2;
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      const int bx = b % N2, by = b / N2;
+      if (bx >= ax && by >= ay) out[b] = fma(ka, f[(bx - ax) + N2 * (by - ay)], out[b]);
+    }
+  }
+}
+
+// out = sc Lap f in coefficient space: sc sum_i (b_i + 1)(b_i + 2) / h_i^2 f_{b + 2 e_i}.
+template <int D, int M, typename T>
+__device__ __forceinline__ void lap_coef(const T* f, T* out, const T* ih, T sc) {
+  constexpr int N2 = 2 * M + 2, NP = VK<D, M>::NP;
+  const T ix2 = sc * ih[0] * ih[0], iy2 = sc * ih[1] * ih[1];
+#pragma unroll
+  for (int b = 0; b < NP; ++b) {
+    const int bx = b % N2, by = b / N2;
+    T v = T(0);
+    if (bx + 2 < N2) v = fma(T((bx + 1) * (bx + 2)) * ix2, f[b + 2], v);
+    if (D > 1 && by + 2 < N2) v = fma(T((by + 1) * (by + 2)) * iy2, f[b + 2 * N2], v);
+    out[b] = v;
+  }
+}
+
+template <int D, int M, class S>
+__global__ void __launch_bounds__(256) p_half_var(typename S::View p, typename S::View u, typename S::View kp,
+                                                  Grid g, VarArgs<typename S::C> va) {
+  using T = typename S::C;
+  constexpr int N2 = 2 * M + 2, MP = M + 1, NP = VK<D, M>::NP, NC = Dims<D, M>::NC;
+  int32_t j[3];
+  if (!node_of_thread<D>(g, j)) return;
+  uint32_t cn[1 << D];
+  corner_nodes<D>(g, j, cn);  // dual q = j - 1 + e
+  const uint32_t n0 = out_index<D>(g, j);
+  T div[NP];  // w_0 div c
+#pragma unroll
+  for (int b = 0; b < NP; ++b) div[b] = T(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    T c[NP];
+    interp_full<D, M, S>(u, i, cn, c);
+    const int st = i == 0 ? 1 : N2;
+    const T f = va.w0 * va.ih[i];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      const int bi = i == 0 ? b % N2 : b / N2;
+      if (bi + 1 < N2) div[b] = fma(T(bi + 1) * f, c[b + st], div[b]);
+    }
+  }
+  T t[NP], acc[NC];
+  tprod<D, M, S>(kp, n0, div, t);  // t_0 = w_0 r_0
+#pragma unroll
+  for (int s = 0; s < NC; ++s) acc[s] = t[(s % MP) + N2 * (s / MP)];
+#pragma unroll 1
+  for (int k = 1; k <= VK<D, M>::KMAX; ++k) {
+    T l[NP];
+    lap_coef<D, M>(t, l, va.ih, va.ratio[k]);
+    tprod<D, M, S>(kp, n0, l, t);  // t_k = w_k r_k
+#pragma unroll
+    for (int s = 0; s < NC; ++s) acc[s] += t[(s % MP) + N2 * (s / MP)];
+  }
+  finish_pressure<D, M, S>(p, n0, acc);
+}
+
+template <int D, int M, class S>
+__global__ void __launch_bounds__(256) u_half_var(typename S::View u, typename S::View p, typename S::View ku,
+                                                  Grid g, VarArgs<typename S::C> va, typename S::C wscale) {
+  using T = typename S::C;
+  constexpr int N2 = 2 * M + 2, MP = M + 1, NP = VK<D, M>::NP, NC = Dims<D, M>::NC;
+  int32_t j[3];
+  if (!node_of_thread<D>(g, j)) return;
+  uint32_t cn[1 << D];
+  corner_nodes<D>(g, j, cn);  // primal j = q + e
+  const uint32_t n0 = out_index<D>(g, j);
+  T gk[NP], q[NP];  // gk: t_k = w_k g_k
+  interp_full<D, M, S>(p, 0, cn, gk);
+#pragma unroll
+  for (int b = 0; b < NP; ++b) {
+    gk[b] *= va.w0;
+    q[b] = gk[b];
+  }
+#pragma unroll 1
+  for (int k = 1; k <= VK<D, M>::KMAX; ++k) {
+    T l[NP];
+    lap_coef<D, M>(gk, l, va.ih, va.ratio[k]);
+    tprod<D, M, S>(ku, n0, l, gk);
+#pragma unroll
+    for (int b = 0; b < NP; ++b) q[b] += gk[b];
+  }
+  // u_i[s] -= wscale (s_i + 1) / h_i q[s + e_i]
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const T f = wscale * va.ih[i];
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+      const int sx = s % MP, sy = s / MP;
+      const int si = i == 0 ? sx : sy;
+      const T qv = q[(sx + (i == 0)) + N2 * (sy + (i == 1))];
+      const T a = -(T)(si + 1) * f;
+      S::update(u, i * NC + s, n0, [&](T x) { return fma(a, qv, x); });
+    }
+  }
+}
+
 }  // namespace hl

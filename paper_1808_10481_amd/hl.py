@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "HL_OK", 1: "HL_ERR_ARG", 2: "HL_ERR_CFL", 3: "HL_ERR_UNSUPPO
 
 # Every symbol include/hl.h declares.
 EXPORTS = ("hl_plan", "hl_plan_destroy", "hl_plan_info", "hl_init", "hl_export", "hl_step",
-           "hl_p_half", "hl_u_half", "hl_norms", "hl_adjoint_step", "hl_last_error")
+           "hl_p_half", "hl_u_half", "hl_set_kappa", "hl_norms", "hl_adjoint_step", "hl_last_error")
 
 
 class HLProblem(ctypes.Structure):
@@ -66,6 +66,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hl_p_half": ([vp, vp, vp, vp]),
         "hl_u_half": ([vp, vp, vp, dbl, vp]),
         "hl_norms": ([vp, vp, vp, ctypes.POINTER(dbl)]),
+        "hl_set_kappa": ([vp, vp, vp]),
         "hl_adjoint_step": ([vp, vp, vp, vp, vp, vp, i64, vp]),
     }
     for name, args in sig.items():
@@ -228,6 +229,20 @@ class Plan:
             gg = ctypes.c_void_p(grad_kappa.data_ptr())
         _check(lib().hl_adjoint_step(self._h, ctypes.c_void_p(p_bar.data_ptr()), ctypes.c_void_p(u_bar.data_ptr()),
                                      pp, uu, gg, int(nsteps), _stream_ptr(stream)))
+
+    def set_kappa(self, kappa_p=None, kappa_u=None):
+        """Variable kappa: FP64 Taylor data (K,)*d + (2m+2,)*d about the primal
+        and dual nodes (hl_set_kappa); None, None restores the constant kappa."""
+        if kappa_p is None and kappa_u is None:
+            _check(lib().hl_set_kappa(self._h, None, None))
+            return
+        n2 = 2 * self.m + 2
+        shape = self.cells + (n2,) * self.d
+        kp = np.ascontiguousarray(kappa_p, dtype=np.float64)
+        ku = np.ascontiguousarray(kappa_u, dtype=np.float64)
+        if kp.shape != shape or ku.shape != shape:
+            raise ValueError(f"kappa data must have shape {shape}")
+        _check(lib().hl_set_kappa(self._h, kp.ctypes.data_as(ctypes.c_void_p), ku.ctypes.data_as(ctypes.c_void_p)))
 
     def norms(self, p, u):
         out = (ctypes.c_double * 2)()
