@@ -237,6 +237,55 @@ def run_varkappa(hl, torch, steps, K=1024, m=3):
     return res
 
 
+def run_batch(hl, torch, steps, nshots=32, m=3):
+    """Batched shots: `nshots` periodic square grids with seeded sizes in
+    [256, 1024] (the batched configuration's size mix), m=3 FP32, per-shot wave
+    speed c in [1, 3] and standing-mode data; `steps` steps advanced (a) with
+    one launch per half-step for all shots (hl_batch_step) and (b) shot by
+    shot with hl_step.  Constant kappa per shot (per-node kappa data for 32
+    grids of this size would take ~15 GB of host memory to generate)."""
+    from paper_1808_10481_amd import inputs
+    rng = np.random.default_rng(6)
+    sizes = [int(k) for k in rng.integers(256, 1025, nshots)]
+    speeds = rng.uniform(1.0, 3.0, nshots)
+    plans, states = [], []
+    for K, c in zip(sizes, speeds):
+        plan = hl.Plan(2, m, (K, K), cfl=0.5, c=float(c), precision="fp32")
+        P0, U0 = inputs.standing_mode(2, m, (K, K), (1.0, 1.0), tuple(int(w) for w in rng.integers(1, 9, 2)),
+                                      0.0, plan.dt / 2, kappa=float(c) ** 2)
+        p, u = plan.alloc()
+        plan.init(p, u, P0, U0)
+        plans.append(plan)
+        states.append((p, u))
+    cells = sum(K * K for K in sizes)
+    batch = hl.Batch(plans)
+    ps, us = [p for p, _ in states], [u for _, u in states]
+    batch.step(ps, us, 16)                                     # warm-up + graph capture
+    for plan, (p, u) in zip(plans, states):
+        plan.step(p, u, 16)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    batch.step(ps, us, steps)
+    ev[1].record(stream)
+    for plan, (p, u) in zip(plans, states):
+        plan.step(p, u, steps)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    tb, ts = ev[0].elapsed_time(ev[1]) / steps, ev[1].elapsed_time(ev[2]) / steps
+    batch.close()
+    for plan in plans:
+        plan.close()
+    del states, ps, us
+    torch.cuda.empty_cache()
+    return {"batched": {"value": cells / (tb * 1e-3), "unit": "cell-updates/s", "ms_per_step": tb},
+            "per_shot": {"value": cells / (ts * 1e-3), "unit": "cell-updates/s", "ms_per_step": ts},
+            "speedup_batched_vs_per_shot": ts / tb, "steps": steps,
+            "config": {"workload": f"batched_shots_2d {nshots} shots m={m} fp32, sizes seeded in [256, 1024]^2, "
+                                   "c per shot in [1, 3]", "cells": cells, "sizes": sizes}}
+
+
 def run_adjoint(hl, torch, steps, K=512, m=2):
     """Discrete adjoint on the shape of the gradient workload (2D, m=2, 512^2,
     periodic, constant kappa): `steps` transposed steps alone, then `steps`
@@ -334,6 +383,8 @@ def main():
     ap.add_argument("--no-walls", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-varkappa", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--steps-batch", type=int, default=48)
     ap.add_argument("--steps-varkappa", type=int, default=50)
     ap.add_argument("--steps-adjoint", type=int, default=100)
     ap.add_argument("--steps-walls", type=int, default=200)
@@ -413,6 +464,9 @@ def main():
 
     if not args.no_varkappa:
         out["variable_kappa_2d"] = run_varkappa(hl, torch, args.steps_varkappa)
+
+    if not args.no_batch:
+        out["batched_shots_2d"] = run_batch(hl, torch, args.steps_batch)
 
     if not args.no_adjoint:
         out["adjoint_2d"] = run_adjoint(hl, torch, args.steps_adjoint)

@@ -216,6 +216,20 @@ hl_status hl_norms(hl_plan_t plan, const void* p, const void* u, double* out);
 hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* p,
                           const void* u, void* grad_kappa, int64_t nsteps, void* stream);
 
+/* Batched shots: many independent periodic problems ("shots") of the same
+ * d, m and precision - each with its own grid size, time step, coefficient
+ * (hl_set_kappa on every plan, or on none) and buffers - advanced together,
+ * one kernel launch per half-step for all of them (shot s takes its own range
+ * of workgroups).  hl_batch_create keeps the plan handles (they must outlive
+ * the batch).  hl_batch_step advances shot i's (p[i], u[i]) by nsteps steps,
+ * exactly as hl_step on each plan would; descriptors are rebuilt (after
+ * waiting for the stream) when the buffers change, and nsteps >= 16 replays a
+ * captured graph of 16 batched steps.  Periodic plans only. */
+typedef struct hl_batch_s* hl_batch_t;
+hl_status hl_batch_create(const hl_plan_t* plans, int32_t n, hl_batch_t* out);
+hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_t nsteps, void* stream);
+hl_status hl_batch_destroy(hl_batch_t batch);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char* hl_last_error(void);
 

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -188,6 +189,21 @@ struct hl_plan_s {
   hipGraphExec_t gexec = nullptr;
   const void* graph_p = nullptr;  // buffers the graph was captured for
   const void* graph_u = nullptr;
+};
+
+// A batch of shots (plans of the same d, m and precision) advanced together.
+struct hl_batch_s {
+  std::vector<hl_plan_s*> plans;
+  hl::KernelSet ks;                   // the common kernel set
+  int device = 0;
+  bool var = false;                   // variable kappa (every plan, or none)
+  void* dp = nullptr;                 // device descriptors of the p / u half-steps
+  void* du = nullptr;
+  size_t cap = 0;                     // bytes allocated for each
+  std::vector<void*> bp, bu;          // buffers the descriptors describe
+  int pblocks = 0, ublocks = 0;
+  hipStream_t cap_stream = nullptr;   // graph of kGraphChunk batched steps
+  hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -1109,6 +1125,120 @@ hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* 
     if (e == hipSuccess) e = plan->ks.adj_u(va, u_bar, p_bar, s);                    // Ub -= A^T Pb
   }
   return e == hipSuccess ? HL_OK : hip_fail(e, "hl_adjoint_step: gradient launch");
+}
+
+hl_status hl_batch_create(const hl_plan_t* plans, int32_t n, hl_batch_t* out) {
+  g_last_error.clear();
+  if (!plans || !out || n < 1) return fail(HL_ERR_ARG, "hl_batch_create: need n >= 1 plans and an output handle");
+  for (int32_t i = 0; i < n; ++i) {
+    hl_status st = check_plan(plans[i], "hl_batch_create");
+    if (st != HL_OK) return st;
+    const hl_plan_s* p = plans[i];
+    if (p->walls) return fail(HL_ERR_UNSUPPORTED, "hl_batch_create: batches are built for periodic plans");
+    if (p->d != plans[0]->d || p->m != plans[0]->m || p->precision != plans[0]->precision)
+      return fail(HL_ERR_ARG, "hl_batch_create: every plan must have the same d, m and precision");
+  }
+  hl_batch_s* b = new (std::nothrow) hl_batch_s();
+  if (!b) return fail(HL_ERR_NOMEM, "hl_batch_create: out of host memory");
+  b->plans.assign(plans, plans + n);
+  b->ks = plans[0]->ks;
+  b->device = plans[0]->device;
+  *out = b;
+  return HL_OK;
+}
+
+hl_status hl_batch_destroy(hl_batch_t batch) {
+  g_last_error.clear();
+  if (!batch) return HL_OK;
+  if (batch->gexec) (void)hipGraphExecDestroy(batch->gexec);
+  if (batch->cap_stream) (void)hipStreamDestroy(batch->cap_stream);
+  if (batch->dp) (void)hipFree(batch->dp);
+  if (batch->du) (void)hipFree(batch->du);
+  delete batch;
+  return HL_OK;
+}
+
+hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_t nsteps, void* stream) {
+  g_last_error.clear();
+  if (!batch) return fail(HL_ERR_ARG, "hl_batch_step: batch is NULL");
+  if (!p || !u) return fail(HL_ERR_ARG, "hl_batch_step: NULL buffer arrays");
+  if (nsteps < 0) return fail(HL_ERR_ARG, "hl_batch_step: nsteps must be >= 0");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != batch->device)
+    return fail(HL_ERR_DEVICE, "hl_batch_step: current HIP device differs from the batch's device");
+  const int n = (int)batch->plans.size();
+  const bool var = batch->plans[0]->var_kappa;
+  for (int i = 0; i < n; ++i) {
+    if (!p[i] || !u[i] || p[i] == u[i]) return fail(HL_ERR_ARG, "hl_batch_step: p[i] and u[i] must be distinct non-NULL");
+    if (batch->plans[i]->var_kappa != var)
+      return fail(HL_ERR_ARG, "hl_batch_step: variable kappa must be set on every plan of the batch or on none");
+  }
+  if (var && !batch->ks.p_half_var)
+    return fail(HL_ERR_UNSUPPORTED, "hl_batch_step: variable kappa is not built for this (d, m, precision)");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  const bool same = var == batch->var && batch->bp.size() == (size_t)n &&
+                    std::equal(batch->bp.begin(), batch->bp.end(), p) && std::equal(batch->bu.begin(), batch->bu.end(), u);
+  if (!same) {
+    // descriptors for these buffers; wait for work that may still read the old ones
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hl_batch_step: pending work failed");
+    if (batch->gexec) (void)hipGraphExecDestroy(batch->gexec);
+    batch->gexec = nullptr;
+    std::vector<hl::PlanView> views((size_t)n);
+    std::vector<hl::BatchShot> shots((size_t)n);
+    for (int i = 0; i < n; ++i) {
+      views[i] = view(batch->plans[i]);
+      shots[i] = hl::BatchShot{&views[i], p[i], u[i]};
+    }
+    std::vector<unsigned char> pd, ud;
+    batch->ks.batch_desc(shots.data(), n, var, &pd, &ud, &batch->pblocks, &batch->ublocks);
+    if (pd.size() > batch->cap) {
+      if (batch->dp) (void)hipFree(batch->dp);
+      if (batch->du) (void)hipFree(batch->du);
+      batch->dp = batch->du = nullptr;
+      batch->cap = 0;
+      e = hipMalloc(&batch->dp, pd.size());
+      if (e == hipSuccess) e = hipMalloc(&batch->du, ud.size());
+      if (e != hipSuccess) return fail(HL_ERR_NOMEM, "hl_batch_step: descriptor allocation failed");
+      batch->cap = pd.size();
+    }
+    e = hipMemcpy(batch->dp, pd.data(), pd.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(batch->du, ud.data(), ud.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hl_batch_step: descriptor upload");
+    batch->bp.assign(p, p + n);
+    batch->bu.assign(u, u + n);
+    batch->var = var;
+  }
+  auto one_step = [&](hipStream_t st) -> hipError_t {
+    hipError_t le = batch->ks.p_batch(batch->dp, n, batch->pblocks, var, st);
+    if (le == hipSuccess) le = batch->ks.u_batch(batch->du, n, batch->ublocks, var, st);
+    return le;
+  };
+  int64_t k = 0;
+  if (nsteps >= kGraphChunk) {
+    if (!batch->gexec) {
+      if (!batch->cap_stream && (e = hipStreamCreateWithFlags(&batch->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "hl_batch_step: stream");
+      if ((e = hipStreamBeginCapture(batch->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "hl_batch_step: capture");
+      hipError_t le = hipSuccess;
+      for (int64_t i = 0; i < kGraphChunk && le == hipSuccess; ++i) le = one_step(batch->cap_stream);
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(batch->cap_stream, &graph);
+      if (le != hipSuccess) e = le;
+      if (e == hipSuccess) e = hipGraphInstantiate(&batch->gexec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        batch->gexec = nullptr;
+        return hip_fail(e, "hl_batch_step: graph capture");
+      }
+    }
+    for (; k + kGraphChunk <= nsteps; k += kGraphChunk)
+      if ((e = hipGraphLaunch(batch->gexec, s)) != hipSuccess) return hip_fail(e, "hl_batch_step: graph launch");
+  }
+  for (; k < nsteps; ++k)
+    if ((e = one_step(s)) != hipSuccess) return hip_fail(e, "hl_batch_step: launch");
+  return HL_OK;
 }
 
 }  // extern "C"

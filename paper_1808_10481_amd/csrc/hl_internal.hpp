@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstring>
+#include <vector>
+
 #include "hl.h"
 #include "hl_kernels.hpp"
 
@@ -28,6 +31,16 @@ typedef hipError_t (*UHalfFn)(const PlanView&, void* u, const void* p, double ws
 typedef hipError_t (*GhostFn)(const PlanView&, void* u, hipStream_t);
 // Transposed half-steps: pb -= B^T ub (AdjFn p), ub -= A^T pb (AdjFn u).
 typedef hipError_t (*AdjFn)(const PlanView&, void* out, const void* in, hipStream_t);
+// Batched shots: descriptor images of the p and u half-steps of every shot
+// (built where the storage type is known) and the two batched launches.
+struct BatchShot {
+  const PlanView* v;
+  void* p;
+  void* u;
+};
+typedef void (*BatchDescFn)(const BatchShot* shots, int n, bool var, std::vector<unsigned char>* pdesc,
+                            std::vector<unsigned char>* udesc, int* pblocks, int* ublocks);
+typedef hipError_t (*BatchHalfFn)(const void* desc, int n, int blocks, bool var, hipStream_t);
 
 struct KernelSet {
   PHalfFn p_half;
@@ -36,6 +49,8 @@ struct KernelSet {
   AdjFn adj_p, adj_u;    // transposed half-steps, NULL where not built
   PHalfFn p_half_var;    // variable-kappa half-steps, NULL where not built
   UHalfFn u_half_var;
+  BatchDescFn batch_desc;
+  BatchHalfFn p_batch, u_batch;
   int table_words;       // TableLayout<D, M>::TOTAL
   int p_off[3];          // offsets of the pressure merged tables, per component
   int u_off;             // offset of the velocity (Q) merged table
@@ -180,6 +195,72 @@ constexpr bool kPlain = false;
 template <typename W>
 constexpr bool kPlain<PlainStore<W>> = true;
 
+template <int D, int M, class S>
+constexpr bool kVarBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 3));
+
+template <int D, int M, class S>
+void batch_desc(const BatchShot* shots, int n, bool var, std::vector<unsigned char>* pdesc,
+                std::vector<unsigned char>* udesc, int* pblocks, int* ublocks) {
+  using T = typename S::C;
+  constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
+  std::vector<ShotHalf<S>> P((size_t)n), U((size_t)n);
+  int fp = 0, fu = 0;
+  for (int i = 0; i < n; ++i) {
+    const PlanView& v = *shots[i].v;
+    ShotHalf<S>& a = P[i];
+    a = ShotHalf<S>{};
+    a.out = S::make(shots[i].p, 1, NC, v.gp.onodes);
+    a.in = S::make(shots[i].u, D, NC, v.gp.snodes);
+    a.kap = var ? S::make(v.kap_p, 1, NP, v.gp.onodes) : a.out;
+    a.tab = (const T*)v.tab;
+    a.g = v.gp;
+    a.va = var_args<S>(v);
+    a.wscale = T(1);
+    for (int k = 0; k < 3; ++k) a.ih[k] = (T)v.ih[k];
+    a.first_block = fp;
+    fp += v.gp.per_xcd * kXcds;
+    ShotHalf<S>& b = U[i];
+    b = ShotHalf<S>{};
+    b.out = S::make(shots[i].u, D, NC, v.gu.onodes);
+    b.in = S::make(shots[i].p, 1, NC, v.gu.snodes);
+    b.kap = var ? S::make(v.kap_u, 1, NP, v.gu.onodes) : b.out;
+    b.tab = (const T*)v.tab;
+    b.g = v.gu;
+    b.va = a.va;
+    b.wscale = T(1);
+    for (int k = 0; k < 3; ++k) b.ih[k] = (T)v.ih[k];
+    b.first_block = fu;
+    fu += v.gu.per_xcd * kXcds;
+  }
+  const size_t bytes = (size_t)n * sizeof(ShotHalf<S>);
+  pdesc->resize(bytes);
+  udesc->resize(bytes);
+  std::memcpy(pdesc->data(), P.data(), bytes);
+  std::memcpy(udesc->data(), U.data(), bytes);
+  *pblocks = fp;
+  *ublocks = fu;
+}
+
+template <int D, int M, class S, bool P>
+hipError_t launch_batch(const void* desc, int n, int blocks, bool var, hipStream_t s) {
+  const ShotHalf<S>* d = static_cast<const ShotHalf<S>*>(desc);
+  if (var) {
+    if constexpr (kVarBuilt<D, M, S>) {
+      if (P)
+        hipLaunchKernelGGL((p_half_batch<D, M, S, true>), dim3((unsigned)blocks), block_shape<D>(), 0, s, d, n);
+      else
+        hipLaunchKernelGGL((u_half_batch<D, M, S, true>), dim3((unsigned)blocks), block_shape<D>(), 0, s, d, n);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else {
+    if (P)
+      hipLaunchKernelGGL((p_half_batch<D, M, S, false>), dim3((unsigned)blocks), block_shape<D>(), 0, s, d, n);
+    else
+      hipLaunchKernelGGL((u_half_batch<D, M, S, false>), dim3((unsigned)blocks), block_shape<D>(), 0, s, d, n);
+  }
+  return hipGetLastError();
+}
 template <int D, class S, int M>
 inline bool make_set(KernelSet* out) {
   fill_layout<D, M>(out);
@@ -195,8 +276,11 @@ inline bool make_set(KernelSet* out) {
   }
   out->p_half_var = nullptr;
   out->u_half_var = nullptr;
+  out->batch_desc = &batch_desc<D, M, S>;
+  out->p_batch = &launch_batch<D, M, S, true>;
+  out->u_batch = &launch_batch<D, M, S, false>;
   // variable kappa: FP64 and FP32 storage, d = 1 (all m) and d = 2 (m <= 3)
-  if constexpr (kPlain<S> && (D == 1 || (D == 2 && M <= 3))) {
+  if constexpr (kVarBuilt<D, M, S>) {
     out->p_half_var = &launch_p_var<D, M, S>;
     out->u_half_var = &launch_u_var<D, M, S>;
   }

@@ -105,10 +105,11 @@ __device__ __forceinline__ void pass1d(const T* L, const T* R, T* out) {
   }
 }
 
-// Node of this work-item; false when outside the grid.
+// Node of this work-item in workgroup `blk` of the grid's launch; false when
+// outside the grid.
 template <int D>
-__device__ __forceinline__ bool node_of_thread(const Grid& g, int32_t* j) {
-  const int i = blockIdx.x;
+__device__ __forceinline__ bool node_of_block(const Grid& g, int blk, int32_t* j) {
+  const int i = blk;
   const int t = (i % kXcds) * g.per_xcd + i / kXcds;
   if (t >= g.tiles) return false;
   int tx = t % g.nt[0], ty = 0, tz = 0;
@@ -256,15 +257,15 @@ __device__ __forceinline__ void slice_pair_merge(const typename S::View& f, int 
 // Pressure half-step at every primal node (1D and 2D).
 // tab: packed merged tables (hl_layout.hpp TableLayout), in S::C.
 template <int D, int M, class S>
-__global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_kernel(typename S::View p, typename S::View u,
-                                                                       const typename S::C* __restrict__ tab,
-                                                                       Grid g) {
+__device__ __forceinline__ void p_half_body(typename S::View p, typename S::View u,
+                                            const typename S::C* __restrict__ tab,
+                                            Grid g, int blk) {
   using T = typename S::C;
   using TL = TableLayout<D, M>;
   constexpr int MP = M + 1, NC = Dims<D, M>::NC;
   constexpr int NNZ = merged_nnz<D, M>(false);
   int32_t j[3];
-  if (!node_of_thread<D>(g, j)) return;
+  if (!node_of_block<D>(g, blk, j)) return;
   uint32_t cn[1 << D];
   corner_nodes<D>(g, j, cn);  // dual q = j - 1 + e (p) or primal j = q + e (u)
   T acc[NC];
@@ -280,20 +281,27 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_kernel(typename S
   finish_pressure<D, M, S>(p, out_index<D>(g, j), acc);
 }
 
+template <int D, int M, class S>
+__global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_kernel(typename S::View p, typename S::View u,
+                                                                       const typename S::C* __restrict__ tab,
+                                                                       Grid g) {
+  p_half_body<D, M, S>(p, u, tab, g, blockIdx.x);
+}
+
 // Velocity half-step at every dual node (1D and 2D), weights scaled by wscale.
 template <int D, int M, class S>
-__global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_kernel(typename S::View u, typename S::View p,
-                                                                       const typename S::C* __restrict__ tab,
-                                                                       Grid g, typename S::C wscale,
-                                                                       typename S::C ih0, typename S::C ih1,
-                                                                       typename S::C ih2) {
+__device__ __forceinline__ void u_half_body(typename S::View u, typename S::View p,
+                                            const typename S::C* __restrict__ tab,
+                                            Grid g, typename S::C wscale,
+                                            typename S::C ih0, typename S::C ih1,
+                                            typename S::C ih2, int blk) {
   using T = typename S::C;
   using TL = TableLayout<D, M>;
   constexpr int MP = M + 1;
   constexpr int NG = GSet<D, M>::NG;
   constexpr int NNZ = merged_nnz<D, M>(true);
   int32_t j[3];
-  if (!node_of_thread<D>(g, j)) return;
+  if (!node_of_block<D>(g, blk, j)) return;
   uint32_t cn[1 << D];
   corner_nodes<D>(g, j, cn);  // dual q = j - 1 + e (p) or primal j = q + e (u)
   T Q[NG];
@@ -303,6 +311,15 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_kernel(typename S
   for (int l = 0; l < MP; ++l) slice_pair_merge<D, M, true, 0, 0, S>(p, 0, cn, l, tab + TL::U_OFF + l * NNZ, Q);
   const T ih[3] = {ih0, ih1, ih2};
   finish_velocity<D, M, S>(u, out_index<D>(g, j), Q, wscale, ih);
+}
+
+template <int D, int M, class S>
+__global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_kernel(typename S::View u, typename S::View p,
+                                                                       const typename S::C* __restrict__ tab,
+                                                                       Grid g, typename S::C wscale,
+                                                                       typename S::C ih0, typename S::C ih1,
+                                                                       typename S::C ih2) {
+  u_half_body<D, M, S>(u, p, tab, g, wscale, ih0, ih1, ih2, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -372,14 +389,14 @@ __device__ __forceinline__ void merge3(const T* __restrict__ Mt, int ay, int az,
 }
 
 template <int M, class S>
-__global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_3d(typename S::View p, typename S::View u,
-                                                                   const typename S::C* __restrict__ tab, Grid g) {
+__device__ __forceinline__ void p_half_3d_body(typename S::View p, typename S::View u,
+                                               const typename S::C* __restrict__ tab, Grid g, int blk) {
   using T = typename S::C;
   using TL = TableLayout<3, M>;
   constexpr int MP = M + 1, NC = Dims<3, M>::NC, N2 = 2 * M + 2;
   constexpr int NNZ = Merge3Spec<M, false, 0, 0>::NNZ;
   int32_t j[3];
-  if (!node_of_thread<3>(g, j)) return;
+  if (!node_of_block<3>(g, blk, j)) return;
   uint32_t cn[8];
   corner_nodes<3>(g, j, cn);  // dual q = j - 1 + e (p) or primal j = q + e (u)
   T acc[NC];
@@ -410,17 +427,23 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_3d(typename S::Vi
 }
 
 template <int M, class S>
-__global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_3d(typename S::View u, typename S::View p,
-                                                                   const typename S::C* __restrict__ tab, Grid g,
-                                                                   typename S::C wscale, typename S::C ih0,
-                                                                   typename S::C ih1, typename S::C ih2) {
+__global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_3d(typename S::View p, typename S::View u,
+                                                                   const typename S::C* __restrict__ tab, Grid g) {
+  p_half_3d_body<M, S>(p, u, tab, g, blockIdx.x);
+}
+
+template <int M, class S>
+__device__ __forceinline__ void u_half_3d_body(typename S::View u, typename S::View p,
+                                               const typename S::C* __restrict__ tab, Grid g,
+                                               typename S::C wscale, typename S::C ih0,
+                                               typename S::C ih1, typename S::C ih2, int blk) {
   using T = typename S::C;
   using TL = TableLayout<3, M>;
   constexpr int MP = M + 1, N2 = 2 * M + 2;
   constexpr int NG = GSet<3, M>::NG;
   constexpr int NNZ = Merge3Spec<M, true, 0, 0>::NNZ;
   int32_t j[3];
-  if (!node_of_thread<3>(g, j)) return;
+  if (!node_of_block<3>(g, blk, j)) return;
   uint32_t cn[8];
   corner_nodes<3>(g, j, cn);  // dual q = j - 1 + e (p) or primal j = q + e (u)
   T Q[NG];
@@ -437,6 +460,14 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_3d(typename S::Vi
     }
   const T ih[3] = {ih0, ih1, ih2};
   finish_velocity<3, M, S>(u, out_index<3>(g, j), Q, wscale, ih);
+}
+
+template <int M, class S>
+__global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_3d(typename S::View u, typename S::View p,
+                                                                   const typename S::C* __restrict__ tab, Grid g,
+                                                                   typename S::C wscale, typename S::C ih0,
+                                                                   typename S::C ih1, typename S::C ih2) {
+  u_half_3d_body<M, S>(u, p, tab, g, wscale, ih0, ih1, ih2, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -517,13 +548,13 @@ __global__ void __launch_bounds__(256) ghost_fill(typename S::View u, int32_t E0
 constexpr int kAdjointMaxNC = 27;  // register budget: nc inputs + nc accumulators
 
 template <int D, int M, class S, bool PTYPE>
-__global__ void __launch_bounds__(256) adjoint_half(typename S::View out, typename S::View in,
-                                                    const typename S::C* __restrict__ tab, Grid g) {
+__device__ __forceinline__ void adjoint_half_body(typename S::View out, typename S::View in,
+                                                  const typename S::C* __restrict__ tab, Grid g, int blk) {
   using T = typename S::C;
   constexpr int NC = Dims<D, M>::NC, NO = PTYPE ? 1 : D, NI = PTYPE ? D : 1;
   static_assert(NC <= kAdjointMaxNC, "adjoint kernels are built for nc <= 27");
   int32_t j[3];
-  if (!node_of_thread<D>(g, j)) return;
+  if (!node_of_block<D>(g, blk, j)) return;
   uint32_t cn[1 << D];
   corner_nodes<D>(g, j, cn);
   const uint32_t n0 = out_index<D>(g, j);
@@ -552,6 +583,12 @@ __global__ void __launch_bounds__(256) adjoint_half(typename S::View out, typena
 #pragma unroll
     for (int r = 0; r < NC; ++r) S::update(out, io * NC + r, n0, [&](T x) { return x - acc[r]; });
   }
+}
+
+template <int D, int M, class S, bool PTYPE>
+__global__ void __launch_bounds__(256) adjoint_half(typename S::View out, typename S::View in,
+                                                    const typename S::C* __restrict__ tab, Grid g) {
+  adjoint_half_body<D, M, S, PTYPE>(out, in, tab, g, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -673,12 +710,12 @@ __device__ __forceinline__ void lap_coef(const T* f, T* out, const T* ih, T sc) 
 }
 
 template <int D, int M, class S>
-__global__ void __launch_bounds__(256) p_half_var(typename S::View p, typename S::View u, typename S::View kp,
-                                                  Grid g, VarArgs<typename S::C> va) {
+__device__ __forceinline__ void p_half_var_body(typename S::View p, typename S::View u, typename S::View kp,
+                                                Grid g, VarArgs<typename S::C> va, int blk) {
   using T = typename S::C;
   constexpr int N2 = 2 * M + 2, MP = M + 1, NP = VK<D, M>::NP, NC = Dims<D, M>::NC;
   int32_t j[3];
-  if (!node_of_thread<D>(g, j)) return;
+  if (!node_of_block<D>(g, blk, j)) return;
   uint32_t cn[1 << D];
   corner_nodes<D>(g, j, cn);  // dual q = j - 1 + e
   const uint32_t n0 = out_index<D>(g, j);
@@ -713,12 +750,18 @@ __global__ void __launch_bounds__(256) p_half_var(typename S::View p, typename S
 }
 
 template <int D, int M, class S>
-__global__ void __launch_bounds__(256) u_half_var(typename S::View u, typename S::View p, typename S::View ku,
-                                                  Grid g, VarArgs<typename S::C> va, typename S::C wscale) {
+__global__ void __launch_bounds__(256) p_half_var(typename S::View p, typename S::View u, typename S::View kp,
+                                                  Grid g, VarArgs<typename S::C> va) {
+  p_half_var_body<D, M, S>(p, u, kp, g, va, blockIdx.x);
+}
+
+template <int D, int M, class S>
+__device__ __forceinline__ void u_half_var_body(typename S::View u, typename S::View p, typename S::View ku,
+                                                Grid g, VarArgs<typename S::C> va, typename S::C wscale, int blk) {
   using T = typename S::C;
   constexpr int N2 = 2 * M + 2, MP = M + 1, NP = VK<D, M>::NP, NC = Dims<D, M>::NC;
   int32_t j[3];
-  if (!node_of_thread<D>(g, j)) return;
+  if (!node_of_block<D>(g, blk, j)) return;
   uint32_t cn[1 << D];
   corner_nodes<D>(g, j, cn);  // primal j = q + e
   const uint32_t n0 = out_index<D>(g, j);
@@ -750,6 +793,68 @@ __global__ void __launch_bounds__(256) u_half_var(typename S::View u, typename S
       S::update(u, i * NC + s, n0, [&](T x) { return fma(a, qv, x); });
     }
   }
+}
+
+template <int D, int M, class S>
+__global__ void __launch_bounds__(256) u_half_var(typename S::View u, typename S::View p, typename S::View ku,
+                                                  Grid g, VarArgs<typename S::C> va, typename S::C wscale) {
+  u_half_var_body<D, M, S>(u, p, ku, g, va, wscale, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched shots: one launch per half-step advances many independent problems
+// ("shots": the paper's experiments repeated over sources and grids) of the
+// same (d, m, storage), each with its own grid, time step, coefficient and
+// buffers.  Shot s owns the workgroups [first_block, first_block + 8 per_xcd)
+// of the launch; first_block is a multiple of 8, so every shot keeps its own
+// XCD band mapping.  A workgroup finds its shot by binary search over the
+// descriptor array (uniform, read through the scalar cache).
+// ---------------------------------------------------------------------------
+template <class S>
+struct ShotHalf {
+  typename S::View out, in, kap;   // kap: variable-kappa data (unused for constant kappa)
+  const typename S::C* tab;        // merged tables (constant kappa)
+  Grid g;
+  VarArgs<typename S::C> va;       // variable kappa
+  typename S::C wscale, ih[3];     // velocity half-step
+  int32_t first_block, pad;
+};
+
+template <class S>
+__device__ __forceinline__ int shot_of(const ShotHalf<S>* __restrict__ sh, int n, int blk) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (sh[mid].first_block <= blk)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int D, int M, class S, bool VAR>
+__global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_batch(const ShotHalf<S>* __restrict__ shots, int n) {
+  const ShotHalf<S>& sh = shots[shot_of(shots, n, blockIdx.x)];
+  const int blk = (int)blockIdx.x - sh.first_block;
+  if constexpr (VAR)
+    p_half_var_body<D, M, S>(sh.out, sh.in, sh.kap, sh.g, sh.va, blk);
+  else if constexpr (D == 3)
+    p_half_3d_body<M, S>(sh.out, sh.in, sh.tab, sh.g, blk);
+  else
+    p_half_body<D, M, S>(sh.out, sh.in, sh.tab, sh.g, blk);
+}
+
+template <int D, int M, class S, bool VAR>
+__global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_batch(const ShotHalf<S>* __restrict__ shots, int n) {
+  const ShotHalf<S>& sh = shots[shot_of(shots, n, blockIdx.x)];
+  const int blk = (int)blockIdx.x - sh.first_block;
+  if constexpr (VAR)
+    u_half_var_body<D, M, S>(sh.out, sh.in, sh.kap, sh.g, sh.va, sh.wscale, blk);
+  else if constexpr (D == 3)
+    u_half_3d_body<M, S>(sh.out, sh.in, sh.tab, sh.g, sh.wscale, sh.ih[0], sh.ih[1], sh.ih[2], blk);
+  else
+    u_half_body<D, M, S>(sh.out, sh.in, sh.tab, sh.g, sh.wscale, sh.ih[0], sh.ih[1], sh.ih[2], blk);
 }
 
 }  // namespace hl

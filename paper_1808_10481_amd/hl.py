@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "HL_OK", 1: "HL_ERR_ARG", 2: "HL_ERR_CFL", 3: "HL_ERR_UNSUPPO
 
 # Every symbol include/hl.h declares.
 EXPORTS = ("hl_plan", "hl_plan_destroy", "hl_plan_info", "hl_init", "hl_export", "hl_step",
-           "hl_p_half", "hl_u_half", "hl_set_kappa", "hl_norms", "hl_adjoint_step", "hl_last_error")
+           "hl_p_half", "hl_u_half", "hl_set_kappa", "hl_norms", "hl_adjoint_step", "hl_batch_create",
+           "hl_batch_step", "hl_batch_destroy", "hl_last_error")
 
 
 class HLProblem(ctypes.Structure):
@@ -67,6 +68,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hl_u_half": ([vp, vp, vp, dbl, vp]),
         "hl_norms": ([vp, vp, vp, ctypes.POINTER(dbl)]),
         "hl_set_kappa": ([vp, vp, vp]),
+        "hl_batch_create": ([ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp)]),
+        "hl_batch_step": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i64, vp]),
+        "hl_batch_destroy": ([vp]),
         "hl_adjoint_step": ([vp, vp, vp, vp, vp, vp, i64, vp]),
     }
     for name, args in sig.items():
@@ -259,3 +263,35 @@ class Plan:
             raise ValueError("state buffers are smaller than the plan's state")
         if not (p.is_contiguous() and u.is_contiguous()):
             raise ValueError("state buffers must be contiguous")
+
+
+class Batch:
+    """Shots (Plans of the same d, m, precision) advanced together, one launch
+    per half-step (hl_batch_*).  Keeps the plans alive."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().hl_batch_create(arr, len(self.plans), ctypes.byref(h)))
+        self._h = h
+
+    def step(self, ps, us, nsteps=1, stream=None):
+        if len(ps) != len(self.plans) or len(us) != len(self.plans):
+            raise ValueError("one (p, u) pair per plan")
+        for plan, p, u in zip(self.plans, ps, us):
+            plan._check_buf(p, u)
+        pa = (ctypes.c_void_p * len(ps))(*[p.data_ptr() for p in ps])
+        ua = (ctypes.c_void_p * len(us))(*[u.data_ptr() for u in us])
+        _check(lib().hl_batch_step(self._h, pa, ua, int(nsteps), _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hl_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
