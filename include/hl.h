@@ -137,6 +137,8 @@ hl_status hl_plan_info(hl_plan_t plan, hl_info* out);
 /* Convert host FP64 data (host layout) to the device layout and precision,
  * writing device buffers p (p_words) and u (u_words).  p0 must be non-NULL;
  * u0 == NULL means zero velocity.
+ * u may be NULL (with u0 NULL and no start-up) to write p alone, e.g. the
+ * data of a source for hl_add_source.
  * flags == 0:               u0 holds u at t0 + dt/2 (Sec. 2: staggered data).
  * flags & HL_INIT_STARTUP:  u0 holds u at t0; u at t0 + dt/2 is built on the
  *                           device from the odd Taylor terms over dt/2
@@ -171,6 +173,16 @@ hl_status hl_p_half(hl_plan_t plan, void* p, void* u, void* stream);
 /* One velocity half-step U <- U - s * sum_k w_k kappa^k grad Lap^k I(P),
  * s = weight_scale (1 for the scheme, 0.5 for the start-up).  Asynchronous. */
 hl_status hl_u_half(hl_plan_t plan, void* u, const void* p, double weight_scale, void* stream);
+
+/* Source term z(x, t) = r(t) g(x) of the pressure equation p_t = -kappa div u + z
+ * (Sec. 4, eq. (waveEq1D) forcing): p += a g over every coefficient of p, with
+ * g a device buffer in the p layout (written by hl_init with u = NULL from the
+ * scaled Taylor data of g).  The paper does not say how z enters the step;
+ * the reading taken is the midpoint rule over the step: after the pressure
+ * half-step from t_n, add a = dt r(t_n + dt/2), then run the velocity
+ * half-step (second order in time for the source contribution).
+ * Asynchronous. */
+hl_status hl_add_source(hl_plan_t plan, void* p, const void* g, double a, void* stream);
 
 /* Variable coefficient (Sec. 4, "Smoothly varying wave speed"): kappa(x)
  * given per node as its Taylor polynomial of degree 2m+1 per variable, scaled

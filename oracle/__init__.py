@@ -40,6 +40,7 @@ from .hermite_lf import (  # noqa: F401
     p_half_var,
     u_half_var,
     step_var,
+    step_with_source,
     p_half_adjoint,
     u_half_adjoint,
     p_operator_blocks,

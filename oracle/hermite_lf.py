@@ -69,7 +69,7 @@ __all__ = [
     "step", "startup", "p_update_cells", "u_update_cells", "ghost_pad", "mirror_sign",
     "p_operator_blocks", "u_operator_blocks", "p_half_adjoint", "u_half_adjoint", "adjoint_step",
     "kappa_gradient", "kmax_var", "p_update_cells_var", "u_update_cells_var", "p_half_var", "u_half_var",
-    "step_var",
+    "step_var", "step_with_source",
 ]
 
 _CHUNK = 1 << 14  # nodes per vectorised batch (bounds memory, not arithmetic)
@@ -615,4 +615,25 @@ def step_var(prob: Problem, P, U, Kp, Ku, nsteps: int = 1):
     for _ in range(int(nsteps)):
         P = p_half_var(prob, P, U, Kp)
         U = u_half_var(prob, U, P, Ku)
+    return P, U
+
+
+# ---------------------------------------------------------------------------
+# Source term (periodic or walls)
+# ---------------------------------------------------------------------------
+# p_t = -kappa div u + z(x, t) with z = r(t) g(x) (Sec. 4, eq. (waveEq1D)
+# forcing).  The paper does not say how z enters the step.  Reading taken:
+# the midpoint rule over the step, P^{n+1} = [pressure half-step] + dt r(t_n +
+# dt/2) G, before the velocity half-step (G: scaled Taylor data of g at the
+# primal nodes).
+
+def step_with_source(prob: Problem, P, U, G, r, t0: float, nsteps: int, Kp=None, Ku=None):
+    """nsteps steps from time t0 with the source r(t) G (r a callable);
+    variable kappa when Kp, Ku are given (periodic)."""
+    P = np.array(P, dtype=np.float64, copy=True)
+    U = np.array(U, dtype=np.float64, copy=True)
+    for n in range(int(nsteps)):
+        P = p_half(prob, P, U) if Kp is None else p_half_var(prob, P, U, Kp)
+        P = P + prob.dt * r(t0 + (n + 0.5) * prob.dt) * G
+        U = u_half(prob, U, P) if Ku is None else u_half_var(prob, U, P, Ku)
     return P, U

@@ -693,6 +693,18 @@ hipError_t dot_into(const hl_plan_s* pl, const void* a, const void* b, int field
   return hipGetLastError();
 }
 
+// p += a g over every stored coefficient of a p-shaped buffer.
+template <class S>
+__global__ void axpy_kernel(typename S::View p, typename S::View g, int planes, double a) {
+  using T = typename S::C;
+  const T at = (T)a;
+  for (int pl = 0; pl < planes; ++pl)
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < p.nodes; n += (int64_t)gridDim.x * blockDim.x) {
+      const T gv = S::load(g, pl, (uint32_t)n);
+      S::update(p, pl, (uint32_t)n, [&](T x) { return fma(at, gv, x); });
+    }
+}
+
 hipError_t upload_table(const hl_plan_s* pl, const std::vector<double>& tab, void** out) {
   const size_t bytes = std::max<size_t>(tab.size() * pl->tab_bytes, 16);
   hipError_t e = hipMalloc(out, bytes);
@@ -942,11 +954,13 @@ hl_status hl_init(hl_plan_t plan, const double* p0, const double* u0, uint32_t f
   g_last_error.clear();
   hl_status st = check_plan(plan, "hl_init");
   if (st != HL_OK) return st;
-  if (!p0 || !p || !u) return fail(HL_ERR_ARG, "hl_init: p0, p and u must be non-NULL");
+  if (!p0 || !p) return fail(HL_ERR_ARG, "hl_init: p0 and p must be non-NULL");
   if (flags & ~HL_INIT_STARTUP) return fail(HL_ERR_ARG, "hl_init: unknown flags");
+  if (!u && (u0 || (flags & HL_INIT_STARTUP)))
+    return fail(HL_ERR_ARG, "hl_init: u may be NULL only without u0 and without the start-up");
   hipStream_t s = (hipStream_t)stream;
   if ((st = upload_field(plan, p0, 0, p, s)) != HL_OK) return st;
-  if ((st = upload_field(plan, u0, 1, u, s)) != HL_OK) return st;
+  if (u && (st = upload_field(plan, u0, 1, u, s)) != HL_OK) return st;
   if (flags & HL_INIT_STARTUP) {
     hipError_t e = u_fn(plan)(view(plan), u, p, 0.5, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1015,6 +1029,39 @@ hl_status hl_step(hl_plan_t plan, void* p, void* u, int64_t nsteps, void* stream
     if (e != hipSuccess) return hip_fail(e, "hl_step: launch");
   }
   return HL_OK;
+}
+
+hl_status hl_add_source(hl_plan_t plan, void* p, const void* g, double a, void* stream) {
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_add_source");
+  if (st != HL_OK) return st;
+  if (!p || !g || p == g) return fail(HL_ERR_ARG, "hl_add_source: p and g must be distinct non-NULL buffers");
+  if (!std::isfinite(a)) return fail(HL_ERR_ARG, "hl_add_source: a must be finite");
+  hipStream_t s = (hipStream_t)stream;
+  const int planes = plan->nc;
+  const int64_t nodes = plan->pnodes;
+  const unsigned blocks = (unsigned)std::min<int64_t>(2048, (nodes + 255) / 256);
+  switch (plan->precision) {
+    case HL_FP64: {
+      using S = hl::PlainStore<double>;
+      hipLaunchKernelGGL(axpy_kernel<S>, dim3(blocks), dim3(256), 0, s, S::make(p, 1, planes, nodes),
+                         S::make(g, 1, planes, nodes), planes, a);
+      break;
+    }
+    case HL_FP32: {
+      using S = hl::PlainStore<float>;
+      hipLaunchKernelGGL(axpy_kernel<S>, dim3(blocks), dim3(256), 0, s, S::make(p, 1, planes, nodes),
+                         S::make(g, 1, planes, nodes), planes, a);
+      break;
+    }
+    default: {
+      using S = hl::SplitStore;
+      hipLaunchKernelGGL(axpy_kernel<S>, dim3(blocks), dim3(256), 0, s, S::make(p, 1, planes, nodes),
+                         S::make(g, 1, planes, nodes), planes, a);
+    }
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? HL_OK : hip_fail(e, "hl_add_source: launch");
 }
 
 hl_status hl_set_kappa(hl_plan_t plan, const double* kappa_p, const double* kappa_u) {

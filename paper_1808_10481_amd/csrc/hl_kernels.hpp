@@ -37,6 +37,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "hl_layout.hpp"
 #include "hl_storage.hpp"
 
@@ -220,8 +222,8 @@ __device__ __forceinline__ void slice(const typename S::View& f, int comp, const
 // acc[o] += sum_b Mt[t] * (sigma or delta)[b] over the structurally nonzero
 // (o, b) of one merged table row-block (datum l); the walk comes from the
 // compile-time MergeSpec, so every index is a constant after unrolling.
-template <int D, int M, bool VEL, int FLIPL, typename T>
-__device__ __forceinline__ void merge(const T* __restrict__ Mt, int l, const T* Sg, const T* Df, T* acc) {
+template <int D, int M, bool VEL, int FLIPL, typename T, typename TP>
+__device__ __forceinline__ void merge(TP Mt, int l, const T* Sg, const T* Df, T* acc) {
   using Sp = MergeSpec<D, M, VEL, FLIPL>;
   // Scalar table loads are consumed in chunks: without the barriers the
   // scheduler hoists every s_load of the table to the top of the kernel and
@@ -238,9 +240,9 @@ __device__ __forceinline__ void merge(const T* __restrict__ Mt, int l, const T* 
 }
 
 // Sigma/delta of the two last-dimension slices, then the merged table.
-template <int D, int M, bool VEL, int FLIP0, int FLIPL, class S>
-__device__ __forceinline__ void slice_pair_merge(const typename S::View& f, int comp, const uint32_t* cn, int l,
-                                                 const typename S::C* __restrict__ Mt, typename S::C* acc) {
+template <int D, int M, bool VEL, int FLIP0, int FLIPL, class S, typename TP>
+__device__ __forceinline__ void slice_pair_merge(const typename S::View& f, int comp, const uint32_t* cn, int l, TP Mt,
+                                                 typename S::C* acc) {
   using T = typename S::C;
   constexpr int NB = Dims<D, M>::NB;
   T YL[NB], YR[NB], Sg[NB], Df[NB];
@@ -256,9 +258,9 @@ __device__ __forceinline__ void slice_pair_merge(const typename S::View& f, int 
 
 // Pressure half-step at every primal node (1D and 2D).
 // tab: packed merged tables (hl_layout.hpp TableLayout), in S::C.
-template <int D, int M, class S>
+template <int D, int M, class S, typename TP>
 __device__ __forceinline__ void p_half_body(typename S::View p, typename S::View u,
-                                            const typename S::C* __restrict__ tab,
+                                            TP tab,
                                             Grid g, int blk) {
   using T = typename S::C;
   using TL = TableLayout<D, M>;
@@ -285,13 +287,13 @@ template <int D, int M, class S>
 __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_kernel(typename S::View p, typename S::View u,
                                                                        const typename S::C* __restrict__ tab,
                                                                        Grid g) {
-  p_half_body<D, M, S>(p, u, tab, g, blockIdx.x);
+  p_half_body<D, M, S, const typename S::C* __restrict__>(p, u, tab, g, blockIdx.x);
 }
 
 // Velocity half-step at every dual node (1D and 2D), weights scaled by wscale.
-template <int D, int M, class S>
+template <int D, int M, class S, typename TP>
 __device__ __forceinline__ void u_half_body(typename S::View u, typename S::View p,
-                                            const typename S::C* __restrict__ tab,
+                                            TP tab,
                                             Grid g, typename S::C wscale,
                                             typename S::C ih0, typename S::C ih1,
                                             typename S::C ih2, int blk) {
@@ -319,7 +321,7 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_kernel(typename S
                                                                        Grid g, typename S::C wscale,
                                                                        typename S::C ih0, typename S::C ih1,
                                                                        typename S::C ih2) {
-  u_half_body<D, M, S>(u, p, tab, g, wscale, ih0, ih1, ih2, blockIdx.x);
+  u_half_body<D, M, S, const typename S::C* __restrict__>(u, p, tab, g, wscale, ih0, ih1, ih2, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -372,9 +374,8 @@ __device__ __forceinline__ void xlines(const typename S::View& f, int pl0, const
   }
 }
 
-template <int M, bool VEL, int FY, int FZ, typename T>
-__device__ __forceinline__ void merge3(const T* __restrict__ Mt, int ay, int az, const T (&X)[2][2][2 * M + 2],
-                                       T* acc) {
+template <int M, bool VEL, int FY, int FZ, typename T, typename TP>
+__device__ __forceinline__ void merge3(TP Mt, int ay, int az, const T (&X)[2][2][2 * M + 2], T* acc) {
   constexpr int NNZ = Merge3Spec<M, VEL, FY, FZ>::NNZ;
   constexpr int kChunk = sizeof(T) == 8 ? 16 : 32;
 #pragma unroll
@@ -388,9 +389,9 @@ __device__ __forceinline__ void merge3(const T* __restrict__ Mt, int ay, int az,
   }
 }
 
-template <int M, class S>
+template <int M, class S, typename TP>
 __device__ __forceinline__ void p_half_3d_body(typename S::View p, typename S::View u,
-                                               const typename S::C* __restrict__ tab, Grid g, int blk) {
+                                               TP tab, Grid g, int blk) {
   using T = typename S::C;
   using TL = TableLayout<3, M>;
   constexpr int MP = M + 1, NC = Dims<3, M>::NC, N2 = 2 * M + 2;
@@ -429,12 +430,12 @@ __device__ __forceinline__ void p_half_3d_body(typename S::View p, typename S::V
 template <int M, class S>
 __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_3d(typename S::View p, typename S::View u,
                                                                    const typename S::C* __restrict__ tab, Grid g) {
-  p_half_3d_body<M, S>(p, u, tab, g, blockIdx.x);
+  p_half_3d_body<M, S, const typename S::C* __restrict__>(p, u, tab, g, blockIdx.x);
 }
 
-template <int M, class S>
+template <int M, class S, typename TP>
 __device__ __forceinline__ void u_half_3d_body(typename S::View u, typename S::View p,
-                                               const typename S::C* __restrict__ tab, Grid g,
+                                               TP tab, Grid g,
                                                typename S::C wscale, typename S::C ih0,
                                                typename S::C ih1, typename S::C ih2, int blk) {
   using T = typename S::C;
@@ -467,7 +468,7 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_3d(typename S::Vi
                                                                    const typename S::C* __restrict__ tab, Grid g,
                                                                    typename S::C wscale, typename S::C ih0,
                                                                    typename S::C ih1, typename S::C ih2) {
-  u_half_3d_body<M, S>(u, p, tab, g, wscale, ih0, ih1, ih2, blockIdx.x);
+  u_half_3d_body<M, S, const typename S::C* __restrict__>(u, p, tab, g, wscale, ih0, ih1, ih2, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -673,25 +674,37 @@ __device__ __forceinline__ void interp_full(const typename S::View& f, int comp,
   }
 }
 
+// out += kappa_A f shifted by A (one term of the truncated product; A is a
+// template argument so that every register index is a compile-time constant:
+// as one 64 x 64 loop nest the compiler stopped unrolling and indexed f
+// through scratch memory).
+template <int D, int M, int A, class S>
+__device__ __forceinline__ void tprod_term(const typename S::View& kv, uint32_t n0, const typename S::C* f,
+                                           typename S::C* out) {
+  constexpr int N2 = 2 * M + 2, AX = A % N2, AY = A / N2, NY = D > 1 ? N2 : 1;
+  const typename S::C ka = S::load(kv, A, n0);
+#pragma unroll
+  for (int by = AY; by < NY; ++by)
+#pragma unroll
+    for (int bx = AX; bx < N2; ++bx) out[bx + N2 * by] = fma(ka, f[(bx - AX) + N2 * (by - AY)], out[bx + N2 * by]);
+}
+
+template <int D, int M, class S, int... A>
+__device__ __forceinline__ void tprod_terms(const typename S::View& kv, uint32_t n0, const typename S::C* f,
+                                            typename S::C* out, std::integer_sequence<int, A...>) {
+  (tprod_term<D, M, A, S>(kv, n0, f, out), ...);
+}
+
 // out = T[kappa f]: out_b = sum_{a <= b} kappa_a f_{b-a} (per variable),
 // kappa_a read from plane a of the kappa array at node n0.
 template <int D, int M, class S>
 __device__ __forceinline__ void tprod(const typename S::View& kv, uint32_t n0, const typename S::C* f,
                                       typename S::C* out) {
   using T = typename S::C;
-  constexpr int N2 = 2 * M + 2, NP = VK<D, M>::NP;
+  constexpr int NP = VK<D, M>::NP;
 #pragma unroll
   for (int b = 0; b < NP; ++b) out[b] = T(0);
-#pragma unroll
-  for (int a = 0; a < NP; ++a) {
-    const T ka = S::load(kv, a, n0);
-    const int ax = a % N2, ay = a / N2;
-#pragma unroll
-    for (int b = 0; b < NP; ++b) {
-      const int bx = b % N2, by = b / N2;
-      if (bx >= ax && by >= ay) out[b] = fma(ka, f[(bx - ax) + N2 * (by - ay)], out[b]);
-    }
-  }
+  tprod_terms<D, M, S>(kv, n0, f, out, std::make_integer_sequence<int, NP>{});
 }
 
 // out = sc Lap f in coefficient space: sc sum_i (b_i + 1)(b_i + 2) / h_i^2 f_{b + 2 e_i}.
@@ -820,41 +833,69 @@ struct ShotHalf {
   int32_t first_block, pad;
 };
 
+// A table pointer read from memory, recast to the constant address space so
+// that uniform table reads become scalar loads (a pointer loaded from memory
+// is generic, and generic loads are per-lane flat loads).
+template <typename T>
+using ConstPtr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ ConstPtr<T> const_ptr(const T* p) {
+  return (ConstPtr<T>)(uintptr_t)p;
+}
+
 template <class S>
 __device__ __forceinline__ int shot_of(const ShotHalf<S>* __restrict__ sh, int n, int blk) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) / 2;
-    if (sh[mid].first_block <= blk)
+    if (__builtin_amdgcn_readfirstlane(sh[mid].first_block) <= blk)
       lo = mid;
     else
       hi = mid - 1;
   }
-  return lo;
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// The descriptor of this workgroup's shot, every word passed through
+// readfirstlane: the values are uniform, and saying so keeps pointers, grid
+// and table addresses in scalar registers (otherwise the merged tables are
+// read with vector loads, as in a kernel whose table pointer may vary by lane).
+template <class S>
+__device__ __forceinline__ ShotHalf<S> shot_desc(const ShotHalf<S>* __restrict__ shots, int s) {
+  static_assert(sizeof(ShotHalf<S>) % 4 == 0, "descriptor must be whole words");
+  ShotHalf<S> d;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(shots + s);
+  uint32_t w[sizeof(ShotHalf<S>) / 4];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(ShotHalf<S>) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  __builtin_memcpy(&d, w, sizeof d);
+  return d;
 }
 
 template <int D, int M, class S, bool VAR>
 __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_batch(const ShotHalf<S>* __restrict__ shots, int n) {
-  const ShotHalf<S>& sh = shots[shot_of(shots, n, blockIdx.x)];
+  const ShotHalf<S> sh = shot_desc(shots, shot_of(shots, n, blockIdx.x));
   const int blk = (int)blockIdx.x - sh.first_block;
+  const ConstPtr<typename S::C> tab = const_ptr(sh.tab);
   if constexpr (VAR)
     p_half_var_body<D, M, S>(sh.out, sh.in, sh.kap, sh.g, sh.va, blk);
   else if constexpr (D == 3)
-    p_half_3d_body<M, S>(sh.out, sh.in, sh.tab, sh.g, blk);
+    p_half_3d_body<M, S>(sh.out, sh.in, tab, sh.g, blk);
   else
-    p_half_body<D, M, S>(sh.out, sh.in, sh.tab, sh.g, blk);
+    p_half_body<D, M, S>(sh.out, sh.in, tab, sh.g, blk);
 }
 
 template <int D, int M, class S, bool VAR>
 __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_batch(const ShotHalf<S>* __restrict__ shots, int n) {
-  const ShotHalf<S>& sh = shots[shot_of(shots, n, blockIdx.x)];
+  const ShotHalf<S> sh = shot_desc(shots, shot_of(shots, n, blockIdx.x));
   const int blk = (int)blockIdx.x - sh.first_block;
+  const ConstPtr<typename S::C> tab = const_ptr(sh.tab);
   if constexpr (VAR)
     u_half_var_body<D, M, S>(sh.out, sh.in, sh.kap, sh.g, sh.va, sh.wscale, blk);
   else if constexpr (D == 3)
-    u_half_3d_body<M, S>(sh.out, sh.in, sh.tab, sh.g, sh.wscale, sh.ih[0], sh.ih[1], sh.ih[2], blk);
+    u_half_3d_body<M, S>(sh.out, sh.in, tab, sh.g, sh.wscale, sh.ih[0], sh.ih[1], sh.ih[2], blk);
   else
-    u_half_body<D, M, S>(sh.out, sh.in, sh.tab, sh.g, sh.wscale, sh.ih[0], sh.ih[1], sh.ih[2], blk);
+    u_half_body<D, M, S>(sh.out, sh.in, tab, sh.g, sh.wscale, sh.ih[0], sh.ih[1], sh.ih[2], blk);
 }
 
 }  // namespace hl

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "HL_OK", 1: "HL_ERR_ARG", 2: "HL_ERR_CFL", 3: "HL_ERR_UNSUPPO
 
 # Every symbol include/hl.h declares.
 EXPORTS = ("hl_plan", "hl_plan_destroy", "hl_plan_info", "hl_init", "hl_export", "hl_step",
-           "hl_p_half", "hl_u_half", "hl_set_kappa", "hl_norms", "hl_adjoint_step", "hl_batch_create",
+           "hl_p_half", "hl_u_half", "hl_add_source", "hl_set_kappa", "hl_norms", "hl_adjoint_step", "hl_batch_create",
            "hl_batch_step", "hl_batch_destroy", "hl_last_error")
 
 
@@ -68,6 +68,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hl_u_half": ([vp, vp, vp, dbl, vp]),
         "hl_norms": ([vp, vp, vp, ctypes.POINTER(dbl)]),
         "hl_set_kappa": ([vp, vp, vp]),
+        "hl_add_source": ([vp, vp, vp, dbl, vp]),
         "hl_batch_create": ([ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp)]),
         "hl_batch_step": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i64, vp]),
         "hl_batch_destroy": ([vp]),
@@ -233,6 +234,27 @@ class Plan:
             gg = ctypes.c_void_p(grad_kappa.data_ptr())
         _check(lib().hl_adjoint_step(self._h, ctypes.c_void_p(p_bar.data_ptr()), ctypes.c_void_p(u_bar.data_ptr()),
                                      pp, uu, gg, int(nsteps), _stream_ptr(stream)))
+
+    def source_buffer(self, g, stream=None):
+        """Device buffer (p layout) holding the scaled data g (host layout of p)."""
+        import torch
+        ps, _ = self.host_shapes()
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        assert g.shape == ps, (g.shape, ps)
+        buf = torch.empty(self.info.p_words, dtype=self.torch_dtype(), device="cuda")
+        _check(lib().hl_init(self._h, g.ctypes.data_as(ctypes.c_void_p), None, 0, ctypes.c_void_p(buf.data_ptr()),
+                             None, _stream_ptr(stream)))
+        return buf
+
+    def add_source(self, p, g, a, stream=None):
+        """p += a g (hl_add_source): the source's contribution to one step is
+        a = dt r(t_n + dt/2), added after the pressure half-step."""
+        if not (p.is_cuda and g.is_cuda) or p.dtype != self.torch_dtype() or g.dtype != p.dtype:
+            raise ValueError("p and g must be device buffers of the plan's storage type")
+        if p.numel() < self.info.p_words or g.numel() < self.info.p_words:
+            raise ValueError("buffers are smaller than the plan's pressure state")
+        _check(lib().hl_add_source(self._h, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                   float(a), _stream_ptr(stream)))
 
     def set_kappa(self, kappa_p=None, kappa_u=None):
         """Variable kappa: FP64 Taylor data (K,)*d + (2m+2,)*d about the primal
