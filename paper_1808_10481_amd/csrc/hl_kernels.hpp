@@ -877,12 +877,14 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_batch(const ShotH
   const ShotHalf<S> sh = shot_desc(shots, shot_of(shots, n, blockIdx.x));
   const int blk = (int)blockIdx.x - sh.first_block;
   const ConstPtr<typename S::C> tab = const_ptr(sh.tab);
+  using G = typename S::Global;
+  const typename G::View out = S::global(sh.out), in = S::global(sh.in), kap = S::global(sh.kap);
   if constexpr (VAR)
-    p_half_var_body<D, M, S>(sh.out, sh.in, sh.kap, sh.g, sh.va, blk);
+    p_half_var_body<D, M, G>(out, in, kap, sh.g, sh.va, blk);
   else if constexpr (D == 3)
-    p_half_3d_body<M, S>(sh.out, sh.in, tab, sh.g, blk);
+    p_half_3d_body<M, G>(out, in, tab, sh.g, blk);
   else
-    p_half_body<D, M, S>(sh.out, sh.in, tab, sh.g, blk);
+    p_half_body<D, M, G>(out, in, tab, sh.g, blk);
 }
 
 template <int D, int M, class S, bool VAR>
@@ -890,12 +892,14 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_batch(const ShotH
   const ShotHalf<S> sh = shot_desc(shots, shot_of(shots, n, blockIdx.x));
   const int blk = (int)blockIdx.x - sh.first_block;
   const ConstPtr<typename S::C> tab = const_ptr(sh.tab);
+  using G = typename S::Global;
+  const typename G::View out = S::global(sh.out), in = S::global(sh.in), kap = S::global(sh.kap);
   if constexpr (VAR)
-    u_half_var_body<D, M, S>(sh.out, sh.in, sh.kap, sh.g, sh.va, sh.wscale, blk);
+    u_half_var_body<D, M, G>(out, in, kap, sh.g, sh.va, sh.wscale, blk);
   else if constexpr (D == 3)
-    u_half_3d_body<M, S>(sh.out, sh.in, tab, sh.g, sh.wscale, sh.ih[0], sh.ih[1], sh.ih[2], blk);
+    u_half_3d_body<M, G>(out, in, tab, sh.g, sh.wscale, sh.ih[0], sh.ih[1], sh.ih[2], blk);
   else
-    u_half_body<D, M, S>(sh.out, sh.in, tab, sh.g, sh.wscale, sh.ih[0], sh.ih[1], sh.ih[2], blk);
+    u_half_body<D, M, G>(out, in, tab, sh.g, sh.wscale, sh.ih[0], sh.ih[1], sh.ih[2], blk);
 }
 
 }  // namespace hl

@@ -21,40 +21,61 @@
 
 namespace hl {
 
+// Pointer to T in address space AS: 0 = generic (flat), 1 = global.  Kernel
+// arguments are known to be global; a pointer read from memory (the batched
+// shots' descriptors) is generic unless recast, and generic loads are flat
+// loads with a 64-bit address per lane.
+template <typename T, int AS>
+struct AsPtr {
+  using type = T*;
+};
+template <typename T>
+struct AsPtr<T, 1> {
+  using type = __attribute__((address_space(1))) T*;
+};
+
 // Raw buffer descriptor over `bytes` bytes at `base` (gfx9 word 3: 32-bit
 // untyped data); loads at offsets past the end return zero.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-template <typename W>
+template <typename W, int AS = 0>
 struct PlainStore {
   using C = W;
   static constexpr int kBytes = (int)sizeof(W);
+  using WP = typename AsPtr<W, AS>::type;
+  using CP = typename AsPtr<char, AS>::type;
   struct View {
-    W* base;
+    WP base;
     int64_t nodes;
   };
+  // The same storage addressed through global pointers (batched shots).
+  using Global = PlainStore<W, 1>;
+  template <int A = 1>  // (a template, so that PlainStore<W, 1> is not needed inside itself)
+  __device__ static __forceinline__ typename PlainStore<W, A>::View global(const View& v) {
+    return typename PlainStore<W, A>::View{(typename PlainStore<W, A>::WP)(uintptr_t)v.base, v.nodes};
+  }
   // View of a buffer of ncomp fields of nc planes.
   __host__ static View make(const void* ptr, int ncomp, int nc, int64_t nodes) {
     (void)ncomp, (void)nc;
     return View{static_cast<W*>(const_cast<void*>(ptr)), nodes};
   }
-  __device__ static __forceinline__ char* plane(const View& v, int pl) {
-    return reinterpret_cast<char*>(v.base + (int64_t)pl * v.nodes);
+  __device__ static __forceinline__ CP plane(const View& v, int pl) {
+    return reinterpret_cast<CP>(v.base + (int64_t)pl * v.nodes);
   }
   // Uniform plane base plus a 32-bit per-lane byte offset (planes < 4 GiB).
   __device__ static __forceinline__ C load(const View& v, int pl, uint32_t node) {
-    return *reinterpret_cast<const W*>(plane(v, pl) + node * (uint32_t)sizeof(W));
+    return *reinterpret_cast<WP>(plane(v, pl) + node * (uint32_t)sizeof(W));
   }
   // entry <- f(entry)
   template <class F>
   __device__ static __forceinline__ void update(const View& v, int pl, uint32_t node, F f) {
-    W* q = reinterpret_cast<W*>(plane(v, pl) + node * (uint32_t)sizeof(W));
+    WP q = reinterpret_cast<WP>(plane(v, pl) + node * (uint32_t)sizeof(W));
     *q = f(*q);
   }
   __device__ static __forceinline__ void store(const View& v, int pl, uint32_t node, C x) {
-    *reinterpret_cast<W*>(plane(v, pl) + node * (uint32_t)sizeof(W)) = x;
+    *reinterpret_cast<WP>(plane(v, pl) + node * (uint32_t)sizeof(W)) = x;
   }
 
   // Buffer-descriptor loads (3D kernels): one descriptor per plane.
@@ -62,7 +83,7 @@ struct PlainStore {
     __amdgpu_buffer_rsrc_t r;
   };
   __device__ static __forceinline__ Planes planes(const View& v, int pl) {
-    return Planes{raw_rsrc(plane(v, pl), (uint32_t)(v.nodes * (int64_t)sizeof(W)))};
+    return Planes{raw_rsrc((const void*)(uintptr_t)plane(v, pl), (uint32_t)(v.nodes * (int64_t)sizeof(W)))};
   }
   __device__ static __forceinline__ C bload(const Planes& p, uint32_t node) {
     const uint32_t off = node * (uint32_t)sizeof(W);
@@ -73,14 +94,24 @@ struct PlainStore {
   }
 };
 
-struct SplitStore {
+template <int AS = 0>
+struct SplitStoreT {
   using C = double;
   static constexpr int kBytes = 6;
+  using FP = typename AsPtr<float, AS>::type;
+  using HP = typename AsPtr<uint16_t, AS>::type;
+  using CP = typename AsPtr<char, AS>::type;
   struct View {
-    float* hi;     // hi planes
-    uint16_t* lo;  // lo planes (BF16 bit patterns), same plane numbering
+    FP hi;  // hi planes
+    HP lo;  // lo planes (BF16 bit patterns), same plane numbering
     int64_t nodes;
   };
+  using Global = SplitStoreT<1>;
+  template <int A = 1>
+  __device__ static __forceinline__ typename SplitStoreT<A>::View global(const View& v) {
+    return typename SplitStoreT<A>::View{(typename SplitStoreT<A>::FP)(uintptr_t)v.hi,
+                                         (typename SplitStoreT<A>::HP)(uintptr_t)v.lo, v.nodes};
+  }
   __host__ static View make(const void* ptr, int ncomp, int nc, int64_t nodes) {
     float* hi = static_cast<float*>(const_cast<void*>(ptr));
     return View{hi, reinterpret_cast<uint16_t*>(hi + (int64_t)ncomp * nc * nodes), nodes};
@@ -94,20 +125,17 @@ struct SplitStore {
     b += 0x7fffu + ((b >> 16) & 1u);
     return (uint16_t)(b >> 16);
   }
-  __device__ static __forceinline__ float* hi_plane(const View& v, int pl) { return v.hi + (int64_t)pl * v.nodes; }
-  __device__ static __forceinline__ uint16_t* lo_plane(const View& v, int pl) {
-    return v.lo + (int64_t)pl * v.nodes;
-  }
+  __device__ static __forceinline__ FP hi_plane(const View& v, int pl) { return v.hi + (int64_t)pl * v.nodes; }
+  __device__ static __forceinline__ HP lo_plane(const View& v, int pl) { return v.lo + (int64_t)pl * v.nodes; }
   __device__ static __forceinline__ C load(const View& v, int pl, uint32_t node) {
-    const float hi = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(hi_plane(v, pl)) + node * 4u);
-    const uint16_t lo =
-        *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(lo_plane(v, pl)) + node * 2u);
+    const float hi = *reinterpret_cast<FP>(reinterpret_cast<CP>(hi_plane(v, pl)) + node * 4u);
+    const uint16_t lo = *reinterpret_cast<HP>(reinterpret_cast<CP>(lo_plane(v, pl)) + node * 2u);
     return widen(hi, lo);
   }
   template <class F>
   __device__ static __forceinline__ void update(const View& v, int pl, uint32_t node, F f) {
-    float* qh = reinterpret_cast<float*>(reinterpret_cast<char*>(hi_plane(v, pl)) + node * 4u);
-    uint16_t* ql = reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lo_plane(v, pl)) + node * 2u);
+    FP qh = reinterpret_cast<FP>(reinterpret_cast<CP>(hi_plane(v, pl)) + node * 4u);
+    HP ql = reinterpret_cast<HP>(reinterpret_cast<CP>(lo_plane(v, pl)) + node * 2u);
     const double val = f(widen(*qh, *ql));
     const float hi = (float)val;
     *qh = hi;
@@ -122,7 +150,8 @@ struct SplitStore {
   };
   __device__ static __forceinline__ Planes planes(const View& v, int pl) {
     const uint32_t n = (uint32_t)v.nodes;
-    return Planes{raw_rsrc(hi_plane(v, pl), 4u * n), raw_rsrc(lo_plane(v, pl), 2u * n)};
+    return Planes{raw_rsrc((const void*)(uintptr_t)hi_plane(v, pl), 4u * n),
+                  raw_rsrc((const void*)(uintptr_t)lo_plane(v, pl), 2u * n)};
   }
   __device__ static __forceinline__ C bload(const Planes& p, uint32_t node) {
     const float hi = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(p.hi, node * 4u, 0u, 0));
@@ -130,5 +159,7 @@ struct SplitStore {
     return widen(hi, lo);
   }
 };
+
+using SplitStore = SplitStoreT<0>;
 
 }  // namespace hl
