@@ -306,11 +306,10 @@ std::vector<double> weight_operator(const hl_plan_s* pl, const PolyOps& P, int k
 // with I_{e,a} the interpolant of a unit datum a at corner e (Sec. 2,
 // eq. (interp), tensor product).  Pb -= B^T Ub reads Ub[j - 1 + e'] with
 // block B[1 - e']^T; Ub -= A^T Pb reads Pb[q + e'] with block A[1 - e']^T.
-void build_adjoint_tables(const hl_plan_s* pl, std::vector<double>& tp, std::vector<double>& tu) {
+void build_adjoint_tables(const hl_plan_s* pl, std::vector<double>& tp, std::vector<double>& tu, WeightMode wm) {
   const int d = pl->d, m = pl->m, MP = m + 1, N2 = 2 * m + 2, nc = pl->nc, ne = 1 << d;
   const PolyOps P = poly_ops(pl);
   const std::vector<double> H = hermite_matrix(m);  // [b][L_0..L_m, R_0..R_m]
-  const WeightMode wm{pl->dt, false};
   const std::vector<double> Wp = weight_operator(pl, P, 1, wm), Wq = weight_operator(pl, P, 0, wm);
   auto row = [&](const int* s) {  // coefficient index of s in {0..2m+1}^d
     int r = 0;
@@ -490,6 +489,35 @@ hl_status build_tables(hl_plan_s* pl, std::vector<double>& tab, WeightMode wm) {
     if ((st = pack3(Wp, out_p, 1, 0, 1.0, ks.p_off[1])) != HL_OK) return st;
     if ((st = pack3(Wp, out_p, 0, 1, 1.0, ks.p_off[2])) != HL_OK) return st;
     if ((st = pack3(Wq, out_g, 0, 0, 1.0, ks.u_off)) != HL_OK) return st;
+    if (ks.f_off >= 0) {
+      // fully merged pressure table F[i][a][o] = A[e = upper corner in every
+      // dimension][o][i][a] (A: the per-corner operator of the transposed
+      // half-steps' construction); every other corner's block must equal it
+      // up to the sigma/delta sign (-1 for a lower corner in a dimension whose
+      // combination is delta), which the kernel's butterfly assumes
+      std::vector<double> tp, tu;
+      build_adjoint_tables(pl, tp, tu, wm);
+      const int nc = pl->nc;
+      // tu[e'][i][a][s] holds A[1 - e'][s][i][a]: e' = 0 is the all-upper corner
+      auto Ablk = [&](int e, int i, int s, int a) { return tu[((((size_t)(7 ^ e)) * 3 + i) * nc + a) * nc + s]; };
+      int t = ks.f_off;
+      for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < nc; ++a)
+          for (int o = 0; o < nc; ++o) {
+            const double F = Ablk(7, i, o, a);
+            const int ad[3] = {a % MP, (a / MP) % MP, a / (MP * MP)}, od[3] = {o % MP, (o / MP) % MP, o / (MP * MP)};
+            for (int e = 0; e < 8; ++e) {
+              double sgn = 1.0;
+              for (int k = 0; k < 3; ++k)
+                if (!((e >> k) & 1) && ((od[k] + ad[k] + (k == i)) & 1)) sgn = -sgn;
+              const double want = sgn * F, got = Ablk(e, i, o, a);
+              if (std::fabs(got - want) > 1e-12 * (std::fabs(F) + 1e-300) + 1e-300)
+                return fail(HL_ERR_ARG, "internal: fully merged 3D table lacks the sigma/delta symmetry");
+            }
+            tab[t++] = F;
+          }
+      t_end = t;
+    }
     if (t_end != ks.table_words) return fail(HL_ERR_ARG, "internal: 3D table size mismatch");
     return HL_OK;
   }
@@ -895,7 +923,7 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
   }
   if (pl->ks.adj_p && !pl->walls) {
     std::vector<double> tp, tu;
-    build_adjoint_tables(pl, tp, tu);
+    build_adjoint_tables(pl, tp, tu, WeightMode{pl->dt, false});
     pl->adj_u_off = tp.size();
     const size_t n = tp.size() + tu.size();
     e = hipMalloc(&pl->dadj, n * pl->tab_bytes);

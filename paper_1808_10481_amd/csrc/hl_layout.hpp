@@ -358,7 +358,9 @@ struct TableLayout {
   static constexpr int p_off(int i) { return (D > 1 && i == 0) ? P_A_OFF : P_B_OFF; }
 };
 
-// 3D: one pressure table per component (derivative dimension), then Q.
+// 3D: one pressure table per component (derivative dimension), then Q; for
+// m <= 2 then the fully merged pressure table (x merged too):
+// F[i][a][o], component i, datum a, output o, (m+1)^3 x (m+1)^3 per component.
 template <int M>
 struct TableLayout<3, M> {
   static constexpr int PG = merge3_size<M, false>();
@@ -366,7 +368,10 @@ struct TableLayout<3, M> {
   static constexpr int P_A_OFF = 0;
   static constexpr int P_B_OFF = 2 * PG;
   static constexpr int U_OFF = 3 * PG;
-  static constexpr int TOTAL = U_OFF + merge3_size<M, true>();
+  static constexpr bool FULL_P = M <= 2;
+  static constexpr int NC = (M + 1) * (M + 1) * (M + 1);
+  static constexpr int F_OFF = U_OFF + merge3_size<M, true>();
+  static constexpr int TOTAL = F_OFF + (FULL_P ? 3 * NC * NC : 0);
 };
 
 }  // namespace hl
