@@ -69,7 +69,8 @@ __all__ = [
     "step", "startup", "p_update_cells", "u_update_cells", "ghost_pad", "mirror_sign",
     "p_operator_blocks", "u_operator_blocks", "p_half_adjoint", "u_half_adjoint", "adjoint_step",
     "kappa_gradient", "kmax_var", "p_update_cells_var", "u_update_cells_var", "p_half_var", "u_half_var",
-    "step_var", "step_with_source",
+    "step_var", "step_with_source", "p_operator_blocks_var", "u_operator_blocks_var",
+    "p_half_var_adjoint", "u_half_var_adjoint", "adjoint_step_var", "kappa_field_gradient",
 ]
 
 _CHUNK = 1 << 14  # nodes per vectorised batch (bounds memory, not arithmetic)
@@ -535,7 +536,7 @@ def _tmul(a: np.ndarray, b: np.ndarray, d: int, ns: int) -> np.ndarray:
     """T[a b]: product of batched cell polynomials (ns batch axes, then d
     coefficient axes of length 2m+2), truncated to the same degrees."""
     n = a.shape[ns]
-    out = np.zeros(np.broadcast_shapes(a.shape, b.shape))
+    out = np.zeros(np.broadcast_shapes(a.shape, b.shape), dtype=np.result_type(a, b))
     for s in itertools.product(range(n), repeat=d):
         bs = a[(slice(None),) * ns + s]
         dst = (slice(None),) * ns + tuple(slice(sk, n) for sk in s)
@@ -573,7 +574,7 @@ def u_update_cells_var(prob: Problem, u_vals, p_corners, kap, dt=None, weight_sc
     for k in range(1, kmax_var(d, m) + 1):
         g = _tmul(kap, _laplacian(g, h, d, 1), d, 1)
         q = q + _w(k, dt) * g
-    out = np.array(u_vals, dtype=np.float64, copy=True)
+    out = np.array(u_vals, dtype=np.result_type(u_vals, q), copy=True)
     for i in range(d):
         out[i] = out[i] - weight_scale * _truncate(_deriv(q, i, h[i], 1), m, d, 1)
     return out
@@ -616,6 +617,185 @@ def step_var(prob: Problem, P, U, Kp, Ku, nsteps: int = 1):
         P = p_half_var(prob, P, U, Kp)
         U = u_half_var(prob, U, P, Ku)
     return P, U
+
+
+# ---------------------------------------------------------------------------
+# Variable kappa: transposed step and gradient with respect to the kappa data
+# ---------------------------------------------------------------------------
+# With kappa data per node the half-step operators are no longer translation
+# invariant: A_j (pressure half-step at primal node j) and B_q (velocity
+# half-step at dual node q) are dense per-node blocks, read off the forward
+# cell updates applied to unit corner data with that node's kappa.  The
+# transpose of a step is again Pb <- Pb - B^T Ub, then Ub <- Ub - A^T Pb.
+# The gradient of <Pb_n, P_n> + <Ub_n, U_n> with respect to the kappa data of
+# node j collects, over the steps, the derivative of that node's cell update
+# paired with the adjoint state at the node (the same chain rule as
+# kappa_gradient, node by node).  The derivative of a cell update with respect
+# to one kappa coefficient is taken by the complex-step method (Squire and
+# Trapp, SIAM Review 40 (1998)): the update is a polynomial in the kappa data
+# with real coefficients, so Im f(kappa + i eps e_b) / eps is its derivative
+# up to rounding for a tiny eps (no difference of nearby values is formed).
+
+_CSTEP = 1e-30
+
+
+def _node_kappa(prob: Problem, Kap: np.ndarray) -> np.ndarray:
+    """Kappa data flattened to (nodes,) + (2m+2,)*d in node order."""
+    d = prob.d
+    return np.asarray(Kap).reshape((-1,) + Kap.shape[d:])
+
+
+def p_operator_blocks_var(prob: Problem, Kp: np.ndarray) -> np.ndarray:
+    """A[j][e][s][i][a] (j the flat primal node): the pressure half-step with
+    kappa data Kp subtracts sum_e sum_{i,a} A[j][e][s][i][a] U_i[j - 1 + e][a]
+    from P[j][s]."""
+    d, nc = prob.d, prob.nc
+    cshape = (prob.m + 1,) * d
+    kap = _node_kappa(prob, Kp)
+    n = kap.shape[0]
+    A = np.zeros((n,) + (2,) * d + (nc, d, nc))
+    for e in itertools.product((0, 1), repeat=d):
+        for i in range(d):
+            for a in range(nc):
+                uc = [np.zeros((2,) * d + (n,) + cshape) for _ in range(d)]
+                uc[i][e + (slice(None),) + np.unravel_index(a, cshape)] = 1.0
+                r = -p_update_cells_var(prob, np.zeros((n,) + cshape), uc, kap)
+                A[(slice(None),) + e + (slice(None), i, a)] = r.reshape(n, nc)
+    return A
+
+
+def u_operator_blocks_var(prob: Problem, Ku: np.ndarray) -> np.ndarray:
+    """B[q][e][i][s][a] (q the flat dual node): the velocity half-step with
+    kappa data Ku subtracts sum_e sum_a B[q][e][i][s][a] P[q + e][a] from
+    U_i[q][s]."""
+    d, nc = prob.d, prob.nc
+    cshape = (prob.m + 1,) * d
+    kap = _node_kappa(prob, Ku)
+    n = kap.shape[0]
+    B = np.zeros((n,) + (2,) * d + (d, nc, nc))
+    for e in itertools.product((0, 1), repeat=d):
+        for a in range(nc):
+            pc = np.zeros((2,) * d + (n,) + cshape)
+            pc[e + (slice(None),) + np.unravel_index(a, cshape)] = 1.0
+            r = -u_update_cells_var(prob, np.zeros((d, n) + cshape), pc, kap)
+            B[(slice(None),) + e + (slice(None), slice(None), a)] = r.reshape(d, n, nc).transpose(1, 0, 2)
+    return B
+
+
+def p_half_var_adjoint(prob: Problem, Pb: np.ndarray, Ub: np.ndarray, Ku: np.ndarray, B=None) -> np.ndarray:
+    """Pb - B(Ku)^T Ub: P[j] receives sum_e B[q]^T Ub[q] from the dual nodes
+    q = j - e whose velocity cells have j as corner e."""
+    d, K, nc = prob.d, tuple(prob.K), prob.nc
+    B = u_operator_blocks_var(prob, Ku) if B is None else B
+    Bn = B.reshape(K + B.shape[1:])
+    Ubf = Ub.reshape((d,) + K + (nc,))
+    out = Pb.reshape(K + (nc,)).copy()
+    axes = tuple(range(d))
+    for e in itertools.product((0, 1), repeat=d):
+        blk = np.roll(Bn[(slice(None),) * d + e], shift=tuple(e), axis=axes)       # B[j - e][e]
+        src = np.roll(Ubf, shift=tuple(e), axis=tuple(range(1, d + 1)))           # Ub[j - e]
+        out -= np.einsum("...isa,i...s->...a", blk, src)
+    return out.reshape(Pb.shape)
+
+
+def u_half_var_adjoint(prob: Problem, Ub: np.ndarray, Pb: np.ndarray, Kp: np.ndarray, A=None) -> np.ndarray:
+    """Ub - A(Kp)^T Pb: U_i[q] receives sum_e A[j]^T Pb[j] from the primal
+    nodes j = q + 1 - e whose pressure cells have q as corner e."""
+    d, K, nc = prob.d, tuple(prob.K), prob.nc
+    A = p_operator_blocks_var(prob, Kp) if A is None else A
+    An = A.reshape(K + A.shape[1:])
+    Pbf = Pb.reshape(K + (nc,))
+    out = Ub.reshape((d,) + K + (nc,)).copy()
+    axes = tuple(range(d))
+    for e in itertools.product((0, 1), repeat=d):
+        sh = tuple(e[k] - 1 for k in range(d))
+        blk = np.roll(An[(slice(None),) * d + e], shift=sh, axis=axes)           # A[q + 1 - e][e]
+        src = np.roll(Pbf, shift=sh, axis=axes)                                   # Pb[q + 1 - e]
+        out -= np.einsum("...sia,...s->i...a", blk, src)
+    return out.reshape(Ub.shape)
+
+
+def adjoint_step_var(prob: Problem, Pb, Ub, Kp, Ku, nsteps: int = 1):
+    """Transpose of `step_var`: nsteps times Pb <- Pb - B^T Ub, then
+    Ub <- Ub - A^T Pb (periodic grid)."""
+    A, B = p_operator_blocks_var(prob, Kp), u_operator_blocks_var(prob, Ku)
+    Pb = np.array(Pb, dtype=np.float64, copy=True)
+    Ub = np.array(Ub, dtype=np.float64, copy=True)
+    for _ in range(int(nsteps)):
+        Pb = p_half_var_adjoint(prob, Pb, Ub, Ku, B)
+        Ub = u_half_var_adjoint(prob, Ub, Pb, Kp, A)
+    return Pb, Ub
+
+
+def _cstep_p(prob: Problem, U, Kp, Pb) -> np.ndarray:
+    """d/dKp[j][b] of <Pb[j], increment part of the pressure cell update at
+    j> for the velocity U, per node j and kappa coefficient b."""
+    d, K = prob.d, tuple(prob.K)
+    nodes = _all_nodes(K)
+    kap = _node_kappa(prob, Kp).astype(np.complex128)
+    n, npc = kap.shape[0], kap[0].size
+    uc = [_gather(U[i], nodes, -1, d, K) for i in range(d)]
+    pb = Pb.reshape(n, -1)
+    cshape = (prob.m + 1,) * d
+    g = np.zeros((n, npc))
+    for b in range(npc):
+        kb = kap.copy()
+        kb.reshape(n, npc)[:, b] += 1j * _CSTEP
+        r = p_update_cells_var(prob, np.zeros((n,) + cshape, dtype=np.complex128), uc, kb)
+        g[:, b] = np.sum(pb * r.reshape(n, -1).imag, axis=1) / _CSTEP
+    return g.reshape(Kp.shape)
+
+
+def _cstep_u(prob: Problem, P, Ku, Ub) -> np.ndarray:
+    """d/dKu[q][b] of <Ub[:, q], increment part of the velocity cell update at
+    q> for the pressure P."""
+    d, K = prob.d, tuple(prob.K)
+    nodes = _all_nodes(K)
+    kap = _node_kappa(prob, Ku).astype(np.complex128)
+    n, npc = kap.shape[0], kap[0].size
+    pc = _gather(P, nodes, 0, d, K)
+    ub = Ub.reshape(d, n, -1)
+    cshape = (prob.m + 1,) * d
+    g = np.zeros((n, npc))
+    for b in range(npc):
+        kb = kap.copy()
+        kb.reshape(n, npc)[:, b] += 1j * _CSTEP
+        r = u_update_cells_var(prob, np.zeros((d, n) + cshape, dtype=np.complex128), pc, kb)
+        g[:, b] = np.sum(ub * r.reshape(d, n, -1).imag, axis=(0, 2)) / _CSTEP
+    return g.reshape(Ku.shape)
+
+
+def kappa_field_gradient(prob: Problem, P0, U0, Kp, Ku, Pbn, Ubn, nsteps: int, p_sources=None):
+    """Gradient with respect to the kappa data Kp, Ku of
+        <Pbn, P_n> + <Ubn, U_n> + sum_t <p_sources[t], P_{t+1}>
+    for n steps of `step_var` from (P0, U0); returns (gKp, gKu, Pb_0, Ub_0),
+    the last two being the gradient with respect to (P0, U0).  p_sources[t]
+    (optional, one array per step) is the adjoint source of a loss on the
+    pressure after step t (e.g. a seismogram misfit at receiver nodes).
+
+    Reverse sweep over the stored trajectory: for step t with adjoint (Pb',
+    Ub') of its result, the velocity half-step contributes d/dKu <Ub', -B P'>,
+    then Pb = Pb' - B^T Ub', the pressure half-step contributes
+    d/dKp <Pb, -A U_t>, then Ub = Ub' - A^T Pb."""
+    A, B = p_operator_blocks_var(prob, Kp), u_operator_blocks_var(prob, Ku)
+    states = [(np.array(P0, dtype=np.float64), np.array(U0, dtype=np.float64))]
+    for _ in range(int(nsteps)):
+        P, U = states[-1]
+        P1 = p_half_var(prob, P, U, Kp)
+        states.append((P1, u_half_var(prob, U, P1, Ku)))
+    Pb, Ub = np.array(Pbn, dtype=np.float64), np.array(Ubn, dtype=np.float64)
+    gKp = np.zeros(np.shape(Kp))
+    gKu = np.zeros(np.shape(Ku))
+    for t in range(int(nsteps) - 1, -1, -1):
+        if p_sources is not None:
+            Pb = Pb + p_sources[t]
+        U_t = states[t][1]
+        P_1 = states[t + 1][0]
+        gKu += _cstep_u(prob, P_1, Ku, Ub)
+        Pb = p_half_var_adjoint(prob, Pb, Ub, Ku, B)
+        gKp += _cstep_p(prob, U_t, Kp, Pb)
+        Ub = u_half_var_adjoint(prob, Ub, Pb, Kp, A)
+    return gKp, gKu, Pb, Ub
 
 
 # ---------------------------------------------------------------------------
