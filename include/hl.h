@@ -228,6 +228,37 @@ hl_status hl_norms(hl_plan_t plan, const void* p, const void* u, double* out);
 hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* p,
                           const void* u, void* grad_kappa, int64_t nsteps, void* stream);
 
+/* Variable-kappa adjoint (plans with hl_set_kappa; Sec. 4, "Smoothly varying
+ * wave speed", differentiated): one transposed step applied in place to the
+ * adjoint state (p_bar, u_bar), and the gradient of that step with respect to
+ * the kappa Taylor data added to the plan's FP64 accumulators.  The step
+ * being undone maps (P_t, U_t) to P' = P_t - A U_t, U' = U_t - B P'; A and B
+ * depend on the kappa data (polynomially), not on the state, so the transpose
+ * is p_bar <- p_bar - B^T u_bar, then u_bar <- u_bar - A^T p_bar, and the
+ * accumulators receive -d<u_bar', B P'>/dkappa_u - d<p_bar, A U_t>/dkappa_p
+ * (p_bar after its update, u_bar' before).  So for a loss l of the final
+ * state, calling this once per step in reverse order, with the adjoint state
+ * starting at dl/d(P_n, U_n), leaves dl/d(P_0, U_0) in (p_bar, u_bar) and
+ * dl/dkappa in the accumulators; a loss on intermediate pressures (receivers)
+ * adds its derivative to p_bar before the step that produced that pressure is
+ * undone.
+ * p_next: the pressure P' after the step being undone (P_{t+1});
+ * u_prev: the velocity U_t before it.  Device buffers in the plan's layout,
+ * not modified; the four buffers must be distinct.  Per node, the kernels run
+ * the adjoint of the truncated-product recurrence (recomputing its forward
+ * terms) and spread the result over the neighbouring cells with a gather (no
+ * atomics), through a plan-owned scratch of d (2m+2)^d planes allocated with
+ * the accumulators on first use (zeroed then).  Built for periodic plans,
+ * d = 1 (all m) and d = 2 (m <= 2), HL_FP64 and HL_FP32; HL_ERR_UNSUPPORTED
+ * otherwise, or without kappa data.  Asynchronous. */
+hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const void* p_next,
+                              const void* u_prev, void* stream);
+
+/* The accumulated kappa gradient: grad_p (for kappa_p) and grad_u (for
+ * kappa_u), host FP64 arrays in hl_set_kappa's layout, either may be NULL.
+ * reset != 0 zeroes the accumulators afterwards.  Synchronous. */
+hl_status hl_kappa_grad(hl_plan_t plan, double* grad_p, double* grad_u, int reset);
+
 /* Batched shots: many independent periodic problems ("shots") of the same
  * d, m and precision - each with its own grid size, time step, coefficient
  * (hl_set_kappa on every plan, or on none) and buffers - advanced together,

@@ -36,6 +36,8 @@ from .hermite_lf import (  # noqa: F401
     ghost_pad,
     adjoint_step,
     kappa_gradient,
+    adjoint_step_var,
+    kappa_field_gradient,
     kmax_var,
     p_half_var,
     u_half_var,

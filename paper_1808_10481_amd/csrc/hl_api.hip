@@ -173,6 +173,12 @@ struct hl_plan_s {
   bool var_kappa = false;
   void* dkap_p = nullptr;
   void* dkap_u = nullptr;
+  // variable-kappa adjoint (allocated on first use): FP64 gradient
+  // accumulators, one plane per kappa coefficient on the primal / dual nodes,
+  // and the scratch of d (2m+2)^d planes between its two kernels
+  double* gkp = nullptr;
+  double* gku = nullptr;
+  void* vscr = nullptr;
   void* tab_dk = nullptr;
   void* tab_rev = nullptr;
   void* fp = nullptr;
@@ -768,6 +774,32 @@ hl_status ensure_gradient(hl_plan_s* pl) {
   return HL_OK;
 }
 
+int64_t kappa_planes(const hl_plan_s* pl) {
+  int64_t n = 1;
+  for (int k = 0; k < pl->d; ++k) n *= 2 * pl->m + 2;
+  return n;
+}
+
+hl_status ensure_var_gradient(hl_plan_s* pl) {
+  if (pl->gkp) return HL_OK;
+  const int64_t np = kappa_planes(pl);
+  const size_t gp = (size_t)np * pl->pnodes * sizeof(double), gu = (size_t)np * pl->unodes * sizeof(double);
+  const size_t sc = (size_t)pl->d * np * std::max(pl->pnodes, pl->unodes) * pl->tab_bytes;
+  hipError_t e = hipMalloc((void**)&pl->gkp, gp);
+  if (e == hipSuccess) e = hipMalloc((void**)&pl->gku, gu);
+  if (e == hipSuccess) e = hipMalloc(&pl->vscr, sc);
+  if (e == hipSuccess) e = hipMemset(pl->gkp, 0, gp);
+  if (e == hipSuccess) e = hipMemset(pl->gku, 0, gu);
+  if (e != hipSuccess) {
+    for (void** q : {(void**)&pl->gkp, (void**)&pl->gku, &pl->vscr}) {
+      if (*q) (void)hipFree(*q);
+      *q = nullptr;
+    }
+    return fail(HL_ERR_NOMEM, std::string("hl_adjoint_step_var: gradient buffers: ") + hipGetErrorString(e));
+  }
+  return HL_OK;
+}
+
 // Launch grid of one half-step: updates K[] nodes stored at index j + ooff
 // of an array with extents oext, corners from an array with extents sext
 // (lower corner at j + soff).
@@ -957,7 +989,7 @@ hl_status hl_plan_destroy(hl_plan_t plan) {
   if (plan->dtab) (void)hipFree(plan->dtab);
   if (plan->dadj) (void)hipFree(plan->dadj);
   for (void* q : {plan->dkap_p, plan->dkap_u, plan->tab_dk, plan->tab_rev, plan->fp, plan->fu, plan->sp, plan->su,
-                  (void*)plan->gpart})
+                  (void*)plan->gpart, (void*)plan->gkp, (void*)plan->gku, plan->vscr})
     if (q) (void)hipFree(q);
   if (plan->dpartial) (void)hipFree(plan->dpartial);
   delete plan;
@@ -1200,6 +1232,61 @@ hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* 
     if (e == hipSuccess) e = plan->ks.adj_u(va, u_bar, p_bar, s);                    // Ub -= A^T Pb
   }
   return e == hipSuccess ? HL_OK : hip_fail(e, "hl_adjoint_step: gradient launch");
+}
+
+hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const void* p_next, const void* u_prev,
+                              void* stream) {
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_adjoint_step_var");
+  if (st != HL_OK) return st;
+  if (!plan->var_kappa) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: the plan has no kappa data (hl_set_kappa)");
+  if (!plan->ks.grad_p_var)
+    return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: built for d = 1 (all m) and d = 2 (m <= 2), HL_FP64 and "
+                                    "HL_FP32");
+  if (!p_bar || !u_bar || !p_next || !u_prev)
+    return fail(HL_ERR_ARG, "hl_adjoint_step_var: NULL buffer");
+  const void* bufs[4] = {p_bar, u_bar, p_next, u_prev};
+  for (int a = 0; a < 4; ++a)
+    for (int b = a + 1; b < 4; ++b)
+      if (bufs[a] == bufs[b]) return fail(HL_ERR_ARG, "hl_adjoint_step_var: the four buffers must be distinct");
+  if ((st = ensure_var_gradient(plan)) != HL_OK) return st;
+  hl::PlanView v = view(plan);
+  hipStream_t s = (hipStream_t)stream;
+  // velocity half-step of the step being undone: gku -= d<Ub, B P'>/dkappa, z = d/dc
+  hipError_t e = plan->ks.grad_u_var(v, u_bar, p_next, plan->gku, plan->vscr, s);
+  if (e == hipSuccess) e = plan->ks.gather_p_var(v, p_bar, plan->vscr, s);            // Pb -= B^T Ub
+  // pressure half-step: gkp -= d<Pb, A U_t>/dkappa, rho = d/dc
+  if (e == hipSuccess) e = plan->ks.grad_p_var(v, p_bar, u_prev, plan->gkp, plan->vscr, s);
+  if (e == hipSuccess) e = plan->ks.gather_u_var(v, u_bar, plan->vscr, s);            // Ub -= A^T Pb
+  if (e != hipSuccess) return hip_fail(e, "hl_adjoint_step_var: launch");
+  return HL_OK;
+}
+
+hl_status hl_kappa_grad(hl_plan_t plan, double* grad_p, double* grad_u, int reset) {
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_kappa_grad");
+  if (st != HL_OK) return st;
+  if (!plan->ks.grad_p_var)
+    return fail(HL_ERR_UNSUPPORTED, "hl_kappa_grad: built for d = 1 (all m) and d = 2 (m <= 2), HL_FP64 and HL_FP32");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hl_kappa_grad: pending work failed");
+  if ((st = ensure_var_gradient(plan)) != HL_OK) return st;
+  const LayoutMap L = hl_host::field_layout(plan->d, 2 * plan->m + 1, plan->K, false, 0);
+  const int64_t np = kappa_planes(plan);
+  double* dev[2] = {plan->gkp, plan->gku};
+  double* host[2] = {grad_p, grad_u};
+  const int64_t nodes[2] = {plan->pnodes, plan->unodes};
+  for (int f = 0; f < 2; ++f) {
+    if (host[f]) {
+      std::vector<double> img((size_t)(np * nodes[f]));
+      e = hipMemcpy(img.data(), dev[f], img.size() * sizeof(double), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(e, "hl_kappa_grad: copy to host");
+      L.for_each([&](int64_t h, int64_t dv) { host[f][h] = img[(size_t)dv]; });
+    }
+    if (reset && (e = hipMemset(dev[f], 0, (size_t)(np * nodes[f]) * sizeof(double))) != hipSuccess)
+      return hip_fail(e, "hl_kappa_grad: reset");
+  }
+  return HL_OK;
 }
 
 hl_status hl_batch_create(const hl_plan_t* plans, int32_t n, hl_batch_t* out) {

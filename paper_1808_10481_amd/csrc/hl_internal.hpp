@@ -41,6 +41,13 @@ struct BatchShot {
 typedef void (*BatchDescFn)(const BatchShot* shots, int n, bool var, std::vector<unsigned char>* pdesc,
                             std::vector<unsigned char>* udesc, int* pblocks, int* ublocks);
 typedef hipError_t (*BatchHalfFn)(const void* desc, int n, int blocks, bool var, hipStream_t);
+// Variable-kappa adjoint: the per-node gradient kernels (bar: adjoint field of
+// the half-step's output, fwd: the forward field it reads, gk: FP64 kappa
+// gradient accumulators, scr: scratch of d (2m+2)^d planes) and the gathers
+// that finish the transposed half-steps from that scratch.
+typedef hipError_t (*VarGradFn)(const PlanView&, const void* bar, const void* fwd, double* gk, void* scr,
+                                hipStream_t);
+typedef hipError_t (*VarGatherFn)(const PlanView&, void* bar, const void* scr, hipStream_t);
 
 struct KernelSet {
   PHalfFn p_half;
@@ -49,6 +56,8 @@ struct KernelSet {
   AdjFn adj_p, adj_u;    // transposed half-steps, NULL where not built
   PHalfFn p_half_var;    // variable-kappa half-steps, NULL where not built
   UHalfFn u_half_var;
+  VarGradFn grad_p_var, grad_u_var;      // variable-kappa adjoint, NULL where not built
+  VarGatherFn gather_p_var, gather_u_var;
   BatchDescFn batch_desc;
   BatchHalfFn p_batch, u_batch;
   int table_words;       // TableLayout<D, M>::TOTAL
@@ -195,6 +204,48 @@ hipError_t launch_u_var(const PlanView& pv, void* u, const void* p, double wscal
   return hipGetLastError();
 }
 
+template <int D, int M, class S>
+hipError_t launch_grad_p_var(const PlanView& pv, const void* pb, const void* u, double* gk, void* scr,
+                             hipStream_t s) {
+  constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
+  const Grid& g = pv.gp;
+  hipLaunchKernelGGL((grad_p_var<D, M, S>), grid_shape(g), block_shape<D>(), 0, s, S::make(pb, 1, NC, g.onodes),
+                     S::make(u, D, NC, g.snodes), S::make(pv.kap_p, 1, NP, g.onodes), gk,
+                     S::make(scr, D, NP, g.onodes), g, var_args<S>(pv));
+  return hipGetLastError();
+}
+
+template <int D, int M, class S>
+hipError_t launch_grad_u_var(const PlanView& pv, const void* ub, const void* p, double* gk, void* scr,
+                             hipStream_t s) {
+  constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
+  const Grid& g = pv.gu;
+  hipLaunchKernelGGL((grad_u_var<D, M, S>), grid_shape(g), block_shape<D>(), 0, s, S::make(ub, D, NC, g.onodes),
+                     S::make(p, 1, NC, g.snodes), S::make(pv.kap_u, 1, NP, g.onodes), gk,
+                     S::make(scr, 1, NP, g.onodes), g, var_args<S>(pv));
+  return hipGetLastError();
+}
+
+// Pb -= sum over the dual nodes q = j - e of the transposed interpolation of z[q]
+template <int D, int M, class S>
+hipError_t launch_gather_p_var(const PlanView& pv, void* pb, const void* scr, hipStream_t s) {
+  constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
+  const Grid& g = pv.gp;
+  hipLaunchKernelGGL((var_adjoint_gather<D, M, S, true>), grid_shape(g), block_shape<D>(), 0, s,
+                     S::make(pb, 1, NC, g.onodes), S::make(scr, 1, NP, g.snodes), g);
+  return hipGetLastError();
+}
+
+// Ub -= sum over the primal nodes j = q + 1 - e of the transposed interpolation of rho[j]
+template <int D, int M, class S>
+hipError_t launch_gather_u_var(const PlanView& pv, void* ub, const void* scr, hipStream_t s) {
+  constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
+  const Grid& g = pv.gu;
+  hipLaunchKernelGGL((var_adjoint_gather<D, M, S, false>), grid_shape(g), block_shape<D>(), 0, s,
+                     S::make(ub, D, NC, g.onodes), S::make(scr, D, NP, g.snodes), g);
+  return hipGetLastError();
+}
+
 template <class S>
 constexpr bool kPlain = false;
 template <typename W>
@@ -202,6 +253,8 @@ constexpr bool kPlain<PlainStore<W>> = true;
 
 template <int D, int M, class S>
 constexpr bool kVarBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 3));
+template <int D, int M, class S>
+constexpr bool kVarGradBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 2));
 
 template <int D, int M, class S>
 void batch_desc(const BatchShot* shots, int n, bool var, std::vector<unsigned char>* pdesc,
@@ -288,6 +341,17 @@ inline bool make_set(KernelSet* out) {
   if constexpr (kVarBuilt<D, M, S>) {
     out->p_half_var = &launch_p_var<D, M, S>;
     out->u_half_var = &launch_u_var<D, M, S>;
+  }
+  // variable-kappa adjoint and kappa gradient: d = 1 (all m) and d = 2 (m <= 2)
+  out->grad_p_var = nullptr;
+  out->grad_u_var = nullptr;
+  out->gather_p_var = nullptr;
+  out->gather_u_var = nullptr;
+  if constexpr (kVarGradBuilt<D, M, S>) {
+    out->grad_p_var = &launch_grad_p_var<D, M, S>;
+    out->grad_u_var = &launch_grad_u_var<D, M, S>;
+    out->gather_p_var = &launch_gather_p_var<D, M, S>;
+    out->gather_u_var = &launch_gather_u_var<D, M, S>;
   }
   return true;
 }

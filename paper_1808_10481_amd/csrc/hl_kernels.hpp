@@ -882,6 +882,304 @@ __global__ void __launch_bounds__(256) u_half_var(typename S::View u, typename S
 }
 
 // ---------------------------------------------------------------------------
+// Variable kappa: transposed half-steps and the gradient with respect to the
+// kappa data.  The increment of a half-step at one node, paired with adjoint
+// data y spread onto the cell polynomial, is
+//   S = <y, sum_k t_k>,   t_0 = T[kappa f] (pressure) or f (velocity),
+//   t_k = r_k T[kappa Lap t_{k-1}],   r_k = w_k / w_{k-1},
+// with f = w_0 div c (pressure) or w_0 c (velocity).  With the adjoint series
+//   lam_kmax = y,   lam_{k-1} = y + r_k Lap^T T^T[kappa] lam_k
+// (T^T[kappa] g: b -> sum_a kappa_a g_{a+b}) one has S = <lam_0, t_0>, so
+//   dS/df = T^T[kappa] lam_0 (pressure), lam_0 (velocity), and
+//   dS/dkappa_a = sum_k sum_b lam_k[a + b] g_k[b],
+//   g_k = r_k Lap t_{k-1} (k >= 1), g_0 = f (pressure side only).
+// The transposed interpolation then spreads dS/dc onto the 2^d corner blocks
+// (a gather over the neighbouring cells, second kernel).  t_{k-1} is
+// recomputed from t_0 for each k: no per-node stack of kmax polynomials.
+// ---------------------------------------------------------------------------
+
+// out_b += kappa_A g_{A+b} (one term of the transposed truncated product).
+template <int D, int M, int A, class S>
+__device__ __forceinline__ void tprodT_term(const typename S::View& kv, uint32_t n0, const typename S::C* g,
+                                            typename S::C* out) {
+  constexpr int N2 = 2 * M + 2, AX = A % N2, AY = A / N2, NY = D > 1 ? N2 : 1;
+  const typename S::C ka = S::load(kv, A, n0);
+#pragma unroll
+  for (int by = 0; by + AY < NY; ++by)
+#pragma unroll
+    for (int bx = 0; bx + AX < N2; ++bx) out[bx + N2 * by] = fma(ka, g[(bx + AX) + N2 * (by + AY)], out[bx + N2 * by]);
+}
+
+template <int D, int M, class S, int... A>
+__device__ __forceinline__ void tprodT_terms(const typename S::View& kv, uint32_t n0, const typename S::C* g,
+                                             typename S::C* out, std::integer_sequence<int, A...>) {
+  (tprodT_term<D, M, A, S>(kv, n0, g, out), ...);
+}
+
+// out = T^T[kappa] g.
+template <int D, int M, class S>
+__device__ __forceinline__ void tprodT(const typename S::View& kv, uint32_t n0, const typename S::C* g,
+                                       typename S::C* out) {
+  using T = typename S::C;
+  constexpr int NP = VK<D, M>::NP;
+#pragma unroll
+  for (int b = 0; b < NP; ++b) out[b] = T(0);
+  tprodT_terms<D, M, S>(kv, n0, g, out, std::make_integer_sequence<int, NP>{});
+}
+
+// grad_A += sum_b lam_{A+b} g_b (the kappa_A derivative of <lam, T[kappa g]>).
+template <int D, int M, int A, typename T>
+__device__ __forceinline__ void corr_term(const T* lam, const T* g, T* grad) {
+  constexpr int N2 = 2 * M + 2, AX = A % N2, AY = A / N2, NY = D > 1 ? N2 : 1;
+  T acc = grad[A];
+#pragma unroll
+  for (int by = 0; by + AY < NY; ++by)
+#pragma unroll
+    for (int bx = 0; bx + AX < N2; ++bx) acc = fma(lam[(bx + AX) + N2 * (by + AY)], g[bx + N2 * by], acc);
+  grad[A] = acc;
+}
+
+template <int D, int M, typename T, int... A>
+__device__ __forceinline__ void corr_terms(const T* lam, const T* g, T* grad, std::integer_sequence<int, A...>) {
+  (corr_term<D, M, A>(lam, g, grad), ...);
+}
+
+template <int D, int M, typename T>
+__device__ __forceinline__ void corr(const T* lam, const T* g, T* grad) {
+  corr_terms<D, M>(lam, g, grad, std::make_integer_sequence<int, VK<D, M>::NP>{});
+}
+
+// out = sc Lap^T f: sc sum_i (b_i - 1) b_i / h_i^2 f_{b - 2 e_i}.
+template <int D, int M, typename T>
+__device__ __forceinline__ void lapT_coef(const T* f, T* out, const T* ih, T sc) {
+  constexpr int N2 = 2 * M + 2, NP = VK<D, M>::NP;
+  const T ix2 = sc * ih[0] * ih[0], iy2 = sc * ih[1] * ih[1];
+#pragma unroll
+  for (int b = 0; b < NP; ++b) {
+    const int bx = b % N2, by = b / N2;
+    T v = T(0);
+    if (bx >= 2) v = fma(T((bx - 1) * bx) * ix2, f[b - 2], v);
+    if (D > 1 && by >= 2) v = fma(T((by - 1) * by) * iy2, f[b - 2 * N2], v);
+    out[b] = v;
+  }
+}
+
+// The series part shared by both sides: given t_0 and y, returns lam_0 in lam
+// and adds sum_{k >= 1} sum_b lam_k[a + b] g_k[b] to grad.
+template <int D, int M, class S>
+__device__ __forceinline__ void adjoint_series(const typename S::View& kv, uint32_t n0, const typename S::C* t0,
+                                               const typename S::C* y, const VarArgs<typename S::C>& va,
+                                               typename S::C* lam, typename S::C* grad) {
+  using T = typename S::C;
+  constexpr int NP = VK<D, M>::NP;
+#pragma unroll
+  for (int b = 0; b < NP; ++b) lam[b] = y[b];
+#pragma unroll 1
+  for (int k = VK<D, M>::KMAX; k >= 1; --k) {
+    T t[NP], l[NP];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) t[b] = t0[b];
+#pragma unroll 1
+    for (int q = 1; q < k; ++q) {  // t = t_{k-1}
+      lap_coef<D, M>(t, l, va.ih, va.ratio[q]);
+      tprod<D, M, S>(kv, n0, l, t);
+    }
+    lap_coef<D, M>(t, l, va.ih, va.ratio[k]);  // g_k
+    corr<D, M>(lam, l, grad);
+    tprodT<D, M, S>(kv, n0, lam, t);
+    lapT_coef<D, M>(t, l, va.ih, va.ratio[k]);
+#pragma unroll
+    for (int b = 0; b < NP; ++b) lam[b] = y[b] + l[b];
+  }
+}
+
+// Pressure side at primal node j: with Pb the adjoint pressure and U_t the
+// velocity before the step, gk -= dS/dkappa (FP64 accumulators, one plane per
+// kappa coefficient) and rho_i = d S / d c^(i) (D NP planes of scratch).
+template <int D, int M, class S>
+__global__ void __launch_bounds__(256) grad_p_var(typename S::View pb, typename S::View u, typename S::View kp,
+                                                  double* __restrict__ gk, typename S::View rho, Grid g,
+                                                  VarArgs<typename S::C> va) {
+  using T = typename S::C;
+  constexpr int N2 = 2 * M + 2, MP = M + 1, NP = VK<D, M>::NP, NC = Dims<D, M>::NC;
+  int32_t j[3];
+  if (!node_of_block<D>(g, blockIdx.x, j)) return;
+  uint32_t cn[1 << D];
+  corner_nodes<D>(g, j, cn);  // dual q = j - 1 + e
+  const uint32_t n0 = out_index<D>(g, j);
+  T f[NP];  // f = w_0 div c
+#pragma unroll
+  for (int b = 0; b < NP; ++b) f[b] = T(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    T c[NP];
+    interp_full<D, M, S>(u, i, cn, c);
+    const int st = i == 0 ? 1 : N2;
+    const T w = va.w0 * va.ih[i];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      const int bi = i == 0 ? b % N2 : b / N2;
+      if (bi + 1 < N2) f[b] = fma(T(bi + 1) * w, c[b + st], f[b]);
+    }
+  }
+  T y[NP], t0[NP], lam[NP], grad[NP];
+#pragma unroll
+  for (int b = 0; b < NP; ++b) {
+    y[b] = T(0);
+    grad[b] = T(0);
+  }
+#pragma unroll
+  for (int s = 0; s < NC; ++s) y[(s % MP) + N2 * (s / MP)] = S::load(pb, s, n0);
+  tprod<D, M, S>(kp, n0, f, t0);
+  adjoint_series<D, M, S>(kp, n0, t0, y, va, lam, grad);
+  corr<D, M>(lam, f, grad);  // k = 0: t_0 = T[kappa f]
+#pragma unroll
+  for (int b = 0; b < NP; ++b) gk[(size_t)b * g.onodes + n0] -= (double)grad[b];
+  T phi[NP];  // dS/df
+  tprodT<D, M, S>(kp, n0, lam, phi);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const T w = va.w0 * va.ih[i];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      const int bi = i == 0 ? b % N2 : b / N2;
+      const T v = bi >= 1 ? T(bi) * w * phi[b - (i == 0 ? 1 : N2)] : T(0);
+      S::store(rho, i * NP + b, n0, v);
+    }
+  }
+}
+
+// Velocity side at dual node q: with Ub the adjoint velocity and P' the
+// pressure after the step's pressure half-step, gk -= dS/dkappa and
+// z = dS/dc (NP planes of scratch).
+template <int D, int M, class S>
+__global__ void __launch_bounds__(256) grad_u_var(typename S::View ub, typename S::View p, typename S::View ku,
+                                                  double* __restrict__ gk, typename S::View z, Grid g,
+                                                  VarArgs<typename S::C> va) {
+  using T = typename S::C;
+  constexpr int N2 = 2 * M + 2, MP = M + 1, NP = VK<D, M>::NP, NC = Dims<D, M>::NC;
+  int32_t j[3];
+  if (!node_of_block<D>(g, blockIdx.x, j)) return;
+  uint32_t cn[1 << D];
+  corner_nodes<D>(g, j, cn);  // primal j = q + e
+  const uint32_t n0 = out_index<D>(g, j);
+  T t0[NP], y[NP], lam[NP], grad[NP];
+  interp_full<D, M, S>(p, 0, cn, t0);
+#pragma unroll
+  for (int b = 0; b < NP; ++b) {
+    t0[b] *= va.w0;
+    y[b] = T(0);
+    grad[b] = T(0);
+  }
+  // S = sum_i sum_s Ub_i[s] (s_i + 1) / h_i Q[s + e_i]
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+      const int sx = s % MP, sy = s / MP;
+      const int si = i == 0 ? sx : sy;
+      y[(sx + (i == 0)) + N2 * (sy + (i == 1))] += T(si + 1) * va.ih[i] * S::load(ub, i * NC + s, n0);
+    }
+  adjoint_series<D, M, S>(ku, n0, t0, y, va, lam, grad);
+#pragma unroll
+  for (int b = 0; b < NP; ++b) {
+    gk[(size_t)b * g.onodes + n0] -= (double)grad[b];
+    S::store(z, b, n0, va.w0 * lam[b]);
+  }
+}
+
+// acc[a] += sum_b H_e(b, a) z[b]: the transposed interpolation onto corner e
+// (bit k: upper side in dimension k) of a cell.  H_e(b, a) is the weight of
+// corner datum a in coefficient b of the interpolant: pass_coef for the upper
+// corner, with the sign of the delta combination for the lower one.
+template <int M, int SIDE>
+constexpr double hcol(int b, int a) {
+  return pass_coef<M, 0>(b, a) * ((SIDE == 0 && ((b + a) & 1)) ? -1.0 : 1.0);
+}
+
+template <int D, int M, int E, typename T>
+__device__ __forceinline__ void interp_T(const T* z, T* acc) {
+  constexpr int N2 = 2 * M + 2, MP = M + 1;
+  if constexpr (D == 1) {
+#pragma unroll
+    for (int a = 0; a < MP; ++a)
+#pragma unroll
+      for (int b = 0; b < N2; ++b) {
+        const double h = hcol<M, E & 1>(b, a);
+        if (h != 0.0) acc[a] = fma(T(h), z[b], acc[a]);
+      }
+  } else {
+    T zy[N2][MP];
+#pragma unroll
+    for (int bx = 0; bx < N2; ++bx)
+#pragma unroll
+      for (int ay = 0; ay < MP; ++ay) {
+        T v = T(0);
+#pragma unroll
+        for (int by = 0; by < N2; ++by) {
+          const double h = hcol<M, (E >> 1) & 1>(by, ay);
+          if (h != 0.0) v = fma(T(h), z[bx + N2 * by], v);
+        }
+        zy[bx][ay] = v;
+      }
+#pragma unroll
+    for (int ay = 0; ay < MP; ++ay)
+#pragma unroll
+      for (int ax = 0; ax < MP; ++ax)
+#pragma unroll
+        for (int bx = 0; bx < N2; ++bx) {
+          const double h = hcol<M, E & 1>(bx, ax);
+          if (h != 0.0) acc[ax + MP * ay] = fma(T(h), zy[bx][ay], acc[ax + MP * ay]);
+        }
+  }
+}
+
+template <int D, int M, class S, int EP>
+__device__ __forceinline__ void gather_corner(const typename S::View& scr, int comp, uint32_t node,
+                                              typename S::C* acc) {
+  constexpr int NP = VK<D, M>::NP;
+  typename S::C z[NP];
+#pragma unroll
+  for (int b = 0; b < NP; ++b) z[b] = S::load(scr, comp * NP + b, node);
+  // slot EP of the output node's stencil is corner E = EP ^ (2^D - 1) of the
+  // source node's cell
+  interp_T<D, M, EP ^ ((1 << D) - 1)>(z, acc);
+}
+
+template <int D, int M, class S, int... EP>
+__device__ __forceinline__ void gather_corners(const typename S::View& scr, int comp, const uint32_t* cn,
+                                               typename S::C* acc, std::integer_sequence<int, EP...>) {
+  (gather_corner<D, M, S, EP>(scr, comp, cn[EP], acc), ...);
+}
+
+// Second stage of a transposed variable-kappa half-step: out -= the
+// transposed interpolation of the per-cell dS/dc held in scr over the
+// output node's stencil (the source node's cell has the output node as
+// corner 1 - e where the output's stencil has the source as slot e).
+//   PTYPE = true:  out = Pb (primal), scr = z over the dual nodes (NP planes)
+//   PTYPE = false: out = Ub (dual, D components), scr = rho over the primal
+//                  nodes (D NP planes)
+template <int D, int M, class S, bool PTYPE>
+__global__ void __launch_bounds__(256) var_adjoint_gather(typename S::View out, typename S::View scr, Grid g) {
+  using T = typename S::C;
+  constexpr int NC = Dims<D, M>::NC, NO = PTYPE ? 1 : D;
+  int32_t j[3];
+  if (!node_of_block<D>(g, blockIdx.x, j)) return;
+  uint32_t cn[1 << D];
+  corner_nodes<D>(g, j, cn);
+  const uint32_t n0 = out_index<D>(g, j);
+#pragma unroll 1
+  for (int io = 0; io < NO; ++io) {
+    T acc[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) acc[a] = T(0);
+    gather_corners<D, M, S>(scr, io, cn, acc, std::make_integer_sequence<int, (1 << D)>{});
+#pragma unroll
+    for (int a = 0; a < NC; ++a) S::update(out, io * NC + a, n0, [&](T x) { return x - acc[a]; });
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Batched shots: one launch per half-step advances many independent problems
 // ("shots": the paper's experiments repeated over sources and grids) of the
 // same (d, m, storage), each with its own grid, time step, coefficient and

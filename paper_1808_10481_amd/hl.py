@@ -28,8 +28,9 @@ STATUS_NAMES = {0: "HL_OK", 1: "HL_ERR_ARG", 2: "HL_ERR_CFL", 3: "HL_ERR_UNSUPPO
 
 # Every symbol include/hl.h declares.
 EXPORTS = ("hl_plan", "hl_plan_destroy", "hl_plan_info", "hl_init", "hl_export", "hl_step",
-           "hl_p_half", "hl_u_half", "hl_add_source", "hl_set_kappa", "hl_norms", "hl_adjoint_step", "hl_batch_create",
-           "hl_batch_step", "hl_batch_destroy", "hl_last_error")
+           "hl_p_half", "hl_u_half", "hl_add_source", "hl_set_kappa", "hl_norms", "hl_adjoint_step",
+           "hl_adjoint_step_var", "hl_kappa_grad", "hl_batch_create", "hl_batch_step", "hl_batch_destroy",
+           "hl_last_error")
 
 
 class HLProblem(ctypes.Structure):
@@ -73,6 +74,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hl_batch_step": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i64, vp]),
         "hl_batch_destroy": ([vp]),
         "hl_adjoint_step": ([vp, vp, vp, vp, vp, vp, i64, vp]),
+        "hl_adjoint_step_var": ([vp, vp, vp, vp, vp, vp]),
+        "hl_kappa_grad": ([vp, vp, vp, ctypes.c_int]),
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -234,6 +237,26 @@ class Plan:
             gg = ctypes.c_void_p(grad_kappa.data_ptr())
         _check(lib().hl_adjoint_step(self._h, ctypes.c_void_p(p_bar.data_ptr()), ctypes.c_void_p(u_bar.data_ptr()),
                                      pp, uu, gg, int(nsteps), _stream_ptr(stream)))
+
+    def adjoint_step_var(self, p_bar, u_bar, p_next, u_prev, stream=None):
+        """One transposed variable-kappa step on the adjoint state, in place,
+        adding its kappa gradient to the plan's accumulators
+        (hl_adjoint_step_var); p_next = P_{t+1}, u_prev = U_t of the step
+        being undone."""
+        self._check_buf(p_bar, u_bar)
+        self._check_buf(p_next, u_prev)
+        _check(lib().hl_adjoint_step_var(self._h, ctypes.c_void_p(p_bar.data_ptr()), ctypes.c_void_p(u_bar.data_ptr()),
+                                         ctypes.c_void_p(p_next.data_ptr()), ctypes.c_void_p(u_prev.data_ptr()),
+                                         _stream_ptr(stream)))
+
+    def kappa_grad(self, reset=False):
+        """(grad_p, grad_u): the accumulated gradient with respect to the kappa
+        data, FP64 arrays shaped like set_kappa's inputs (hl_kappa_grad)."""
+        shape = self.cells + (2 * self.m + 2,) * self.d
+        gp, gu = np.zeros(shape), np.zeros(shape)
+        _check(lib().hl_kappa_grad(self._h, gp.ctypes.data_as(ctypes.c_void_p), gu.ctypes.data_as(ctypes.c_void_p),
+                                   1 if reset else 0))
+        return gp, gu
 
     def source_buffer(self, g, stream=None):
         """Device buffer (p layout) holding the scaled data g (host layout of p)."""

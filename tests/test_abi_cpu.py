@@ -92,6 +92,8 @@ def test_plan_rejects_null_and_reserved():
 def test_adjoint_rejects_null_plan():
     st = hl.lib().hl_adjoint_step(None, None, None, None, None, None, 1, None)
     assert st == hl.HL_ERR_ARG
+    assert hl.lib().hl_adjoint_step_var(None, None, None, None, None, None) == hl.HL_ERR_ARG
+    assert hl.lib().hl_kappa_grad(None, None, None, 0) == hl.HL_ERR_ARG
 
 
 def test_null_plan_arguments():
