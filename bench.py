@@ -260,6 +260,18 @@ def run_batch(hl, torch, steps, nshots=32, m=3):
     cells = sum(K * K for K in sizes)
     batch = hl.Batch(plans)
     ps, us = [p for p, _ in states], [u for _, u in states]
+    # a Ricker point source per shot (f0 seeded in [5, 15] cycles per unit
+    # time, narrow Gaussian support of width 2 h at a seeded position), inside
+    # the batched launch
+    srcs, amps, nsrc = [], [], 0
+    for plan, K in zip(plans, sizes):
+        nodes, vals = inputs.point_source(2, m, (K, K), (1.0, 1.0), tuple(rng.uniform(0.2, 0.8, 2)), 2.0 / K)
+        f0 = float(rng.uniform(5.0, 15.0))
+        r = inputs.ricker(f0, 1.2 / f0)
+        srcs.append((nodes, vals))
+        amps.append(np.array([plan.dt * r((n + 0.5) * plan.dt) for n in range(steps + 32)]))
+        nsrc += len(nodes)
+    batch.set_sources(srcs, amps)
     batch.step(ps, us, 16)                                     # warm-up + graph capture
     for plan, (p, u) in zip(plans, states):
         plan.step(p, u, 16)
@@ -282,8 +294,10 @@ def run_batch(hl, torch, steps, nshots=32, m=3):
     return {"batched": {"value": cells / (tb * 1e-3), "unit": "cell-updates/s", "ms_per_step": tb},
             "per_shot": {"value": cells / (ts * 1e-3), "unit": "cell-updates/s", "ms_per_step": ts},
             "speedup_batched_vs_per_shot": ts / tb, "steps": steps,
+            "note": "per-shot stepping has no source term; the batched steps include the Ricker sources",
             "config": {"workload": f"batched_shots_2d {nshots} shots m={m} fp32, sizes seeded in [256, 1024]^2, "
-                                   "c per shot in [1, 3]", "cells": cells, "sizes": sizes}}
+                                   "c per shot in [1, 3], one Ricker point source per shot (f0 in [5, 15])",
+                       "cells": cells, "sizes": sizes, "source_nodes": nsrc}}
 
 
 def run_adjoint(hl, torch, steps, K=512, m=2):
@@ -322,6 +336,84 @@ def run_adjoint(hl, torch, steps, K=512, m=2):
         torch.cuda.empty_cache()
     res["config"] = {"workload": f"adjoint_2d m={m} {K}^2 periodic constant kappa", "d": 2, "m": m, "cells": [K, K]}
     return res
+
+
+def run_kappa_gradient(hl, torch, steps, K=512, m=2, ndir=8):
+    """Gradient of a receiver misfit with respect to the kappa data (2D, m=2,
+    512^2, periodic, FP32): the "observed" traces come from a seeded smooth
+    kappa, the model kappa is a seeded smooth perturbation of it; a Gaussian
+    pulse (width 0.05, seeded centre) starts the wave, 16 receivers on a line
+    record coefficient 0 of the pressure after every step.  Timed: forward
+    with sqrt(N) checkpoints plus the checkpointed backward (segment re-runs
+    and hl_adjoint_step_var per step).  Then the gradient's directional
+    derivatives against fourth-order central differences of the same FP32
+    forward on `ndir` random smooth directions."""
+    from paper_1808_10481_amd import autograd as hag
+    from paper_1808_10481_amd import inputs
+    rng = np.random.default_rng(11)
+    d, KK = 2, (K, K)
+    log(f"[bench] kappa gradient 2d m={m} {K}^2 fp32: {steps} steps, sqrt(N) checkpoints")
+    waves = tuple(int(w) for w in rng.integers(1, 4, d))
+    amps_true = tuple(rng.uniform(0.15, 0.3, d))
+    amps_model = tuple(a * rng.uniform(0.7, 0.9) for a in amps_true)
+    kt = [inputs.kappa_sines(d, m, KK, (1.0, 1.0), amps_true, waves, g) for g in ("primal", "dual")]
+    km = [inputs.kappa_sines(d, m, KK, (1.0, 1.0), amps_model, waves, g) for g in ("primal", "dual")]
+    cmax = float(np.sqrt(1.0 + sum(amps_true)))
+    plan = hl.Plan(d, m, KK, cfl=0.5, c=cmax, precision="fp32")
+    p0, u0 = plan.alloc()
+    centre = tuple(rng.uniform(0.3, 0.7, d))
+    plan.init(p0, u0, inputs.gaussian_pulse(d, m, KK, (1.0, 1.0), centre, 0.05), np.zeros(plan.host_shapes()[1]))
+    rec = [(int(x), K // 4) for x in np.linspace(K // 16, K - K // 16, 16)]
+    with torch.no_grad():
+        obs, _, _ = hag.receiver_traces(torch.tensor(kt[0]), torch.tensor(kt[1]), p0, u0, plan, steps, rec)
+    obs = obs.double()
+
+    def misfit(a, b, grad):
+        with torch.set_grad_enabled(grad):
+            tr, _, _ = hag.receiver_traces(a, b, p0, u0, plan, steps, rec)
+            return 0.5 * ((tr.double() - obs) ** 2).sum()
+
+    kp = torch.tensor(km[0], requires_grad=True)
+    ku = torch.tensor(km[1], requires_grad=True)
+    misfit(torch.tensor(km[0]), torch.tensor(km[1]), False)     # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = misfit(kp, ku, True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    gp, gu = kp.grad.numpy(), ku.grad.numpy()
+    decay = np.ones((2 * m + 2,) * d)
+    for idx in np.ndindex(*decay.shape):
+        decay[idx] = 0.5 ** sum(idx)
+    errs = []
+    eps = 2e-3
+    for _ in range(ndir):
+        dp = rng.normal(size=gp.shape) * decay
+        du = rng.normal(size=gu.shape) * decay
+
+        def L(s):
+            return float(misfit(torch.tensor(km[0] + s * dp), torch.tensor(km[1] + s * du), False))
+
+        fd = (-L(2 * eps) + 8 * L(eps) - 8 * L(-eps) + L(-2 * eps)) / (12 * eps)
+        an = float(np.sum(gp * dp) + np.sum(gu * du))
+        errs.append(abs(fd - an) / max(abs(fd), 1e-300))
+    plan.close()
+    del p0, u0
+    torch.cuda.empty_cache()
+    fwd_ms, bwd_ms = (t1 - t0) * 1e3, (t2 - t1) * 1e3
+    seg = int(np.ceil(np.sqrt(steps)))
+    log(f"[bench] kappa gradient: forward {fwd_ms:.1f} ms, backward {bwd_ms:.1f} ms, FD rel err max {max(errs):.2e}")
+    return {"config": {"workload": f"kappa_gradient_2d m={m} {K}^2 periodic fp32, receiver misfit, "
+                                   f"16 receivers, {steps} steps, sqrt(N) checkpoints", "d": d, "m": m,
+                       "cells": [K, K], "steps": steps, "checkpoint_segment": seg},
+            "misfit": float(loss.detach()), "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+            "ms_per_step_forward_plus_backward": (fwd_ms + bwd_ms) / steps,
+            "gradient_cell_steps_per_s": K * K * steps / ((t2 - t0)),
+            "fd_check": {"directions": ndir, "eps": eps, "rel_err": errs, "max_rel_err": max(errs),
+                         "note": "fourth-order central differences of the FP32 forward"}}
 
 
 def copy_probe(torch, nbytes=1 << 30, reps=20):
@@ -387,6 +479,8 @@ def main():
     ap.add_argument("--steps-batch", type=int, default=48)
     ap.add_argument("--steps-varkappa", type=int, default=50)
     ap.add_argument("--steps-adjoint", type=int, default=100)
+    ap.add_argument("--no-kgrad", action="store_true")
+    ap.add_argument("--steps-kgrad", type=int, default=2000)
     ap.add_argument("--steps-walls", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -470,6 +564,9 @@ def main():
 
     if not args.no_adjoint:
         out["adjoint_2d"] = run_adjoint(hl, torch, args.steps_adjoint)
+
+    if not args.no_kgrad:
+        out["kappa_gradient_2d"] = run_kappa_gradient(hl, torch, args.steps_kgrad)
 
     if not args.no_copy_probe:
         out["copy_probe"] = copy_probe(torch)

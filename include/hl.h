@@ -273,6 +273,23 @@ hl_status hl_batch_create(const hl_plan_t* plans, int32_t n, hl_batch_t* out);
 hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_t nsteps, void* stream);
 hl_status hl_batch_destroy(hl_batch_t batch);
 
+/* Sources inside the batched launch (Sec. 4: the forcing z = r(t) g(x) of the
+ * pressure equation, entering each step by the midpoint rule as in
+ * hl_add_source): from the next hl_batch_step on, batch step n (counted from
+ * this call over every later hl_batch_step) adds amps[i][n] * g_i to shot i's
+ * pressure after its pressure half-step, for n < namps.  g_i is given on the
+ * primal nodes of its support: counts[i] nodes (0: no source), nodes[i][k] the
+ * node's flat host index (C order over j_1..j_d, j_1 slowest), values[i] the
+ * scaled Taylor data of g there, counts[i] x (m+1)^d in hl_init's coefficient
+ * order.  amps[i] (namps values, NULL: zeros) are the amplitudes
+ * a = dt_i r(t_n + dt_i/2) of shot i.  Host arrays, copied (values and
+ * amplitudes rounded to the batch's precision).  counts == NULL removes the
+ * sources.  HL_FP64 and HL_FP32 batches; the added launch (one work-item per
+ * source datum) and the step counter's update join each batched step and its
+ * captured graph.  Synchronous. */
+hl_status hl_batch_set_sources(hl_batch_t batch, const int64_t* counts, const int64_t* const* nodes,
+                               const double* const* values, const double* const* amps, int64_t namps);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char* hl_last_error(void);
 

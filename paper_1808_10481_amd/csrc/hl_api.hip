@@ -210,6 +210,15 @@ struct hl_batch_s {
   int pblocks = 0, ublocks = 0;
   hipStream_t cap_stream = nullptr;   // graph of kGraphChunk batched steps
   hipGraphExec_t gexec = nullptr;
+  // sources (hl_batch_set_sources): entries, values and amplitudes on the
+  // device, the shots' pressure buffers, and the step counter
+  bool src = false;
+  void* d_pbase = nullptr;
+  void* d_ent = nullptr;
+  void* d_val = nullptr;
+  void* d_amps = nullptr;
+  int64_t* d_counter = nullptr;
+  int64_t nent = 0, namps = 0;
 };
 
 namespace {
@@ -220,6 +229,20 @@ constexpr int64_t kGraphChunk = 16;   // steps per captured graph (32 kernel nod
 #define HL_3D_YGROUP 2
 #endif
 constexpr int32_t kYGroup3 = HL_3D_YGROUP;
+
+// Advances a batch's step counter (one work-item; runs after the step's source).
+__global__ void batch_tick(int64_t* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] += 1;
+}
+
+void drop_sources(hl_batch_s* b) {
+  for (void** q : {&b->d_pbase, &b->d_ent, &b->d_val, &b->d_amps, (void**)&b->d_counter}) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  b->src = false;
+  b->nent = b->namps = 0;
+}
 
 void drop_graph(hl_plan_s* pl) {
   if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
@@ -1316,7 +1339,108 @@ hl_status hl_batch_destroy(hl_batch_t batch) {
   if (batch->cap_stream) (void)hipStreamDestroy(batch->cap_stream);
   if (batch->dp) (void)hipFree(batch->dp);
   if (batch->du) (void)hipFree(batch->du);
+  drop_sources(batch);
   delete batch;
+  return HL_OK;
+}
+
+hl_status hl_batch_set_sources(hl_batch_t batch, const int64_t* counts, const int64_t* const* nodes,
+                               const double* const* values, const double* const* amps, int64_t namps) {
+  g_last_error.clear();
+  if (!batch) return fail(HL_ERR_ARG, "hl_batch_set_sources: batch is NULL");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hl_batch_set_sources: pending work failed");
+  if (batch->gexec) (void)hipGraphExecDestroy(batch->gexec);
+  batch->gexec = nullptr;
+  batch->bp.clear();  // the next hl_batch_step rebuilds its tables
+  drop_sources(batch);
+  if (!counts) return HL_OK;
+  if (!batch->ks.batch_src)
+    return fail(HL_ERR_UNSUPPORTED, "hl_batch_set_sources: built for HL_FP64 and HL_FP32 batches");
+  if (namps < 0 || !nodes || !values || !amps) return fail(HL_ERR_ARG, "hl_batch_set_sources: bad arguments");
+  const int n = (int)batch->plans.size();
+  const hl_plan_s* p0 = batch->plans[0];
+  const int d = p0->d, mp = p0->m + 1, nc = p0->nc;
+  const bool f64 = p0->precision == HL_FP64;
+  std::vector<hl::BatchSource> ent;
+  std::vector<double> val, amp((size_t)n * (size_t)namps, 0.0);
+  for (int i = 0; i < n; ++i) {
+    if (counts[i] < 0) return fail(HL_ERR_ARG, "hl_batch_set_sources: negative count");
+    if (counts[i] == 0) continue;
+    if (!nodes[i] || !values[i]) return fail(HL_ERR_ARG, "hl_batch_set_sources: NULL node or value array");
+    const hl_plan_s* pl = batch->plans[i];
+    if ((int64_t)nc * pl->pnodes > (int64_t)UINT32_MAX)
+      return fail(HL_ERR_UNSUPPORTED, "hl_batch_set_sources: pressure array too large for 32-bit word offsets");
+    int64_t hn = 1;
+    for (int k = 0; k < d; ++k) hn *= pl->K[k];
+    // distinct nodes: each entry's update is a plain read-modify-write
+    std::vector<int64_t> sorted(nodes[i], nodes[i] + counts[i]);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      return fail(HL_ERR_ARG, "hl_batch_set_sources: a shot's source nodes must be distinct");
+    for (int64_t q = 0; q < counts[i]; ++q) {
+      int64_t flat = nodes[i][q];
+      if (flat < 0 || flat >= hn) return fail(HL_ERR_ARG, "hl_batch_set_sources: node index out of range");
+      int64_t j[3] = {0, 0, 0};
+      for (int k = d - 1; k >= 0; --k) {  // host order: j_1 slowest
+        j[k] = flat % pl->K[k];
+        flat /= pl->K[k];
+      }
+      const int64_t dn = j[0] + (int64_t)pl->pext[0] * (j[1] + (int64_t)pl->pext[1] * j[2]);
+      for (int c = 0; c < nc; ++c) {
+        int a[3] = {0, 0, 0}, r = c;
+        for (int k = d - 1; k >= 0; --k) {  // host coefficient order: a_1 slowest
+          a[k] = r % mp;
+          r /= mp;
+        }
+        const int plane = a[0] + mp * (a[1] + mp * a[2]);
+        const double v = values[i][q * nc + c];
+        if (!std::isfinite(v)) return fail(HL_ERR_ARG, "hl_batch_set_sources: values must be finite");
+        ent.push_back(hl::BatchSource{(int32_t)i, (uint32_t)(plane * pl->pnodes + dn)});
+        val.push_back(v);
+      }
+    }
+    if (amps[i])
+      for (int64_t t = 0; t < namps; ++t) {
+        if (!std::isfinite(amps[i][t])) return fail(HL_ERR_ARG, "hl_batch_set_sources: amplitudes must be finite");
+        amp[(size_t)i * namps + t] = amps[i][t];
+      }
+  }
+  const size_t wb = f64 ? 8 : 4;
+  auto words = [&](const std::vector<double>& v) {
+    std::vector<unsigned char> out(std::max<size_t>(v.size(), 1) * wb, 0);
+    for (size_t k = 0; k < v.size(); ++k) {
+      if (f64) {
+        std::memcpy(out.data() + 8 * k, &v[k], 8);
+      } else {
+        const float x = (float)v[k];
+        std::memcpy(out.data() + 4 * k, &x, 4);
+      }
+    }
+    return out;
+  };
+  const std::vector<unsigned char> vw = words(val), aw = words(amp);
+  const int64_t zero = 0;
+  e = hipMalloc(&batch->d_pbase, (size_t)n * sizeof(void*));
+  if (e == hipSuccess) e = hipMalloc(&batch->d_ent, std::max<size_t>(ent.size(), 1) * sizeof(hl::BatchSource));
+  if (e == hipSuccess) e = hipMalloc(&batch->d_val, vw.size());
+  if (e == hipSuccess) e = hipMalloc(&batch->d_amps, aw.size());
+  if (e == hipSuccess) e = hipMalloc((void**)&batch->d_counter, sizeof(int64_t));
+  if (e != hipSuccess) {
+    drop_sources(batch);
+    return fail(HL_ERR_NOMEM, "hl_batch_set_sources: device allocation failed");
+  }
+  if (!ent.empty()) e = hipMemcpy(batch->d_ent, ent.data(), ent.size() * sizeof(hl::BatchSource), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(batch->d_val, vw.data(), vw.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(batch->d_amps, aw.data(), aw.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(batch->d_counter, &zero, sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    drop_sources(batch);
+    return hip_fail(e, "hl_batch_set_sources: upload");
+  }
+  batch->nent = (int64_t)ent.size();
+  batch->namps = namps;
+  batch->src = true;
   return HL_OK;
 }
 
@@ -1367,12 +1491,24 @@ hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_
     e = hipMemcpy(batch->dp, pd.data(), pd.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(batch->du, ud.data(), ud.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hl_batch_step: descriptor upload");
+    if (batch->src) {
+      e = hipMemcpy(batch->d_pbase, p, (size_t)n * sizeof(void*), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(e, "hl_batch_step: source buffer table upload");
+    }
     batch->bp.assign(p, p + n);
     batch->bu.assign(u, u + n);
     batch->var = var;
   }
   auto one_step = [&](hipStream_t st) -> hipError_t {
     hipError_t le = batch->ks.p_batch(batch->dp, n, batch->pblocks, var, st);
+    if (le == hipSuccess && batch->src) {
+      le = batch->ks.batch_src(batch->d_pbase, batch->d_ent, batch->d_val, batch->d_amps, batch->namps,
+                               batch->d_counter, batch->nent, st);
+      if (le == hipSuccess) {
+        hipLaunchKernelGGL(batch_tick, dim3(1), dim3(64), 0, st, batch->d_counter);
+        le = hipGetLastError();
+      }
+    }
     if (le == hipSuccess) le = batch->ks.u_batch(batch->du, n, batch->ublocks, var, st);
     return le;
   };

@@ -48,6 +48,10 @@ typedef hipError_t (*BatchHalfFn)(const void* desc, int n, int blocks, bool var,
 typedef hipError_t (*VarGradFn)(const PlanView&, const void* bar, const void* fwd, double* gk, void* scr,
                                 hipStream_t);
 typedef hipError_t (*VarGatherFn)(const PlanView&, void* bar, const void* scr, hipStream_t);
+// Batched sources: pbase (device array of the shots' pressure buffers), the
+// entries, their values and the amplitude table in the storage word type.
+typedef hipError_t (*BatchSrcFn)(const void* pbase, const void* ent, const void* val, const void* amps,
+                                 int64_t namps, const int64_t* counter, int64_t nent, hipStream_t);
 
 struct KernelSet {
   PHalfFn p_half;
@@ -60,6 +64,7 @@ struct KernelSet {
   VarGatherFn gather_p_var, gather_u_var;
   BatchDescFn batch_desc;
   BatchHalfFn p_batch, u_batch;
+  BatchSrcFn batch_src;  // plain storage only, else NULL
   int table_words;       // TableLayout<D, M>::TOTAL
   int p_off[3];          // offsets of the pressure merged tables, per component
   int u_off;             // offset of the velocity (Q) merged table
@@ -319,6 +324,25 @@ hipError_t launch_batch(const void* desc, int n, int blocks, bool var, hipStream
   }
   return hipGetLastError();
 }
+template <typename W>
+hipError_t launch_batch_src(const void* pbase, const void* ent, const void* val, const void* amps, int64_t namps,
+                            const int64_t* counter, int64_t nent, hipStream_t s) {
+  if (nent <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_source_add<W>, dim3((unsigned)((nent + 255) / 256)), dim3(256), 0, s,
+                     static_cast<W* const*>(pbase), static_cast<const BatchSource*>(ent),
+                     static_cast<const W*>(val), static_cast<const W*>(amps), namps, counter, nent);
+  return hipGetLastError();
+}
+
+template <class S>
+struct SrcLauncher {
+  static constexpr BatchSrcFn fn = nullptr;
+};
+template <typename W>
+struct SrcLauncher<PlainStore<W>> {
+  static constexpr BatchSrcFn fn = &launch_batch_src<W>;
+};
+
 template <int D, class S, int M>
 inline bool make_set(KernelSet* out) {
   fill_layout<D, M>(out);
@@ -337,6 +361,7 @@ inline bool make_set(KernelSet* out) {
   out->batch_desc = &batch_desc<D, M, S>;
   out->p_batch = &launch_batch<D, M, S, true>;
   out->u_batch = &launch_batch<D, M, S, false>;
+  out->batch_src = SrcLauncher<S>::fn;
   // variable kappa: FP64 and FP32 storage, d = 1 (all m) and d = 2 (m <= 3)
   if constexpr (kVarBuilt<D, M, S>) {
     out->p_half_var = &launch_p_var<D, M, S>;

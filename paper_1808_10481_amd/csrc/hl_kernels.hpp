@@ -1269,4 +1269,29 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_batch(const ShotH
     u_half_body<D, M, G>(out, in, tab, sh.g, sh.wscale, sh.ih[0], sh.ih[1], sh.ih[2], blk);
 }
 
+// Sources inside a batch (the source term z = r(t) g(x) of Sec. 4, added by
+// the midpoint rule after each pressure half-step): entry i adds
+// amps[shot][n] * val[i] to word `word` of its shot's pressure array, n the
+// batch's step counter (no source from step namps on).  The entries are the
+// nodes of each shot's (compactly supported) g, so the launch is small.
+struct BatchSource {
+  int32_t shot;
+  uint32_t word;  // plane * nodes + node in the shot's pressure array
+};
+
+template <typename W>
+__global__ void __launch_bounds__(256) batch_source_add(W* const* __restrict__ pbase,
+                                                        const BatchSource* __restrict__ ent,
+                                                        const W* __restrict__ val, const W* __restrict__ amps,
+                                                        int64_t namps, const int64_t* __restrict__ counter,
+                                                        int64_t nent) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nent) return;
+  const int64_t n = counter[0];
+  if (n < 0 || n >= namps) return;
+  const BatchSource e = ent[i];
+  W* q = pbase[e.shot] + e.word;
+  *q = fma(amps[(int64_t)e.shot * namps + n], val[i], *q);
+}
+
 }  // namespace hl

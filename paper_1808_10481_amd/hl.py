@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "HL_OK", 1: "HL_ERR_ARG", 2: "HL_ERR_CFL", 3: "HL_ERR_UNSUPPO
 EXPORTS = ("hl_plan", "hl_plan_destroy", "hl_plan_info", "hl_init", "hl_export", "hl_step",
            "hl_p_half", "hl_u_half", "hl_add_source", "hl_set_kappa", "hl_norms", "hl_adjoint_step",
            "hl_adjoint_step_var", "hl_kappa_grad", "hl_batch_create", "hl_batch_step", "hl_batch_destroy",
-           "hl_last_error")
+           "hl_batch_set_sources", "hl_last_error")
 
 
 class HLProblem(ctypes.Structure):
@@ -73,6 +73,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hl_batch_create": ([ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp)]),
         "hl_batch_step": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i64, vp]),
         "hl_batch_destroy": ([vp]),
+        "hl_batch_set_sources": ([vp, vp, vp, vp, vp, i64]),
         "hl_adjoint_step": ([vp, vp, vp, vp, vp, vp, i64, vp]),
         "hl_adjoint_step_var": ([vp, vp, vp, vp, vp, vp]),
         "hl_kappa_grad": ([vp, vp, vp, ctypes.c_int]),
@@ -329,6 +330,42 @@ class Batch:
         pa = (ctypes.c_void_p * len(ps))(*[p.data_ptr() for p in ps])
         ua = (ctypes.c_void_p * len(us))(*[u.data_ptr() for u in us])
         _check(lib().hl_batch_step(self._h, pa, ua, int(nsteps), _stream_ptr(stream)))
+
+    def set_sources(self, sources, amps=None):
+        """Sources inside the batched launch (hl_batch_set_sources).
+        sources[i]: None, or (nodes, values) with nodes an int array (k, d) of
+        primal node tuples and values a float array (k,) + (m+1,)*d of the
+        scaled data of g_i there; amps[i]: the amplitudes dt r(t_n + dt/2)
+        of shot i for batch steps n = 0, 1, ...  sources=None removes them."""
+        if sources is None:
+            _check(lib().hl_batch_set_sources(self._h, None, None, None, None, 0))
+            return
+        n = len(self.plans)
+        if len(sources) != n or amps is None or len(amps) != n:
+            raise ValueError("one source (or None) and one amplitude array per shot")
+        namps = max([len(a) for a in amps if a is not None] + [0])
+        keep = []
+        counts = (ctypes.c_int64 * n)()
+        nodes = (ctypes.c_void_p * n)()
+        vals = (ctypes.c_void_p * n)()
+        amp = (ctypes.c_void_p * n)()
+        for i, (plan, src) in enumerate(zip(self.plans, sources)):
+            if src is not None:
+                nd = np.asarray(src[0], dtype=np.int64).reshape(-1, plan.d)
+                flat = np.ravel_multi_index(tuple(nd[:, k] for k in range(plan.d)), plan.cells)
+                flat = np.ascontiguousarray(flat, dtype=np.int64)
+                v = np.ascontiguousarray(src[1], dtype=np.float64).reshape(nd.shape[0], -1)
+                if v.shape[1] != plan.info.nc:
+                    raise ValueError("values must hold (m+1)^d coefficients per node")
+                counts[i] = nd.shape[0]
+                nodes[i], vals[i] = flat.ctypes.data, v.ctypes.data
+                keep += [flat, v]
+            if amps[i] is not None:
+                a = np.zeros(namps)
+                a[:len(amps[i])] = np.asarray(amps[i], dtype=np.float64)
+                amp[i] = a.ctypes.data
+                keep.append(a)
+        _check(lib().hl_batch_set_sources(self._h, counts, nodes, vals, amp, namps))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -119,6 +119,25 @@ def gaussian_pulse(d, m, K, length, center, width):
     return outer(fac)
 
 
+def point_source(d, m, K, length, center, width):
+    """A compactly supported stand-in for a point source: the Gaussian of
+    gaussian_pulse with a narrow width, kept on the primal nodes where its data
+    are not negligible (1e-12 of the peak).  Returns (node tuples (k, d), their
+    scaled data (k,) + (m+1,)*d)."""
+    G = gaussian_pulse(d, m, K, length, center, width)
+    mag = np.abs(G).reshape(G.shape[:d] + (-1,)).max(-1)
+    mask = mag > 1e-12 * mag.max()
+    return np.argwhere(mask), G[mask]
+
+
+def ricker(f0, t0):
+    """Ricker wavelet r(t) = (1 - 2 a) exp(-a), a = (pi f0 (t - t0))^2."""
+    def r(t):
+        a = (np.pi * f0 * (t - t0)) ** 2
+        return (1.0 - 2.0 * a) * np.exp(-a)
+    return r
+
+
 def kappa_sines(d, m, K, length, amps, waves, grid="primal"):
     """Taylor data of kappa(x) = 1 + sum_k amps_k sin(2 pi waves_k x_k / length_k)
     (periodic, smooth, positive for sum |amps| < 1) to degree 2m+1 per

@@ -89,3 +89,117 @@ def test_batch_rejects_mixed_problems():
     with pytest.raises(hl.HLError) as ei:
         batch.step([pa, pc], [ua, uc], 1)
     assert ei.value.status == hl.HL_ERR_ARG
+
+
+def _ricker(f0, t0, t_stop):
+    """Ricker wavelet r(t) = (1 - 2 a) exp(-a), a = (pi f0 (t - t0))^2, cut to
+    zero after t_stop."""
+    def r(t):
+        if t > t_stop:
+            return 0.0
+        a = (np.pi * f0 * (t - t0)) ** 2
+        return (1.0 - 2.0 * a) * np.exp(-a)
+    return r
+
+
+def _point_source(d, m, K, centre, width):
+    """A narrow Gaussian g as scaled data, kept on the nodes where it is not
+    negligible: (node tuples, their data, the dense array with zeros elsewhere)."""
+    G = inputs.gaussian_pulse(d, m, K, (1.0,) * d, centre, width)
+    mag = np.abs(G).reshape(G.shape[:d] + (-1,)).max(-1)
+    mask = mag > 1e-12 * mag.max()
+    Gs = np.zeros_like(G)
+    Gs[mask] = G[mask]
+    return np.argwhere(mask), G[mask], Gs
+
+
+@pytest.mark.parametrize("d,m,prec,sizes,var", [
+    (2, 2, "fp64", [(40, 24), (17, 9), (64, 64)], True),
+    (1, 3, "fp32", [(37,), (120,), (2,)], False),
+    (2, 3, "fp32", [(64, 48), (100, 37), (5, 3)], False),
+])
+def test_batch_sources_equal_per_plan_steps_and_oracle(d, m, prec, sizes, var):
+    """Sources inside the batched launch: bit-identical to each plan's own
+    pressure half-step, hl_add_source of the dense g and velocity half-step;
+    the FP64 case also against the oracle's midpoint-rule source step."""
+    import oracle
+    from tolerances import _close, tol
+    _say(f"[batch] sources d={d} m={m} {prec} shots={sizes} var={var}")
+    rng = np.random.default_rng(77 + 10 * d + m)
+    plans, states, kap, srcs, dense, amps, rs = [], [], [], [], [], [], []
+    namps, total = 26, 28
+    for K in sizes:
+        plan = hl.Plan(d, m, K, cfl=float(rng.uniform(0.3, 0.9)), c=float(rng.uniform(0.8, 1.8)), precision=prec)
+        kk = None
+        if var:
+            a = tuple(rng.uniform(0.05, 0.2, d))
+            w = tuple(int(x) for x in rng.integers(1, 3, d))
+            kk = (inputs.kappa_sines(d, m, K, (1.0,) * d, a, w, "primal"),
+                  inputs.kappa_sines(d, m, K, (1.0,) * d, a, w, "dual"))
+            plan.set_kappa(*kk)
+        p, u = plan.alloc()
+        plan.init(p, u, inputs.random_data(rng, d, m, K) * 0.1, inputs.random_data(rng, d, m, K, ncomp=d) * 0.1)
+        nodes, vals, Gs = _point_source(d, m, K, tuple(rng.uniform(0.2, 0.8, d)), 2.5 / max(K))
+        f0 = float(rng.uniform(5.0, 15.0))
+        r = _ricker(f0, 1.2 / f0, namps * plan.dt)
+        plans.append(plan)
+        states.append((p, u))
+        kap.append(kk)
+        srcs.append((nodes, vals))
+        dense.append(Gs)
+        rs.append(r)
+        amps.append(np.array([plan.dt * r((n + 0.5) * plan.dt) for n in range(namps)]))
+    init = [plan.export(p, u) for plan, (p, u) in zip(plans, states)]
+    ref = [(p.clone(), u.clone()) for p, u in states]
+    gbuf = [plan.source_buffer(G) for plan, G in zip(plans, dense)]
+    batch = hl.Batch(plans)
+    batch.set_sources(srcs, amps)
+    t = 0
+    for n in (3, 20, 5):                      # eager, graph replay + tail, past the last amplitude
+        batch.step([p for p, _ in states], [u for _, u in states], n)
+        for k in range(n):
+            for i, (plan, (p, u)) in enumerate(zip(plans, ref)):
+                plan.p_half(p, u)
+                if t + k < namps:
+                    plan.add_source(p, gbuf[i], amps[i][t + k])
+                plan.u_half(u, p)
+        t += n
+        torch.cuda.synchronize()
+        for (p, u), (pr, ur) in zip(states, ref):
+            assert torch.equal(p, pr) and torch.equal(u, ur)
+    assert t == total
+    if prec == "fp64":
+        for i in range(len(plans)):
+            plan = plans[i]
+            prob = oracle.Problem(d, m, tuple(sizes[i]), (1.0,) * d, plan.dt, plan.kappa)
+            kw = {} if kap[i] is None else {"Kp": kap[i][0], "Ku": kap[i][1]}
+            if kap[i] is not None:
+                prob = oracle.Problem(d, m, tuple(sizes[i]), (1.0,) * d, plan.dt, 1.0)
+            Po, Uo = oracle.step_with_source(prob, init[i][0], init[i][1], dense[i], rs[i], 0.0, total, **kw)
+            Pg, Ug = plan.export(*states[i])
+            _close(Pg, Po, *tol("fp64", d, m))
+            _close(Ug, Uo, *tol("fp64", d, m))
+    batch.set_sources(None)                    # removed: plain batched steps again
+    batch.step([p for p, _ in states], [u for _, u in states], 2)
+    for plan, (p, u) in zip(plans, ref):
+        plan.step(p, u, 2)
+    torch.cuda.synchronize()
+    for (p, u), (pr, ur) in zip(states, ref):
+        assert torch.equal(p, pr) and torch.equal(u, ur)
+    batch.close()
+
+
+def test_batch_sources_reject_bad_input():
+    a = hl.Plan(2, 1, (8, 6), precision="fp32")
+    batch = hl.Batch([a])
+    nodes = np.array([[1, 2], [1, 2]])
+    with pytest.raises(hl.HLError) as ei:
+        batch.set_sources([(nodes, np.ones((2, 2, 2)))], [np.ones(3)])
+    assert ei.value.status == hl.HL_ERR_ARG
+    c = hl.Plan(2, 1, (8, 6), precision="fp32_comp")
+    bc = hl.Batch([c])
+    with pytest.raises(hl.HLError) as ei:
+        bc.set_sources([(nodes[:1], np.ones((1, 2, 2)))], [np.ones(3)])
+    assert ei.value.status == hl.HL_ERR_UNSUPPORTED
+    batch.close()
+    bc.close()
