@@ -116,6 +116,9 @@ typedef struct {
   int32_t word_bytes;   /* 8 (FP64), 4 (FP32) or 2 (FP32_COMP) */
   int64_t p_words;      /* words of p: nc * (device p nodes), times 3 for FP32_COMP */
   int64_t u_words;      /* words of u: d * nc * (device u nodes, ghosts included), times 3 for FP32_COMP */
+  int32_t tile[2];      /* tile (= workgroup) extents in x and y of the half-step launches */
+  int32_t ygroup;       /* 3D: tile rows per group in the tile order (0 otherwise) */
+  int32_t reserved;
 } hl_info;
 
 typedef struct hl_plan_s* hl_plan_t;
@@ -227,6 +230,21 @@ hl_status hl_norms(hl_plan_t plan, const void* p, const void* u, double* out);
  * Asynchronous. */
 hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* p,
                           const void* u, void* grad_kappa, int64_t nsteps, void* stream);
+
+/* Launch shape of the half-steps (not part of the paper: the work
+ * decomposition).  Every output node is computed by one work-item with the
+ * same arithmetic whatever the tile, so results do not depend on it.
+ * hl_set_tile: tiles of tx x ty nodes (tx a multiple of 32 in [32, 256],
+ * ty >= 1, 1 in 1D, 64 <= tx ty <= 256; tx = ty = 0: the default 64 x 4, or
+ * 256 in 1D) and, in 3D, tile rows per group in the XCD-banded tile order
+ * (ygroup, 0: the default 2).  hl_tune: times `reps` steps (after one warm-up
+ * step) for each candidate shape (1D: 256, 128, 64; 2D/3D: 64x4, 64x2, 64x1,
+ * 128x2, 128x1, 256x1, 32x8, in 3D each with y-groups 1, 2, 4) on copies of
+ * (p, u) in buffers of its own, keeps the fastest and reports it through
+ * hl_plan_info; p and u are not modified.  Batches launch every shot with the
+ * default shape.  Synchronous. */
+hl_status hl_set_tile(hl_plan_t plan, int32_t tx, int32_t ty, int32_t ygroup);
+hl_status hl_tune(hl_plan_t plan, const void* p, const void* u, int32_t reps, void* stream);
 
 /* Variable-kappa adjoint (plans with hl_set_kappa; Sec. 4, "Smoothly varying
  * wave speed", differentiated): one transposed step applied in place to the

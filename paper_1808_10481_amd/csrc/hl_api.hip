@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <functional>
 #include <cmath>
 #include <cstdio>
@@ -826,9 +827,8 @@ hl_status ensure_var_gradient(hl_plan_s* pl) {
 // Launch grid of one half-step: updates K[] nodes stored at index j + ooff
 // of an array with extents oext, corners from an array with extents sext
 // (lower corner at j + soff).
-bool make_grid(const hl_plan_s* pl, const int32_t* K, const int32_t* oext, int32_t ooff, const int32_t* sext,
-               int32_t soff, int64_t onodes, int64_t snodes, hl::Grid* g) {
-  const int* tile = pl->ks.tile;
+bool make_grid(const hl_plan_s* pl, const int32_t* tile, int32_t ygroup, const int32_t* K, const int32_t* oext,
+               int32_t ooff, const int32_t* sext, int32_t soff, int64_t onodes, int64_t snodes, hl::Grid* g) {
   int64_t tiles = 1;
   for (int k = 0; k < 3; ++k) {
     g->K[k] = K[k];
@@ -840,15 +840,41 @@ bool make_grid(const hl_plan_s* pl, const int32_t* K, const int32_t* oext, int32
   if (tiles > (int64_t)INT32_MAX / 2) return false;
   g->tiles = (int32_t)tiles;
   g->per_xcd = (int32_t)((tiles + hl::kXcds - 1) / hl::kXcds);
-  // 3D: tile numbering x, then y in groups of kYGroup3 tile rows, then z
+  // 3D: tile numbering x, then y in groups of `ygroup` tile rows, then z
   // (z-neighbour planes reused from L2); 1D/2D: plain row-major
-  g->ygroup = pl->d == 3 ? std::min<int32_t>(kYGroup3, g->nt[1]) : g->nt[1];
+  g->ygroup = pl->d == 3 ? std::max<int32_t>(1, std::min<int32_t>(ygroup, g->nt[1])) : g->nt[1];
   g->ooff = ooff;
   g->soff = soff;
+  g->tx = tile[0];
+  g->ty = tile[1];
   g->pad = 0;
   g->onodes = onodes;
   g->snodes = snodes;
   return true;
+}
+
+// The two half-step grids of a plan for a tile shape (tx, ty) and 3D y-group:
+// p half-step: primal nodes (walls: K+1, on the walls too) from dual corners
+// q = j - 1 + e, stored at q + uoff; u half-step: dual nodes from primal
+// corners j = q + e.
+bool build_grids(const hl_plan_s* pl, int32_t tx, int32_t ty, int32_t ygroup, hl::Grid* gp, hl::Grid* gu) {
+  int32_t Kp[3], Ku[3];
+  for (int k = 0; k < 3; ++k) {
+    Kp[k] = pl->pext[k];
+    Ku[k] = pl->K[k];
+  }
+  const int32_t tile[3] = {tx, ty, 1};
+  return make_grid(pl, tile, ygroup, Kp, pl->pext, 0, pl->uext, pl->uoff - 1, pl->pnodes, pl->unodes, gp) &&
+         make_grid(pl, tile, ygroup, Ku, pl->uext, pl->uoff, pl->pext, 0, pl->unodes, pl->pnodes, gu);
+}
+
+// Tile shapes a plan may use: x extent a multiple of 32 (whole or half
+// wavefronts along the coalesced axis), 64..256 work-items.
+bool valid_tile(int d, int32_t tx, int32_t ty) {
+  if (tx < 32 || tx > 256 || tx % 32 != 0 || ty < 1) return false;
+  if (d == 1 && ty != 1) return false;
+  const int32_t n = tx * ty;
+  return n >= 64 && n <= 256;
 }
 
 }  // namespace
@@ -929,21 +955,9 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
     delete pl;
     return fail(HL_ERR_UNSUPPORTED, "hl_plan: (d, m, precision) not built");
   }
-  {
-    // p half-step: primal nodes (walls: K+1, on the walls too) from dual
-    // corners q = j - 1 + e, stored at q + uoff; u half-step: dual nodes from
-    // primal corners j = q + e
-    int32_t Kp[3], Ku[3];
-    for (int k = 0; k < 3; ++k) {
-      Kp[k] = pl->pext[k];
-      Ku[k] = pl->K[k];
-    }
-    const bool ok_p = make_grid(pl, Kp, pl->pext, 0, pl->uext, pl->uoff - 1, pl->pnodes, pl->unodes, &pl->gp);
-    const bool ok_u = make_grid(pl, Ku, pl->uext, pl->uoff, pl->pext, 0, pl->unodes, pl->pnodes, &pl->gu);
-    if (!ok_p || !ok_u) {
-      delete pl;
-      return fail(HL_ERR_UNSUPPORTED, "hl_plan: grid too large for the launch");
-    }
+  if (!build_grids(pl, pl->ks.tile[0], pl->ks.tile[1], kYGroup3, &pl->gp, &pl->gu)) {
+    delete pl;
+    return fail(HL_ERR_UNSUPPORTED, "hl_plan: grid too large for the launch");
   }
   std::vector<double> tab;
   hl_status st = build_tables(pl, tab, WeightMode{pl->dt, false});
@@ -1028,6 +1042,10 @@ hl_status hl_plan_info(hl_plan_t plan, hl_info* out) {
   out->nc = plan->nc;
   out->word_bytes = plan->word_bytes;
   out->p_words = (int64_t)plan->words_per_coef * plan->nc * plan->pnodes;
+  out->tile[0] = plan->gp.tx;
+  out->tile[1] = plan->gp.ty;
+  out->ygroup = plan->d == 3 ? plan->gp.ygroup : 0;
+  out->reserved = 0;
   out->u_words = (int64_t)plan->words_per_coef * plan->d * plan->nc * plan->unodes;
   return HL_OK;
 }
@@ -1257,6 +1275,89 @@ hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* 
   return e == hipSuccess ? HL_OK : hip_fail(e, "hl_adjoint_step: gradient launch");
 }
 
+hl_status hl_set_tile(hl_plan_t plan, int32_t tx, int32_t ty, int32_t ygroup) {
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_set_tile");
+  if (st != HL_OK) return st;
+  if (tx == 0 && ty == 0) {
+    tx = plan->ks.tile[0];
+    ty = plan->ks.tile[1];
+  }
+  if (!valid_tile(plan->d, tx, ty))
+    return fail(HL_ERR_ARG, "hl_set_tile: tx a multiple of 32 in [32, 256], ty >= 1 (1 in 1D), 64 <= tx ty <= 256");
+  if (ygroup < 0) return fail(HL_ERR_ARG, "hl_set_tile: ygroup must be >= 0");
+  hl::Grid gp, gu;
+  if (!build_grids(plan, tx, ty, ygroup == 0 ? kYGroup3 : ygroup, &gp, &gu))
+    return fail(HL_ERR_UNSUPPORTED, "hl_set_tile: grid too large for the launch");
+  hipError_t e = hipDeviceSynchronize();  // launches in flight keep their own grid copies; graphs are rebuilt
+  if (e != hipSuccess) return hip_fail(e, "hl_set_tile: pending work failed");
+  drop_graph(plan);
+  plan->gp = gp;
+  plan->gu = gu;
+  return HL_OK;
+}
+
+hl_status hl_tune(hl_plan_t plan, const void* p, const void* u, int32_t reps, void* stream) {
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_tune");
+  if (st != HL_OK) return st;
+  if (!p || !u || p == u) return fail(HL_ERR_ARG, "hl_tune: p and u must be distinct non-NULL buffers");
+  if (reps < 1) return fail(HL_ERR_ARG, "hl_tune: reps must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t pbytes = (size_t)plan->words_per_coef * plan->nc * plan->pnodes * plan->word_bytes;
+  const size_t ubytes = (size_t)plan->words_per_coef * plan->d * plan->nc * plan->unodes * plan->word_bytes;
+  void *tp = nullptr, *tu = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&tp, pbytes);
+  if (e == hipSuccess) e = hipMalloc(&tu, ubytes);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipMemcpyAsync(tp, p, pbytes, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(tu, u, ubytes, hipMemcpyDeviceToDevice, s);
+  // candidates: (tx, ty, y-group); the plan's steps run on copies of (p, u)
+  std::vector<std::array<int32_t, 3>> cand;
+  if (plan->d == 1) {
+    for (int32_t tx : {256, 128, 64}) cand.push_back({tx, 1, 1});
+  } else {
+    const int32_t shapes[][2] = {{64, 4}, {64, 2}, {64, 1}, {128, 2}, {128, 1}, {256, 1}, {32, 8}};
+    for (const auto& sh : shapes)
+      for (int32_t yg : plan->d == 3 ? std::vector<int32_t>{1, 2, 4} : std::vector<int32_t>{1})
+        cand.push_back({sh[0], sh[1], yg});
+  }
+  float best = -1.0f;
+  std::array<int32_t, 3> pick = {plan->ks.tile[0], plan->ks.tile[1], kYGroup3};
+  for (size_t c = 0; c < cand.size() && e == hipSuccess; ++c) {
+    hl_plan_s trial = *plan;  // grids only; no ownership is taken or released
+    if (!build_grids(plan, cand[c][0], cand[c][1], cand[c][2], &trial.gp, &trial.gu)) continue;
+    const hl::PlanView v = view(&trial);
+    auto one = [&]() -> hipError_t {
+      hipError_t le = hipSuccess;
+      if (plan->walls) le = plan->ks.ghost(v, tu, s);
+      if (le == hipSuccess) le = p_fn(plan)(v, tp, tu, s);
+      if (le == hipSuccess) le = u_fn(plan)(v, tu, tp, 1.0, s);
+      return le;
+    };
+    e = one();  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int32_t r = 0; r < reps && e == hipSuccess; ++r) e = one();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && (best < 0.0f || ms < best)) {
+      best = ms;
+      pick = cand[c];
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (void* q : {tp, tu})
+    if (q) (void)hipFree(q);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "hl_tune: trial steps");
+  return hl_set_tile(plan, pick[0], pick[1], pick[2]);
+}
+
 hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const void* p_next, const void* u_prev,
                               void* stream) {
   g_last_error.clear();
@@ -1473,7 +1574,12 @@ hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_
     std::vector<hl::PlanView> views((size_t)n);
     std::vector<hl::BatchShot> shots((size_t)n);
     for (int i = 0; i < n; ++i) {
-      views[i] = view(batch->plans[i]);
+      // the batched launch has one workgroup shape: every shot uses the
+      // kernel set's default tile, whatever its plan was tuned to
+      const hl_plan_s* pl = batch->plans[i];
+      views[i] = view(pl);
+      if (!build_grids(pl, batch->ks.tile[0], batch->ks.tile[1], kYGroup3, &views[i].gp, &views[i].gu))
+        return fail(HL_ERR_UNSUPPORTED, "hl_batch_step: grid too large for the launch");
       shots[i] = hl::BatchShot{&views[i], p[i], u[i]};
     }
     std::vector<unsigned char> pd, ud;

@@ -117,6 +117,9 @@ inline dim3 block_shape() {
   return dim3(TileShape<D>::X, TileShape<D>::Y, 1);
 }
 
+// Workgroup shape of a grid (its tile).
+inline dim3 block_shape(const Grid& g) { return dim3((unsigned)g.tx, (unsigned)g.ty, 1); }
+
 inline dim3 grid_shape(const Grid& g) { return dim3((unsigned)(g.per_xcd * kXcds), 1, 1); }
 
 template <int D, int M, class S>
@@ -127,9 +130,9 @@ hipError_t launch_p(const PlanView& pv, void* p, const void* u, hipStream_t s) {
   const typename S::View vp = S::make(p, 1, NC, g.onodes);
   const typename S::View vu = S::make(u, D, NC, g.snodes);
   if constexpr (D == 3)
-    hipLaunchKernelGGL((p_half_3d<M, S>), grid_shape(g), block_shape<D>(), 0, s, vp, vu, (const T*)pv.tab, g);
+    hipLaunchKernelGGL((p_half_3d<M, S>), grid_shape(g), block_shape(g), 0, s, vp, vu, (const T*)pv.tab, g);
   else
-    hipLaunchKernelGGL((p_half_kernel<D, M, S>), grid_shape(g), block_shape<D>(), 0, s, vp, vu, (const T*)pv.tab,
+    hipLaunchKernelGGL((p_half_kernel<D, M, S>), grid_shape(g), block_shape(g), 0, s, vp, vu, (const T*)pv.tab,
                        g);
   return hipGetLastError();
 }
@@ -142,10 +145,10 @@ hipError_t launch_u(const PlanView& pv, void* u, const void* p, double wscale, h
   const typename S::View vu = S::make(u, D, NC, g.onodes);
   const typename S::View vp = S::make(p, 1, NC, g.snodes);
   if constexpr (D == 3)
-    hipLaunchKernelGGL((u_half_3d<M, S>), grid_shape(g), block_shape<D>(), 0, s, vu, vp, (const T*)pv.tab, g,
+    hipLaunchKernelGGL((u_half_3d<M, S>), grid_shape(g), block_shape(g), 0, s, vu, vp, (const T*)pv.tab, g,
                        (T)wscale, (T)pv.ih[0], (T)pv.ih[1], (T)pv.ih[2]);
   else
-    hipLaunchKernelGGL((u_half_kernel<D, M, S>), grid_shape(g), block_shape<D>(), 0, s, vu, vp, (const T*)pv.tab,
+    hipLaunchKernelGGL((u_half_kernel<D, M, S>), grid_shape(g), block_shape(g), 0, s, vu, vp, (const T*)pv.tab,
                        g, (T)wscale, (T)pv.ih[0], (T)pv.ih[1], (T)pv.ih[2]);
   return hipGetLastError();
 }
@@ -174,7 +177,7 @@ hipError_t launch_adjoint(const PlanView& pv, void* out, const void* in, hipStre
   const Grid& g = PTYPE ? pv.gp : pv.gu;
   const typename S::View vo = S::make(out, PTYPE ? 1 : D, NC, g.onodes);
   const typename S::View vi = S::make(in, PTYPE ? D : 1, NC, g.snodes);
-  hipLaunchKernelGGL((adjoint_half<D, M, S, PTYPE>), grid_shape(g), block_shape<D>(), 0, s, vo, vi,
+  hipLaunchKernelGGL((adjoint_half<D, M, S, PTYPE>), grid_shape(g), block_shape(g), 0, s, vo, vi,
                      (const T*)pv.adj_tab, g);
   return hipGetLastError();
 }
@@ -193,7 +196,7 @@ template <int D, int M, class S>
 hipError_t launch_p_var(const PlanView& pv, void* p, const void* u, hipStream_t s) {
   constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
   const Grid& g = pv.gp;
-  hipLaunchKernelGGL((p_half_var<D, M, S>), grid_shape(g), block_shape<D>(), 0, s, S::make(p, 1, NC, g.onodes),
+  hipLaunchKernelGGL((p_half_var<D, M, S>), grid_shape(g), block_shape(g), 0, s, S::make(p, 1, NC, g.onodes),
                      S::make(u, D, NC, g.snodes), S::make(pv.kap_p, 1, NP, g.onodes), g, var_args<S>(pv));
   return hipGetLastError();
 }
@@ -203,7 +206,7 @@ hipError_t launch_u_var(const PlanView& pv, void* u, const void* p, double wscal
   using T = typename S::C;
   constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
   const Grid& g = pv.gu;
-  hipLaunchKernelGGL((u_half_var<D, M, S>), grid_shape(g), block_shape<D>(), 0, s, S::make(u, D, NC, g.onodes),
+  hipLaunchKernelGGL((u_half_var<D, M, S>), grid_shape(g), block_shape(g), 0, s, S::make(u, D, NC, g.onodes),
                      S::make(p, 1, NC, g.snodes), S::make(pv.kap_u, 1, NP, g.onodes), g, var_args<S>(pv),
                      (T)wscale);
   return hipGetLastError();
@@ -214,7 +217,7 @@ hipError_t launch_grad_p_var(const PlanView& pv, const void* pb, const void* u, 
                              hipStream_t s) {
   constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
   const Grid& g = pv.gp;
-  hipLaunchKernelGGL((grad_p_var<D, M, S>), grid_shape(g), block_shape<D>(), 0, s, S::make(pb, 1, NC, g.onodes),
+  hipLaunchKernelGGL((grad_p_var<D, M, S>), grid_shape(g), block_shape(g), 0, s, S::make(pb, 1, NC, g.onodes),
                      S::make(u, D, NC, g.snodes), S::make(pv.kap_p, 1, NP, g.onodes), gk,
                      S::make(scr, D, NP, g.onodes), g, var_args<S>(pv));
   return hipGetLastError();
@@ -225,7 +228,7 @@ hipError_t launch_grad_u_var(const PlanView& pv, const void* ub, const void* p, 
                              hipStream_t s) {
   constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
   const Grid& g = pv.gu;
-  hipLaunchKernelGGL((grad_u_var<D, M, S>), grid_shape(g), block_shape<D>(), 0, s, S::make(ub, D, NC, g.onodes),
+  hipLaunchKernelGGL((grad_u_var<D, M, S>), grid_shape(g), block_shape(g), 0, s, S::make(ub, D, NC, g.onodes),
                      S::make(p, 1, NC, g.snodes), S::make(pv.kap_u, 1, NP, g.onodes), gk,
                      S::make(scr, 1, NP, g.onodes), g, var_args<S>(pv));
   return hipGetLastError();
@@ -236,7 +239,7 @@ template <int D, int M, class S>
 hipError_t launch_gather_p_var(const PlanView& pv, void* pb, const void* scr, hipStream_t s) {
   constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
   const Grid& g = pv.gp;
-  hipLaunchKernelGGL((var_adjoint_gather<D, M, S, true>), grid_shape(g), block_shape<D>(), 0, s,
+  hipLaunchKernelGGL((var_adjoint_gather<D, M, S, true>), grid_shape(g), block_shape(g), 0, s,
                      S::make(pb, 1, NC, g.onodes), S::make(scr, 1, NP, g.snodes), g);
   return hipGetLastError();
 }
@@ -246,7 +249,7 @@ template <int D, int M, class S>
 hipError_t launch_gather_u_var(const PlanView& pv, void* ub, const void* scr, hipStream_t s) {
   constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
   const Grid& g = pv.gu;
-  hipLaunchKernelGGL((var_adjoint_gather<D, M, S, false>), grid_shape(g), block_shape<D>(), 0, s,
+  hipLaunchKernelGGL((var_adjoint_gather<D, M, S, false>), grid_shape(g), block_shape(g), 0, s,
                      S::make(ub, D, NC, g.onodes), S::make(scr, D, NP, g.snodes), g);
   return hipGetLastError();
 }

@@ -73,6 +73,7 @@ struct Grid {
   int32_t oext[3];    // output array extents
   int32_t soff;       // lower corner of node j at index j + soff (-1 or 0)
   int32_t sext[3];    // corner (source) array extents
+  int32_t tx, ty;     // tile extents in x and y = the workgroup shape (tx * ty <= 256)
   int32_t pad;
   int64_t onodes;     // output array nodes (plane size)
   int64_t snodes;     // source array nodes (plane size)
@@ -124,8 +125,8 @@ __device__ __forceinline__ bool node_of_block(const Grid& g, int blk, int32_t* j
     ty = grp * g.ygroup + rem % gy;
     tz = rem / gy;
   }
-  j[0] = tx * TileShape<D>::X + threadIdx.x;
-  j[1] = ty * TileShape<D>::Y + threadIdx.y;
+  j[0] = tx * g.tx + threadIdx.x;
+  j[1] = ty * g.ty + threadIdx.y;
   j[2] = tz;
   return j[0] < g.K[0] && j[1] < g.K[1] && j[2] < g.K[2];
 }

@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "HL_OK", 1: "HL_ERR_ARG", 2: "HL_ERR_CFL", 3: "HL_ERR_UNSUPPO
 
 # Every symbol include/hl.h declares.
 EXPORTS = ("hl_plan", "hl_plan_destroy", "hl_plan_info", "hl_init", "hl_export", "hl_step",
-           "hl_p_half", "hl_u_half", "hl_add_source", "hl_set_kappa", "hl_norms", "hl_adjoint_step",
+           "hl_p_half", "hl_u_half", "hl_add_source", "hl_set_kappa", "hl_norms", "hl_set_tile", "hl_tune",
+           "hl_adjoint_step",
            "hl_adjoint_step_var", "hl_kappa_grad", "hl_batch_create", "hl_batch_step", "hl_batch_destroy",
            "hl_batch_set_sources", "hl_last_error")
 
@@ -43,7 +44,8 @@ class HLProblem(ctypes.Structure):
 class HLInfo(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("nu", ctypes.c_double), ("nodes", ctypes.c_int64),
                 ("nc", ctypes.c_int32), ("word_bytes", ctypes.c_int32), ("p_words", ctypes.c_int64),
-                ("u_words", ctypes.c_int64)]
+                ("u_words", ctypes.c_int64), ("tile", ctypes.c_int32 * 2), ("ygroup", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class HLError(RuntimeError):
@@ -76,6 +78,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hl_batch_set_sources": ([vp, vp, vp, vp, vp, i64]),
         "hl_adjoint_step": ([vp, vp, vp, vp, vp, vp, i64, vp]),
         "hl_adjoint_step_var": ([vp, vp, vp, vp, vp, vp]),
+        "hl_set_tile": ([vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+        "hl_tune": ([vp, vp, vp, ctypes.c_int32, vp]),
         "hl_kappa_grad": ([vp, vp, vp, ctypes.c_int]),
     }
     for name, args in sig.items():
@@ -144,6 +148,25 @@ class Plan:
     @property
     def dt(self):
         return self.info.dt
+
+    def _refresh_info(self):
+        info = HLInfo()
+        _check(lib().hl_plan_info(self._h, ctypes.byref(info)))
+        self.info = info
+
+    def set_tile(self, tx=0, ty=0, ygroup=0):
+        """Tile (workgroup) shape of the half-step launches (hl_set_tile); 0s: defaults."""
+        _check(lib().hl_set_tile(self._h, int(tx), int(ty), int(ygroup)))
+        self._refresh_info()
+
+    def tune(self, p, u, reps=3, stream=None):
+        """Pick the fastest tile shape by timing steps on copies of (p, u)
+        (hl_tune); returns (tx, ty, ygroup)."""
+        self._check_buf(p, u)
+        _check(lib().hl_tune(self._h, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(u.data_ptr()), int(reps),
+                             _stream_ptr(stream)))
+        self._refresh_info()
+        return (self.info.tile[0], self.info.tile[1], self.info.ygroup)
 
     def close(self):
         if getattr(self, "_h", None):
