@@ -241,24 +241,30 @@ def run_varkappa(hl, torch, steps, K=1024, m=3):
 
 def run_batch(hl, torch, steps, nshots=32, m=3):
     """Batched shots: `nshots` periodic square grids with seeded sizes in
-    [256, 1024] (the batched configuration's size mix), m=3 FP32, per-shot wave
-    speed c in [1, 3] and standing-mode data; `steps` steps advanced (a) with
-    one launch per half-step for all shots (hl_batch_step) and (b) shot by
-    shot with hl_step.  Constant kappa per shot (per-node kappa data for 32
-    grids of this size would take ~15 GB of host memory to generate)."""
+    [256, 1024] (the batched configuration's size mix), m=3 FP32, each with
+    its own seeded layered medium c(y) in [1, 3] (three smoothed tanh steps,
+    per-node kappa data on both grids) and a Ricker point source, starting at
+    rest; `steps` steps advanced (a) with one launch per half-step for all
+    shots (hl_batch_step, sources inside the batched step) and (b) shot by
+    shot with hl_step (no source)."""
     from paper_1808_10481_amd import inputs
     rng = np.random.default_rng(6)
     sizes = [int(k) for k in rng.integers(256, 1025, nshots)]
-    speeds = rng.uniform(1.0, 3.0, nshots)
-    plans, states = [], []
-    for K, c in zip(sizes, speeds):
-        plan = hl.Plan(2, m, (K, K), cfl=0.5, c=float(c), precision="fp32")
-        P0, U0 = inputs.standing_mode(2, m, (K, K), (1.0, 1.0), tuple(int(w) for w in rng.integers(1, 9, 2)),
-                                      0.0, plan.dt / 2, kappa=float(c) ** 2)
+    plans, states, media = [], [], []
+    for K in sizes:
+        up = rng.uniform(0.3, 1.0, 2)
+        med = inputs.layered_speed(1.0, [up[0], up[1], -(up[0] + up[1])], np.sort(rng.uniform(0.15, 0.85, 3)),
+                                   float(rng.uniform(0.02, 0.05)))
+        cmax = 1.0 + up[0] + up[1]
+        plan = hl.Plan(2, m, (K, K), cfl=0.5, c=float(cmax), precision="fp32")
+        plan.set_kappa(inputs.kappa_layers(2, m, (K, K), (1.0, 1.0), med, "primal"),
+                       inputs.kappa_layers(2, m, (K, K), (1.0, 1.0), med, "dual"))
         p, u = plan.alloc()
-        plan.init(p, u, P0, U0)
+        p.zero_()
+        u.zero_()
         plans.append(plan)
         states.append((p, u))
+        media.append(med)
     cells = sum(K * K for K in sizes)
     batch = hl.Batch(plans)
     ps, us = [p for p, _ in states], [u for _, u in states]
@@ -298,7 +304,8 @@ def run_batch(hl, torch, steps, nshots=32, m=3):
             "speedup_batched_vs_per_shot": ts / tb, "steps": steps,
             "note": "per-shot stepping has no source term; the batched steps include the Ricker sources",
             "config": {"workload": f"batched_shots_2d {nshots} shots m={m} fp32, sizes seeded in [256, 1024]^2, "
-                                   "c per shot in [1, 3], one Ricker point source per shot (f0 in [5, 15])",
+                                   "layered c(y) in [1, 3] per shot (variable kappa), one Ricker point source per "
+                                   "shot (f0 in [5, 15])",
                        "cells": cells, "sizes": sizes, "source_nodes": nsrc}}
 
 

@@ -162,6 +162,58 @@ def kappa_sines(d, m, K, length, amps, waves, grid="primal"):
     return out
 
 
+def scaled_tanh(s, w, h, n):
+    """Rows k = 0..n of (h^k / k!) d^k/ds^k tanh(s / w), by the Taylor-series
+    recurrence of T' = 1 - T^2: with T = sum_k t_k u^k about u = s/w,
+    (k + 1) t_{k+1} = [k = 0] - sum_{j <= k} t_j t_{k-j}; the scaled
+    coefficient of order k is t_k (h/w)^k."""
+    t = [np.tanh(np.asarray(s, dtype=np.float64) / w)]
+    for k in range(n):
+        conv = sum(t[j] * t[k - j] for j in range(k + 1))
+        t.append(((1.0 if k == 0 else 0.0) - conv) / (k + 1))
+    return np.stack([t[k] * (h / w) ** k for k in range(n + 1)], axis=-1)
+
+
+def _series_mul(a, b):
+    """Truncated product of Taylor rows (last axis = order, same scaling)."""
+    n = a.shape[-1]
+    out = np.zeros(np.broadcast_shapes(a.shape, b.shape))
+    for i in range(n):
+        out[..., i:] += a[..., i:i + 1] * b[..., :n - i]
+    return out
+
+
+def layered_speed(c0, jumps, positions, width):
+    """A smooth layered medium in the last coordinate y:
+    c(y) = c0 + sum_i jumps_i (1 + tanh((y - y_i) / width)) / 2; jumps summing
+    to zero make it periodic on [0, 1) up to the tanh tails."""
+    return dict(c0=float(c0), jumps=[float(v) for v in jumps], positions=[float(v) for v in positions],
+                width=float(width))
+
+
+def kappa_layers(d, m, K, length, medium, grid="primal"):
+    """Taylor data of kappa = c(y)^2 (c from layered_speed, y = x_d) to degree
+    2m+1 per variable about the primal or dual nodes: (K,)*d + (2m+2,)*d; the
+    coefficients of order > 0 in the other variables are zero."""
+    K = tuple(int(k) for k in K)
+    n = 2 * m + 2
+    L = float(length[d - 1])
+    h = L / K[d - 1]
+    off = 0.0 if grid == "primal" else 0.5
+    y = (np.arange(K[d - 1]) + off) * h
+    c = np.zeros((K[d - 1], n))
+    c[:, 0] = medium["c0"]
+    for dj, yi in zip(medium["jumps"], medium["positions"]):
+        th = scaled_tanh(y - yi * L, medium["width"] * L, h, n - 1)
+        c[:, 0] += 0.5 * dj
+        c += 0.5 * dj * th
+    kap = _series_mul(c, c)                                             # (K_d, n)
+    out = np.zeros(K + (n,) * d)
+    idx = (slice(None),) * d + (0,) * (d - 1) + (slice(None),)
+    out[idx] = kap.reshape((1,) * (d - 1) + (K[d - 1], n))
+    return out
+
+
 def random_data(rng, d, m, K, ncomp=None):
     """Uniform[-1,1] scaled data (any data is valid input to the linear scheme)."""
     shape = tuple(int(k) for k in K) + (m + 1,) * d
