@@ -581,30 +581,37 @@ def u_update_cells_var(prob: Problem, u_vals, p_corners, kap, dt=None, weight_sc
 
 
 def p_half_var(prob: Problem, P, U, Kp, nodes=None, dt=None):
-    """Pressure half-step with kappa data Kp, (K,)*d + (2m+2,)*d on the primal
-    nodes (periodic)."""
-    d, K = prob.d, tuple(prob.K)
+    """Pressure half-step with kappa data Kp, p_nodes() + (2m+2,)*d on the
+    primal nodes; with walls the dual corners include the ghost layer of U as
+    in p_half (the mirror rule does not involve kappa)."""
+    d = prob.d
     full = nodes is None
-    nodes = _all_nodes(K) if full else np.asarray(nodes, dtype=np.int64).reshape(-1, d)
+    nodes = _all_nodes(prob.p_nodes()) if full else np.asarray(nodes, dtype=np.int64).reshape(-1, d)
+    if prob.walls:
+        Ug, off, wrap = ghost_pad(prob, U), 0, None     # padded index q + 1
+    else:
+        Ug, off, wrap = U, -1, tuple(prob.K)
     res = np.empty((nodes.shape[0],) + P.shape[d:], dtype=np.float64)
     for a in range(0, nodes.shape[0], _CHUNK):
         nd = nodes[a:a + _CHUNK]
         idx = tuple(nd[:, k] for k in range(d))
-        uc = [_gather(U[i], nd, -1, d, K) for i in range(d)]
+        uc = [_gather(Ug[i], nd, off, d, wrap) for i in range(d)]
         res[a:a + _CHUNK] = p_update_cells_var(prob, P[idx], uc, Kp[idx], dt=dt)
     return res.reshape(P.shape) if full else res
 
 
 def u_half_var(prob: Problem, U, P, Ku, nodes=None, dt=None, weight_scale: float = 1.0):
-    """Velocity half-step with kappa data Ku on the dual nodes (periodic)."""
-    d, K = prob.d, tuple(prob.K)
+    """Velocity half-step with kappa data Ku, u_nodes() + (2m+2,)*d on the dual
+    nodes (periodic, or walls: the primal corners are all real nodes)."""
+    d = prob.d
     full = nodes is None
-    nodes = _all_nodes(K) if full else np.asarray(nodes, dtype=np.int64).reshape(-1, d)
+    nodes = _all_nodes(prob.u_nodes()) if full else np.asarray(nodes, dtype=np.int64).reshape(-1, d)
+    wrap = None if prob.walls else tuple(prob.K)
     res = np.empty((d, nodes.shape[0]) + P.shape[d:], dtype=np.float64)
     for a in range(0, nodes.shape[0], _CHUNK):
         nd = nodes[a:a + _CHUNK]
         idx = tuple(nd[:, k] for k in range(d))
-        pc = _gather(P, nd, 0, d, K)
+        pc = _gather(P, nd, 0, d, wrap)
         uv = np.stack([U[i][idx] for i in range(d)])
         res[:, a:a + _CHUNK] = u_update_cells_var(prob, uv, pc, Ku[idx], dt=dt, weight_scale=weight_scale)
     return res.reshape(U.shape) if full else res
@@ -718,6 +725,8 @@ def u_half_var_adjoint(prob: Problem, Ub: np.ndarray, Pb: np.ndarray, Kp: np.nda
 def adjoint_step_var(prob: Problem, Pb, Ub, Kp, Ku, nsteps: int = 1):
     """Transpose of `step_var`: nsteps times Pb <- Pb - B^T Ub, then
     Ub <- Ub - A^T Pb (periodic grid)."""
+    if prob.walls:
+        raise NotImplementedError("the adjoint is built for the periodic grid")
     A, B = p_operator_blocks_var(prob, Kp), u_operator_blocks_var(prob, Ku)
     Pb = np.array(Pb, dtype=np.float64, copy=True)
     Ub = np.array(Ub, dtype=np.float64, copy=True)
@@ -777,6 +786,8 @@ def kappa_field_gradient(prob: Problem, P0, U0, Kp, Ku, Pbn, Ubn, nsteps: int, p
     Ub') of its result, the velocity half-step contributes d/dKu <Ub', -B P'>,
     then Pb = Pb' - B^T Ub', the pressure half-step contributes
     d/dKp <Pb, -A U_t>, then Ub = Ub' - A^T Pb."""
+    if prob.walls:
+        raise NotImplementedError("the adjoint is built for the periodic grid")
     A, B = p_operator_blocks_var(prob, Kp), u_operator_blocks_var(prob, Ku)
     states = [(np.array(P0, dtype=np.float64), np.array(U0, dtype=np.float64))]
     for _ in range(int(nsteps)):

@@ -214,6 +214,27 @@ def kappa_layers(d, m, K, length, medium, grid="primal"):
     return out
 
 
+def kappa_box(d, m, K, length, amps, grid="primal"):
+    """Taylor data of kappa(x) = 1 + sum_k amps_k cos(pi x_k / length_k) on the
+    walled box [0, length] (even about every wall, so the odd reflection of p
+    stays a solution): about the K+1 primal nodes x = j h or the K dual nodes
+    x = (q + 1/2) h per dimension, to degree 2m+1 per variable."""
+    K = tuple(int(k) for k in K)
+    n = 2 * m + 2
+    h = [float(length[k]) / K[k] for k in range(d)]
+    cnt = [k + 1 if grid == "primal" else k for k in K]
+    off = 0.0 if grid == "primal" else 0.5
+    out = np.zeros(tuple(cnt) + (n,) * d)
+    out[(Ellipsis,) + (0,) * d] = 1.0
+    for k in range(d):
+        x = (np.arange(cnt[k]) + off) * h[k]
+        f = amps[k] * scaled_sin(x, pi / float(length[k]), pi / 2, h[k], 2 * m + 1)
+        sl = [slice(None)] * d + [0] * d
+        sl[d + k] = slice(None)
+        out[tuple(sl)] += f.reshape([cnt[k] if j == k else 1 for j in range(d)] + [n])
+    return out
+
+
 def random_data(rng, d, m, K, ncomp=None):
     """Uniform[-1,1] scaled data (any data is valid input to the linear scheme)."""
     shape = tuple(int(k) for k in K) + (m + 1,) * d

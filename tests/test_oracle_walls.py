@@ -138,3 +138,62 @@ def test_box_mode_converges(d, m, Ks, T, rate_min):
     e1, e2 = (_box_err(d, m, K, T, waves) for K in Ks)
     rate = np.log2(e1 / e2)
     assert rate >= rate_min, (e1, e2, rate)
+
+
+def _extend_kappa(K, Kap, grid):
+    """Even image extension of walled kappa data to the doubled periodic box
+    (a coefficient of order b_k mirrored across x_k picks up (-1)^{b_k})."""
+    import itertools
+    d = len(K)
+    n = Kap.shape[-1]
+    sgn = (-1.0) ** np.arange(n)
+    out = np.zeros(tuple(2 * k for k in K) + (n,) * d)
+    for je in itertools.product(*[range(2 * k) for k in K]):
+        src, fac = [], np.ones((n,) * d)
+        for k in range(d):
+            lim = K[k] if grid == "primal" else K[k] - 1
+            if je[k] <= lim:
+                src.append(je[k])
+            else:
+                src.append((2 * K[k] if grid == "primal" else 2 * K[k] - 1) - je[k])
+                shape = [1] * d
+                shape[k] = n
+                fac = fac * sgn.reshape(shape)
+        out[je] = fac * Kap[tuple(src)]
+    return out
+
+
+@pytest.mark.parametrize("d,m,K", [(1, 2, (7,)), (2, 1, (5, 4)), (2, 3, (4, 3))])
+def test_variable_kappa_walls_equal_periodic_step_on_image_extension(d, m, K):
+    """Walls with variable kappa (even about every wall): the walled step equals
+    the periodic variable-kappa step on the doubled box holding the image
+    extension of P, U and kappa (written from image positions, not the ghost
+    rule); constant kappa data reproduce the constant walled step."""
+    rng = np.random.default_rng(90 + d + m)
+    L = (1.0, 1.5)[:d]
+    prob = _wprob(d, m, K, 0.0, L)
+    dt = 0.4 * min(prob.h) / np.sqrt(1.3)
+    prob = prob.with_dt(dt)
+    P = inputs.zero_on_walls(inputs.random_data(rng, d, m, prob.p_nodes()), d)
+    U = inputs.random_data(rng, d, m, prob.u_nodes(), ncomp=d)
+    amps = tuple(rng.uniform(0.1, 0.3, d))
+    Kp, Ku = inputs.kappa_box(d, m, K, L, amps, "primal"), inputs.kappa_box(d, m, K, L, amps, "dual")
+    Pw, Uw = H.step_var(prob, P, U, Kp, Ku, 3)
+    per = oracle.Problem(d, m, tuple(2 * k for k in K), tuple(2 * l for l in L), dt)
+    Pe, Ue = _extend_images(prob, P, U)
+    Pp, Up = H.step_var(per, Pe, Ue, _extend_kappa(K, Kp, "primal"), _extend_kappa(K, Ku, "dual"), 3)
+    sl = tuple(slice(0, k + 1) for k in K)
+    tol = 1e-13 * max(np.abs(Pp).max(), np.abs(Up).max())
+    assert np.allclose(Pw, Pp[sl], rtol=0, atol=tol)
+    assert np.allclose(Uw, Up[(slice(None),) + tuple(slice(0, k) for k in K)], rtol=0, atol=tol)
+    # constant kappa data: the constant-coefficient walled step
+    kap = 1.3
+    pc = _wprob(d, m, K, dt, L, kappa=kap)
+    Kc = np.zeros(prob.p_nodes() + (2 * m + 2,) * d)
+    Kc[(Ellipsis,) + (0,) * d] = kap
+    Kcu = np.zeros(prob.u_nodes() + (2 * m + 2,) * d)
+    Kcu[(Ellipsis,) + (0,) * d] = kap
+    P1, U1 = H.step_var(pc, P, U, Kc, Kcu, 2)
+    P2, U2 = H.step(pc, P, U, 2)
+    assert np.allclose(P1, P2, rtol=0, atol=1e-13 * np.abs(P2).max())
+    assert np.allclose(U1, U2, rtol=0, atol=1e-13 * np.abs(U2).max())
