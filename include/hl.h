@@ -191,14 +191,17 @@ hl_status hl_add_source(hl_plan_t plan, void* p, const void* g, double a, void* 
  * given per node as its Taylor polynomial of degree 2m+1 per variable, scaled
  * like the data: kappa~_b = prod_k h_k^{b_k} / b_k! d^b kappa (node),
  * b_k in [0, 2m+1].  kappa_p: about the primal nodes (used by the pressure
- * half-step), kappa_u: about the dual nodes (velocity half-step); host FP64
- * arrays in host layout [j_1]..[j_d][b_1]..[b_d].  Each half-step then runs
+ * half-step; K+1 per dimension with HL_WALLS), kappa_u: about the dual nodes
+ * (velocity half-step; K per dimension); host FP64 arrays in host layout
+ * [j_1]..[j_d][b_1]..[b_d].  With HL_WALLS the ghost velocity is mirrored as
+ * for constant kappa, which keeps p = 0 on the walls when kappa is even about
+ * each wall.  Each half-step then runs
  * the Cauchy-Kowalevsky recurrence d_t^{2k+1} p = -(kappa Lap)^k (kappa div u),
  * d_t^{2k+1} u = -grad (kappa Lap)^k p on the cell polynomials, every product
  * truncated to degree 2m+1 per variable, k = 0..floor(d (2m+1)/2).  The
  * plan's c must be the largest speed (it sets the CFL check and dt).  Both
- * pointers NULL: back to the plan's constant kappa = c^2.  Built for periodic
- * plans, d = 1 (all m) and d = 2 (m <= 3), HL_FP64 and HL_FP32
+ * pointers NULL: back to the plan's constant kappa = c^2.  Built for
+ * d = 1 (all m) and d = 2 (m <= 3), HL_FP64 and HL_FP32, periodic or walls
  * (HL_ERR_UNSUPPORTED otherwise); hl_adjoint_step then returns
  * HL_ERR_UNSUPPORTED.  Synchronous. */
 hl_status hl_set_kappa(hl_plan_t plan, const double* kappa_p, const double* kappa_u);

@@ -1181,25 +1181,29 @@ hl_status hl_set_kappa(hl_plan_t plan, const double* kappa_p, const double* kapp
     }
     return HL_OK;
   }
-  if (plan->walls || !plan->ks.p_half_var)
-    return fail(HL_ERR_UNSUPPORTED, "hl_set_kappa: variable kappa is built for periodic plans, d = 1, or d = 2 "
-                                    "with m <= 3, in HL_FP64 or HL_FP32");
-  // host layout [nodes][b_1..b_d], b_k in 0..2m+1: the field layout of order 2m+1
-  const LayoutMap L = hl_host::field_layout(plan->d, 2 * plan->m + 1, plan->K, false, 0);
-  const int64_t hw = (int64_t)L.nc * L.K[0] * L.K[1] * L.K[2];
-  for (const double* src : {kappa_p, kappa_u})
-    for (int64_t i = 0; i < hw; ++i)
-      if (!std::isfinite(src[i])) return fail(HL_ERR_ARG, "hl_set_kappa: kappa data must be finite");
-  FieldImage im{plan->precision, (int64_t)L.nc * L.nodes, {}, {}};
-  if (!im.alloc()) return fail(HL_ERR_NOMEM, "hl_set_kappa: host staging allocation failed");
-  for (void** q : {&plan->dkap_p, &plan->dkap_u})
-    if (!*q && (e = hipMalloc(q, im.hi_bytes())) != hipSuccess)
-      return fail(HL_ERR_NOMEM, std::string("hl_set_kappa: device allocation: ") + hipGetErrorString(e));
+  if (!plan->ks.p_half_var)
+    return fail(HL_ERR_UNSUPPORTED, "hl_set_kappa: variable kappa is built for d = 1, or d = 2 with m <= 3, in "
+                                    "HL_FP64 or HL_FP32");
+  // host layout [nodes][b_1..b_d], b_k in 0..2m+1: the field layout of order
+  // 2m+1 of p (primal nodes, K+1 per dimension with walls) and of one velocity
+  // component (dual nodes; with walls stored in the padded array, whose ghost
+  // entries the kernels never read)
   const double* srcs[2] = {kappa_p, kappa_u};
-  void* dsts[2] = {plan->dkap_p, plan->dkap_u};
+  void** dsts[2] = {&plan->dkap_p, &plan->dkap_u};
   for (int f = 0; f < 2; ++f) {
+    const LayoutMap L = hl_host::field_layout(plan->d, 2 * plan->m + 1, plan->K, plan->walls, f);
+    const int64_t hw = (int64_t)L.nc * L.K[0] * L.K[1] * L.K[2];
+    for (int64_t i = 0; i < hw; ++i)
+      if (!std::isfinite(srcs[f][i])) return fail(HL_ERR_ARG, "hl_set_kappa: kappa data must be finite");
+  }
+  for (int f = 0; f < 2; ++f) {
+    const LayoutMap L = hl_host::field_layout(plan->d, 2 * plan->m + 1, plan->K, plan->walls, f);
+    FieldImage im{plan->precision, (int64_t)L.nc * L.nodes, {}, {}};
+    if (!im.alloc()) return fail(HL_ERR_NOMEM, "hl_set_kappa: host staging allocation failed");
+    if (!*dsts[f] && (e = hipMalloc(dsts[f], im.hi_bytes())) != hipSuccess)
+      return fail(HL_ERR_NOMEM, std::string("hl_set_kappa: device allocation: ") + hipGetErrorString(e));
     L.for_each([&](int64_t h, int64_t dv) { im.put(dv, srcs[f][h]); });
-    e = hipMemcpy(dsts[f], im.hi.data(), im.hi_bytes(), hipMemcpyHostToDevice);
+    e = hipMemcpy(*dsts[f], im.hi.data(), im.hi_bytes(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hl_set_kappa: copy to device");
   }
   plan->var_kappa = true;
@@ -1364,6 +1368,7 @@ hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const vo
   hl_status st = check_plan(plan, "hl_adjoint_step_var");
   if (st != HL_OK) return st;
   if (!plan->var_kappa) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: the plan has no kappa data (hl_set_kappa)");
+  if (plan->walls) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: built for periodic plans only");
   if (!plan->ks.grad_p_var)
     return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: built for d = 1 (all m) and d = 2 (m <= 2), HL_FP64 and "
                                     "HL_FP32");
@@ -1390,6 +1395,7 @@ hl_status hl_kappa_grad(hl_plan_t plan, double* grad_p, double* grad_u, int rese
   g_last_error.clear();
   hl_status st = check_plan(plan, "hl_kappa_grad");
   if (st != HL_OK) return st;
+  if (plan->walls) return fail(HL_ERR_UNSUPPORTED, "hl_kappa_grad: built for periodic plans only");
   if (!plan->ks.grad_p_var)
     return fail(HL_ERR_UNSUPPORTED, "hl_kappa_grad: built for d = 1 (all m) and d = 2 (m <= 2), HL_FP64 and HL_FP32");
   hipError_t e = hipDeviceSynchronize();

@@ -304,17 +304,19 @@ class Plan:
                                    float(a), _stream_ptr(stream)))
 
     def set_kappa(self, kappa_p=None, kappa_u=None):
-        """Variable kappa: FP64 Taylor data (K,)*d + (2m+2,)*d about the primal
-        and dual nodes (hl_set_kappa); None, None restores the constant kappa."""
+        """Variable kappa: FP64 Taylor data (nodes,) + (2m+2,)*d about the
+        primal nodes (K, or K+1 per dimension with walls) and the dual nodes (K)
+        (hl_set_kappa); None, None restores the constant kappa."""
         if kappa_p is None and kappa_u is None:
             _check(lib().hl_set_kappa(self._h, None, None))
             return
         n2 = 2 * self.m + 2
-        shape = self.cells + (n2,) * self.d
+        pshape = self.host_shapes()[0][:self.d] + (n2,) * self.d     # primal nodes (K+1 with walls)
+        ushape = self.cells + (n2,) * self.d                           # dual nodes
         kp = np.ascontiguousarray(kappa_p, dtype=np.float64)
         ku = np.ascontiguousarray(kappa_u, dtype=np.float64)
-        if kp.shape != shape or ku.shape != shape:
-            raise ValueError(f"kappa data must have shape {shape}")
+        if kp.shape != pshape or ku.shape != ushape:
+            raise ValueError(f"kappa data must have shapes {pshape} (primal) and {ushape} (dual)")
         _check(lib().hl_set_kappa(self._h, kp.ctypes.data_as(ctypes.c_void_p), ku.ctypes.data_as(ctypes.c_void_p)))
 
     def norms(self, p, u):

@@ -110,15 +110,74 @@ def test_set_kappa_none_restores_constant_and_adjoint_refuses():
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
-@pytest.mark.parametrize("kw", [dict(d=2, m=2, cells=(8, 8), boundary="walls"), dict(d=3, m=1, cells=(4, 4, 4)),
+@pytest.mark.parametrize("kw", [dict(d=3, m=1, cells=(4, 4, 4)), dict(d=3, m=1, cells=(4, 4, 4), boundary="walls"),
                                 dict(d=2, m=2, cells=(8, 8), precision="fp32_comp"), dict(d=2, m=4, cells=(8, 8))])
 def test_varkappa_unsupported_cases(kw):
     plan = hl.Plan(**kw)
     d, m = kw["d"], kw["m"]
+    ps = plan.host_shapes()[0][:d] + (2 * m + 2,) * d
     shape = tuple(kw["cells"]) + (2 * m + 2,) * d
     with pytest.raises(hl.HLError) as ei:
-        plan.set_kappa(np.ones(shape), np.ones(shape))
+        plan.set_kappa(np.ones(ps), np.ones(shape))
     assert ei.value.status == hl.HL_ERR_UNSUPPORTED
+
+
+WALL_CASES = [(1, 3, (37,)), (1, 0, (5,)), (1, 7, (20,)), (2, 1, (70, 9)), (2, 3, (41, 10)), (2, 2, (3, 2))]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("d,m,K", WALL_CASES)
+def test_varkappa_walls_half_steps_match_oracle(d, m, K, prec):
+    """Reflecting walls with variable kappa (kappa even about every wall):
+    the ghost refresh, then the variable-kappa half-steps on the walled grids."""
+    _say(f"[varkappa] walls half-steps d={d} m={m} K={K} {prec}")
+    rng = np.random.default_rng(950 + 10 * d + m)
+    plan = hl.Plan(d, m, K, cfl=0.5, c=np.sqrt(1.6), precision=prec, boundary="walls")
+    prob = oracle.Problem(d, m, tuple(K), (1.0,) * d, plan.dt, 1.0, bc="walls")
+    amps = tuple(rng.uniform(0.1, 0.3, d))
+    kp = inputs.kappa_box(d, m, K, (1.0,) * d, amps, "primal")
+    ku = inputs.kappa_box(d, m, K, (1.0,) * d, amps, "dual")
+    plan.set_kappa(kp, ku)
+    P = inputs.zero_on_walls(inputs.random_data(rng, d, m, prob.p_nodes()), d)
+    U = inputs.random_data(rng, d, m, prob.u_nodes(), ncomp=d)
+    p, u = plan.alloc()
+    plan.init(p, u, P, U)
+    P_in, U_in = plan.export(p, u)
+    plan.p_half(p, u)
+    Pg, _ = plan.export(p, u)
+    _close(Pg, oracle.p_half_var(prob, P_in, U_in, kp), *vtol(prec, d, m))
+    plan.u_half(u, p)
+    _, Ug = plan.export(p, u)
+    _close(Ug, oracle.u_half_var(prob, U_in, Pg, ku), *vtol(prec, d, m))
+
+
+def test_varkappa_walls_multistep_fp64():
+    """20 steps (graph replay) of the walled variable-kappa step against the
+    oracle; p stays zero on the walls (even coefficients at wall nodes)."""
+    _say("[varkappa] walls 20 steps 2D m=2 (24, 18) fp64")
+    d, m, K = 2, 2, (24, 18)
+    rng = np.random.default_rng(977)
+    plan = hl.Plan(d, m, K, cfl=0.5, c=np.sqrt(1.6), precision="fp64", boundary="walls")
+    prob = oracle.Problem(d, m, K, (1.0, 1.0), plan.dt, 1.0, bc="walls")
+    kp = inputs.kappa_box(d, m, K, (1.0, 1.0), (0.3, 0.2), "primal")
+    ku = inputs.kappa_box(d, m, K, (1.0, 1.0), (0.3, 0.2), "dual")
+    plan.set_kappa(kp, ku)
+    P = inputs.zero_on_walls(inputs.random_data(rng, d, m, prob.p_nodes()), d)
+    U = inputs.random_data(rng, d, m, prob.u_nodes(), ncomp=d)
+    p, u = plan.alloc()
+    plan.init(p, u, P, U)
+    P_in, U_in = plan.export(p, u)
+    plan.step(p, u, 20)
+    Pg, Ug = plan.export(p, u)
+    Po, Uo = oracle.step_var(prob, P_in, U_in, kp, ku, 20)
+    _close(Pg, Po, *vtol("fp64", d, m))
+    _close(Ug, Uo, *vtol("fp64", d, m))
+    for k in range(d):
+        for j in (0, Pg.shape[k] - 1):
+            idx = [slice(None)] * (2 * d)
+            idx[k] = j
+            idx[d + k] = slice(0, None, 2)
+            assert np.abs(Pg[tuple(idx)]).max() <= 1e-11 * np.abs(Pg).max()
 
 
 def test_varkappa_2d_m3_1024_sampled_fp32():
