@@ -201,7 +201,8 @@ hl_status hl_add_source(hl_plan_t plan, void* p, const void* g, double a, void* 
  * truncated to degree 2m+1 per variable, k = 0..floor(d (2m+1)/2).  The
  * plan's c must be the largest speed (it sets the CFL check and dt).  Both
  * pointers NULL: back to the plan's constant kappa = c^2.  Built for
- * d = 1 (all m) and d = 2 (m <= 3), HL_FP64 and HL_FP32, periodic or walls
+ * d = 1 (all m), d = 2 (m <= 3) and d = 3 (m <= 1), HL_FP64 and HL_FP32,
+ * periodic or walls
  * (HL_ERR_UNSUPPORTED otherwise); hl_adjoint_step then returns
  * HL_ERR_UNSUPPORTED.  Synchronous. */
 hl_status hl_set_kappa(hl_plan_t plan, const double* kappa_p, const double* kappa_u);

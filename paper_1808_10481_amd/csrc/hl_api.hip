@@ -1182,8 +1182,8 @@ hl_status hl_set_kappa(hl_plan_t plan, const double* kappa_p, const double* kapp
     return HL_OK;
   }
   if (!plan->ks.p_half_var)
-    return fail(HL_ERR_UNSUPPORTED, "hl_set_kappa: variable kappa is built for d = 1, or d = 2 with m <= 3, in "
-                                    "HL_FP64 or HL_FP32");
+    return fail(HL_ERR_UNSUPPORTED, "hl_set_kappa: variable kappa is built for d = 1, d = 2 with m <= 3 and d = 3 "
+                                    "with m <= 1, in HL_FP64 or HL_FP32");
   // host layout [nodes][b_1..b_d], b_k in 0..2m+1: the field layout of order
   // 2m+1 of p (primal nodes, K+1 per dimension with walls) and of one velocity
   // component (dual nodes; with walls stored in the padded array, whose ghost

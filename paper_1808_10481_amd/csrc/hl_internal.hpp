@@ -260,7 +260,7 @@ template <typename W>
 constexpr bool kPlain<PlainStore<W>> = true;
 
 template <int D, int M, class S>
-constexpr bool kVarBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 3));
+constexpr bool kVarBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 3) || (D == 3 && M <= 1));
 template <int D, int M, class S>
 constexpr bool kVarGradBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 2));
 
@@ -365,7 +365,7 @@ inline bool make_set(KernelSet* out) {
   out->p_batch = &launch_batch<D, M, S, true>;
   out->u_batch = &launch_batch<D, M, S, false>;
   out->batch_src = SrcLauncher<S>::fn;
-  // variable kappa: FP64 and FP32 storage, d = 1 (all m) and d = 2 (m <= 3)
+  // variable kappa: FP64 and FP32 storage, d = 1 (all m), d = 2 (m <= 3), d = 3 (m <= 1)
   if constexpr (kVarBuilt<D, M, S>) {
     out->p_half_var = &launch_p_var<D, M, S>;
     out->u_half_var = &launch_u_var<D, M, S>;

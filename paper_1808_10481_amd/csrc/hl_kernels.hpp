@@ -694,14 +694,63 @@ struct VarArgs {
   T ih[3];     // 1 / h_k
 };
 
-// Full interpolant c[b_x + N2 b_y] of one component from its 2^D corner blocks.
+// Full interpolant c[b_x + N2 (b_y + N2 b_z)] of one component from its 2^D
+// corner blocks.
 template <int D, int M, class S>
 __device__ __forceinline__ void interp_full(const typename S::View& f, int comp, const uint32_t* cn,
                                             typename S::C* c) {
   using T = typename S::C;
   constexpr int MP = M + 1, N2 = 2 * M + 2, NC = Dims<D, M>::NC;
-  static_assert(D == 1 || D == 2, "variable kappa is built for d <= 2");
-  if constexpr (D == 1) {
+  if constexpr (D == 3) {
+    // x pass on the 8 corners' x-lines per (a_y, a_z), then y, then z
+    T Xc[2][2][MP][MP][N2];  // [e_y][e_z][a_y][a_z][b_x]
+#pragma unroll
+    for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+      for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+        for (int az = 0; az < MP; ++az)
+#pragma unroll
+          for (int ay = 0; ay < MP; ++ay) {
+            T L[MP], R[MP];
+#pragma unroll
+            for (int ax = 0; ax < MP; ++ax) {
+              const int pl = comp * NC + ax + MP * (ay + MP * az);
+              L[ax] = S::load(f, pl, cn[0 + 2 * ey + 4 * ez]);
+              R[ax] = S::load(f, pl, cn[1 + 2 * ey + 4 * ez]);
+            }
+            pass1d<M, 0>(L, R, Xc[ey][ez][ay][az]);
+          }
+    T Yc[2][MP][N2][N2];  // [e_z][a_z][b_x][b_y]
+#pragma unroll
+    for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+      for (int az = 0; az < MP; ++az)
+#pragma unroll
+        for (int bx = 0; bx < N2; ++bx) {
+          T L[MP], R[MP];
+#pragma unroll
+          for (int ay = 0; ay < MP; ++ay) {
+            L[ay] = Xc[0][ez][ay][az][bx];
+            R[ay] = Xc[1][ez][ay][az][bx];
+          }
+          pass1d<M, 0>(L, R, Yc[ez][az][bx]);
+        }
+#pragma unroll
+    for (int by = 0; by < N2; ++by)
+#pragma unroll
+      for (int bx = 0; bx < N2; ++bx) {
+        T L[MP], R[MP], out[N2];
+#pragma unroll
+        for (int az = 0; az < MP; ++az) {
+          L[az] = Yc[0][az][bx][by];
+          R[az] = Yc[1][az][bx][by];
+        }
+        pass1d<M, 0>(L, R, out);
+#pragma unroll
+        for (int bz = 0; bz < N2; ++bz) c[bx + N2 * (by + N2 * bz)] = out[bz];
+      }
+  } else if constexpr (D == 1) {
     T L[MP], R[MP];
 #pragma unroll
     for (int a = 0; a < MP; ++a) {
@@ -749,12 +798,18 @@ __device__ __forceinline__ void interp_full(const typename S::View& f, int comp,
 template <int D, int M, int A, class S>
 __device__ __forceinline__ void tprod_term(const typename S::View& kv, uint32_t n0, const typename S::C* f,
                                            typename S::C* out) {
-  constexpr int N2 = 2 * M + 2, AX = A % N2, AY = A / N2, NY = D > 1 ? N2 : 1;
+  constexpr int N2 = 2 * M + 2, AX = A % N2, AY = (A / N2) % N2, AZ = A / (N2 * N2);
+  constexpr int NY = D > 1 ? N2 : 1, NZ = D > 2 ? N2 : 1;
   const typename S::C ka = S::load(kv, A, n0);
 #pragma unroll
-  for (int by = AY; by < NY; ++by)
+  for (int bz = AZ; bz < NZ; ++bz)
 #pragma unroll
-    for (int bx = AX; bx < N2; ++bx) out[bx + N2 * by] = fma(ka, f[(bx - AX) + N2 * (by - AY)], out[bx + N2 * by]);
+    for (int by = AY; by < NY; ++by)
+#pragma unroll
+      for (int bx = AX; bx < N2; ++bx) {
+        const int o = bx + N2 * (by + N2 * bz);
+        out[o] = fma(ka, f[(bx - AX) + N2 * ((by - AY) + N2 * (bz - AZ))], out[o]);
+      }
 }
 
 template <int D, int M, class S, int... A>
@@ -779,15 +834,25 @@ __device__ __forceinline__ void tprod(const typename S::View& kv, uint32_t n0, c
 template <int D, int M, typename T>
 __device__ __forceinline__ void lap_coef(const T* f, T* out, const T* ih, T sc) {
   constexpr int N2 = 2 * M + 2, NP = VK<D, M>::NP;
-  const T ix2 = sc * ih[0] * ih[0], iy2 = sc * ih[1] * ih[1];
+  const T ix2 = sc * ih[0] * ih[0], iy2 = sc * ih[1] * ih[1], iz2 = sc * ih[2] * ih[2];
 #pragma unroll
   for (int b = 0; b < NP; ++b) {
-    const int bx = b % N2, by = b / N2;
+    const int bx = b % N2, by = (b / N2) % N2, bz = b / (N2 * N2);
     T v = T(0);
     if (bx + 2 < N2) v = fma(T((bx + 1) * (bx + 2)) * ix2, f[b + 2], v);
     if (D > 1 && by + 2 < N2) v = fma(T((by + 1) * (by + 2)) * iy2, f[b + 2 * N2], v);
+    if (D > 2 && bz + 2 < N2) v = fma(T((bz + 1) * (bz + 2)) * iz2, f[b + 2 * N2 * N2], v);
     out[b] = v;
   }
+}
+
+// Index of the cell-polynomial coefficient s + delta (s in {0..m}^D in the
+// data's order, delta a shift per dimension) in the (2m+2)^D layout.
+template <int D, int M>
+__host__ __device__ constexpr int poly_index(int s, int dx, int dy, int dz) {
+  constexpr int MP = M + 1, N2 = 2 * M + 2;
+  const int sx = s % MP, sy = D > 1 ? (s / MP) % MP : 0, sz = D > 2 ? s / (MP * MP) : 0;
+  return (sx + dx) + N2 * ((sy + dy) + N2 * (sz + dz));
 }
 
 template <int D, int M, class S>
@@ -807,25 +872,25 @@ __device__ __forceinline__ void p_half_var_body(typename S::View p, typename S::
   for (int i = 0; i < D; ++i) {
     T c[NP];
     interp_full<D, M, S>(u, i, cn, c);
-    const int st = i == 0 ? 1 : N2;
+    const int st = i == 0 ? 1 : i == 1 ? N2 : N2 * N2;
     const T f = va.w0 * va.ih[i];
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
-      const int bi = i == 0 ? b % N2 : b / N2;
+      const int bi = (b / st) % N2;
       if (bi + 1 < N2) div[b] = fma(T(bi + 1) * f, c[b + st], div[b]);
     }
   }
   T t[NP], acc[NC];
   tprod<D, M, S>(kp, n0, div, t);  // t_0 = w_0 r_0
 #pragma unroll
-  for (int s = 0; s < NC; ++s) acc[s] = t[(s % MP) + N2 * (s / MP)];
+  for (int s = 0; s < NC; ++s) acc[s] = t[poly_index<D, M>(s, 0, 0, 0)];
 #pragma unroll 1
   for (int k = 1; k <= VK<D, M>::KMAX; ++k) {
     T l[NP];
     lap_coef<D, M>(t, l, va.ih, va.ratio[k]);
     tprod<D, M, S>(kp, n0, l, t);  // t_k = w_k r_k
 #pragma unroll
-    for (int s = 0; s < NC; ++s) acc[s] += t[(s % MP) + N2 * (s / MP)];
+    for (int s = 0; s < NC; ++s) acc[s] += t[poly_index<D, M>(s, 0, 0, 0)];
   }
   finish_pressure<D, M, S>(p, n0, acc);
 }
@@ -867,9 +932,8 @@ __device__ __forceinline__ void u_half_var_body(typename S::View u, typename S::
     const T f = wscale * va.ih[i];
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
-      const int sx = s % MP, sy = s / MP;
-      const int si = i == 0 ? sx : sy;
-      const T qv = q[(sx + (i == 0)) + N2 * (sy + (i == 1))];
+      const int si = digit(s, MP, i);
+      const T qv = q[poly_index<D, M>(s, i == 0, i == 1, i == 2)];
       const T a = -(T)(si + 1) * f;
       S::update(u, i * NC + s, n0, [&](T x) { return fma(a, qv, x); });
     }

@@ -44,6 +44,7 @@ def _shots(d, m, prec, sizes, rng, var=False):
     (2, 2, "fp64", [(40, 24), (17, 9), (64, 64)], True),
     (1, 5, "fp64", [(37,), (300,), (2,)], True),
     (3, 1, "fp32", [(9, 8, 7), (20, 5, 3), (2, 2, 2)], False),
+    (3, 1, "fp64", [(9, 8, 7), (20, 5, 3)], True),
     (3, 2, "fp32_comp", [(12, 9, 5), (6, 6, 6)], False),
 ])
 def test_batch_equals_per_plan_steps(d, m, prec, sizes, var):

@@ -43,7 +43,8 @@ def _kappa(d, m, K, rng, smooth):
     return kp, ku
 
 
-CASES = [(1, m, (37,)) for m in (0, 1, 3, 5, 7)] + [(1, 2, (2,))] + [(2, m, (41, 9)) for m in (0, 1, 2, 3)] + [(2, 1, (2, 3))]
+CASES = ([(1, m, (37,)) for m in (0, 1, 3, 5, 7)] + [(1, 2, (2,))] + [(2, m, (41, 9)) for m in (0, 1, 2, 3)]
+         + [(2, 1, (2, 3)), (3, 0, (9, 7, 5)), (3, 1, (70, 6, 5)), (3, 1, (2, 3, 2))])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -110,7 +111,7 @@ def test_set_kappa_none_restores_constant_and_adjoint_refuses():
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
-@pytest.mark.parametrize("kw", [dict(d=3, m=1, cells=(4, 4, 4)), dict(d=3, m=1, cells=(4, 4, 4), boundary="walls"),
+@pytest.mark.parametrize("kw", [dict(d=3, m=2, cells=(4, 4, 4)), dict(d=3, m=2, cells=(4, 4, 4), boundary="walls"),
                                 dict(d=2, m=2, cells=(8, 8), precision="fp32_comp"), dict(d=2, m=4, cells=(8, 8))])
 def test_varkappa_unsupported_cases(kw):
     plan = hl.Plan(**kw)
@@ -122,7 +123,8 @@ def test_varkappa_unsupported_cases(kw):
     assert ei.value.status == hl.HL_ERR_UNSUPPORTED
 
 
-WALL_CASES = [(1, 3, (37,)), (1, 0, (5,)), (1, 7, (20,)), (2, 1, (70, 9)), (2, 3, (41, 10)), (2, 2, (3, 2))]
+WALL_CASES = [(1, 3, (37,)), (1, 0, (5,)), (1, 7, (20,)), (2, 1, (70, 9)), (2, 3, (41, 10)), (2, 2, (3, 2)),
+              (3, 1, (9, 6, 5))]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
