@@ -63,7 +63,10 @@ def hermite_steps(p, u, plan, nsteps, kappa=None):
 def receiver_index(plan, receivers):
     """Device word index of coefficient 0 of the pressure at each receiver
     (host node tuples (j_1, .., j_d)): the p layout stores plane 0 first,
-    nodes with j_1 fastest."""
+    nodes with j_1 fastest (periodic plans: the variable-kappa adjoint is
+    built for them only)."""
+    if plan.boundary != "periodic":
+        raise ValueError("receiver traces are differentiated on periodic plans only")
     idx = []
     for r in receivers:
         n, stride = 0, 1
