@@ -281,7 +281,7 @@ hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const vo
  * reset != 0 zeroes the accumulators afterwards.  Synchronous. */
 hl_status hl_kappa_grad(hl_plan_t plan, double* grad_p, double* grad_u, int reset);
 
-/* Batched shots: many independent periodic problems ("shots") of the same
+/* Batched shots: many independent problems ("shots") of the same
  * d, m and precision - each with its own grid size, time step, coefficient
  * (hl_set_kappa on every plan, or on none) and buffers - advanced together,
  * one kernel launch per half-step for all of them (shot s takes its own range
@@ -289,7 +289,9 @@ hl_status hl_kappa_grad(hl_plan_t plan, double* grad_p, double* grad_u, int rese
  * the batch).  hl_batch_step advances shot i's (p[i], u[i]) by nsteps steps,
  * exactly as hl_step on each plan would; descriptors are rebuilt (after
  * waiting for the stream) when the buffers change, and nsteps >= 16 replays a
- * captured graph of 16 batched steps.  Periodic plans only. */
+ * captured graph of 16 batched steps.  Shots may have reflecting walls
+ * (HL_WALLS): their ghost refresh is launched per shot before the batched
+ * pressure half-step. */
 typedef struct hl_batch_s* hl_batch_t;
 hl_status hl_batch_create(const hl_plan_t* plans, int32_t n, hl_batch_t* out);
 hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_t nsteps, void* stream);

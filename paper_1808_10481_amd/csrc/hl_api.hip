@@ -208,6 +208,8 @@ struct hl_batch_s {
   void* du = nullptr;
   size_t cap = 0;                     // bytes allocated for each
   std::vector<void*> bp, bu;          // buffers the descriptors describe
+  std::vector<hl::PlanView> views;    // per shot (walled shots: the ghost refresh)
+  bool walls = false;                 // some shot has reflecting walls
   int pblocks = 0, ublocks = 0;
   hipStream_t cap_stream = nullptr;   // graph of kGraphChunk batched steps
   hipGraphExec_t gexec = nullptr;
@@ -1426,13 +1428,13 @@ hl_status hl_batch_create(const hl_plan_t* plans, int32_t n, hl_batch_t* out) {
     hl_status st = check_plan(plans[i], "hl_batch_create");
     if (st != HL_OK) return st;
     const hl_plan_s* p = plans[i];
-    if (p->walls) return fail(HL_ERR_UNSUPPORTED, "hl_batch_create: batches are built for periodic plans");
     if (p->d != plans[0]->d || p->m != plans[0]->m || p->precision != plans[0]->precision)
       return fail(HL_ERR_ARG, "hl_batch_create: every plan must have the same d, m and precision");
   }
   hl_batch_s* b = new (std::nothrow) hl_batch_s();
   if (!b) return fail(HL_ERR_NOMEM, "hl_batch_create: out of host memory");
   b->plans.assign(plans, plans + n);
+  for (int32_t i = 0; i < n; ++i) b->walls = b->walls || plans[i]->walls;
   b->ks = plans[0]->ks;
   b->device = plans[0]->device;
   *out = b;
@@ -1478,8 +1480,8 @@ hl_status hl_batch_set_sources(hl_batch_t batch, const int64_t* counts, const in
     const hl_plan_s* pl = batch->plans[i];
     if ((int64_t)nc * pl->pnodes > (int64_t)UINT32_MAX)
       return fail(HL_ERR_UNSUPPORTED, "hl_batch_set_sources: pressure array too large for 32-bit word offsets");
-    int64_t hn = 1;
-    for (int k = 0; k < d; ++k) hn *= pl->K[k];
+    int64_t hn = 1;  // primal nodes (K + 1 per dimension with walls)
+    for (int k = 0; k < d; ++k) hn *= pl->pext[k];
     // distinct nodes: each entry's update is a plain read-modify-write
     std::vector<int64_t> sorted(nodes[i], nodes[i] + counts[i]);
     std::sort(sorted.begin(), sorted.end());
@@ -1490,8 +1492,8 @@ hl_status hl_batch_set_sources(hl_batch_t batch, const int64_t* counts, const in
       if (flat < 0 || flat >= hn) return fail(HL_ERR_ARG, "hl_batch_set_sources: node index out of range");
       int64_t j[3] = {0, 0, 0};
       for (int k = d - 1; k >= 0; --k) {  // host order: j_1 slowest
-        j[k] = flat % pl->K[k];
-        flat /= pl->K[k];
+        j[k] = flat % pl->pext[k];
+        flat /= pl->pext[k];
       }
       const int64_t dn = j[0] + (int64_t)pl->pext[0] * (j[1] + (int64_t)pl->pext[1] * j[2]);
       for (int c = 0; c < nc; ++c) {
@@ -1609,10 +1611,15 @@ hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_
     }
     batch->bp.assign(p, p + n);
     batch->bu.assign(u, u + n);
+    batch->views = views;
     batch->var = var;
   }
   auto one_step = [&](hipStream_t st) -> hipError_t {
-    hipError_t le = batch->ks.p_batch(batch->dp, n, batch->pblocks, var, st);
+    hipError_t le = hipSuccess;
+    // walled shots: refresh their ghost velocity before the pressure half-step
+    for (int i = 0; i < n && le == hipSuccess && batch->walls; ++i)
+      if (batch->plans[i]->walls) le = batch->ks.ghost(batch->views[i], u[i], st);
+    if (le == hipSuccess) le = batch->ks.p_batch(batch->dp, n, batch->pblocks, var, st);
     if (le == hipSuccess && batch->src) {
       le = batch->ks.batch_src(batch->d_pbase, batch->d_ent, batch->d_val, batch->d_amps, batch->namps,
                                batch->d_counter, batch->nent, st);

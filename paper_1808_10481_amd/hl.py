@@ -377,7 +377,8 @@ class Batch:
         for i, (plan, src) in enumerate(zip(self.plans, sources)):
             if src is not None:
                 nd = np.asarray(src[0], dtype=np.int64).reshape(-1, plan.d)
-                flat = np.ravel_multi_index(tuple(nd[:, k] for k in range(plan.d)), plan.cells)
+                pn = plan.host_shapes()[0][:plan.d]                 # primal nodes (K+1 with walls)
+                flat = np.ravel_multi_index(tuple(nd[:, k] for k in range(plan.d)), pn)
                 flat = np.ascontiguousarray(flat, dtype=np.int64)
                 v = np.ascontiguousarray(src[1], dtype=np.float64).reshape(nd.shape[0], -1)
                 if v.shape[1] != plan.info.nc:

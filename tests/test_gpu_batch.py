@@ -22,35 +22,44 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _shots(d, m, prec, sizes, rng, var=False):
+def _shots(d, m, prec, sizes, rng, var=False, walls=()):
     plans, states = [], []
-    for K in sizes:
+    for i, K in enumerate(sizes):
         c = float(rng.uniform(0.8, 1.8))
-        plan = hl.Plan(d, m, K, cfl=float(rng.uniform(0.3, 0.9)), c=c, precision=prec)
+        bc = "walls" if i in walls else "periodic"
+        plan = hl.Plan(d, m, K, cfl=float(rng.uniform(0.3, 0.9)), c=c, precision=prec, boundary=bc)
         if var:
             amps = tuple(rng.uniform(0.05, 0.2, d))
-            waves = tuple(int(w) for w in rng.integers(1, 3, d))
-            plan.set_kappa(inputs.kappa_sines(d, m, K, (1.0,) * d, amps, waves, "primal"),
-                           inputs.kappa_sines(d, m, K, (1.0,) * d, amps, waves, "dual"))
+            if bc == "walls":
+                plan.set_kappa(inputs.kappa_box(d, m, K, (1.0,) * d, amps, "primal"),
+                               inputs.kappa_box(d, m, K, (1.0,) * d, amps, "dual"))
+            else:
+                waves = tuple(int(w) for w in rng.integers(1, 3, d))
+                plan.set_kappa(inputs.kappa_sines(d, m, K, (1.0,) * d, amps, waves, "primal"),
+                               inputs.kappa_sines(d, m, K, (1.0,) * d, amps, waves, "dual"))
         p, u = plan.alloc()
-        plan.init(p, u, inputs.random_data(rng, d, m, K), inputs.random_data(rng, d, m, K, ncomp=d))
+        ps, us = plan.host_shapes()
+        plan.init(p, u, inputs.random_data(rng, d, m, ps[:d]), inputs.random_data(rng, d, m, K, ncomp=d))
         plans.append(plan)
         states.append((p, u))
     return plans, states
 
 
-@pytest.mark.parametrize("d,m,prec,sizes,var", [
-    (2, 3, "fp32", [(64, 48), (100, 37), (33, 80), (128, 128), (2, 3)], False),
-    (2, 2, "fp64", [(40, 24), (17, 9), (64, 64)], True),
-    (1, 5, "fp64", [(37,), (300,), (2,)], True),
-    (3, 1, "fp32", [(9, 8, 7), (20, 5, 3), (2, 2, 2)], False),
-    (3, 1, "fp64", [(9, 8, 7), (20, 5, 3)], True),
-    (3, 2, "fp32_comp", [(12, 9, 5), (6, 6, 6)], False),
+@pytest.mark.parametrize("d,m,prec,sizes,var,walls", [
+    (2, 3, "fp32", [(64, 48), (100, 37), (33, 80), (128, 128), (2, 3)], False, ()),
+    (2, 2, "fp64", [(40, 24), (17, 9), (64, 64)], True, ()),
+    (1, 5, "fp64", [(37,), (300,), (2,)], True, ()),
+    (3, 1, "fp32", [(9, 8, 7), (20, 5, 3), (2, 2, 2)], False, ()),
+    (3, 1, "fp64", [(9, 8, 7), (20, 5, 3)], True, ()),
+    (3, 2, "fp32_comp", [(12, 9, 5), (6, 6, 6)], False, ()),
+    (2, 3, "fp32", [(64, 48), (100, 37), (33, 20)], False, (0, 2)),
+    (2, 2, "fp64", [(40, 24), (17, 9)], True, (1,)),
+    (3, 1, "fp32_comp", [(12, 9, 5), (6, 7, 4)], False, (0, 1)),
 ])
-def test_batch_equals_per_plan_steps(d, m, prec, sizes, var):
-    _say(f"[batch] d={d} m={m} {prec} shots={sizes} var={var}")
+def test_batch_equals_per_plan_steps(d, m, prec, sizes, var, walls):
+    _say(f"[batch] d={d} m={m} {prec} shots={sizes} var={var} walls={walls}")
     rng = np.random.default_rng(len(sizes) + 10 * d + m)
-    plans, states = _shots(d, m, prec, sizes, rng, var)
+    plans, states = _shots(d, m, prec, sizes, rng, var, walls)
     ref = [(p.clone(), u.clone()) for p, u in states]
     batch = hl.Batch(plans)
     for n in (3, 20):                                   # eager, then graph replay + eager tail
@@ -77,10 +86,6 @@ def test_batch_rejects_mixed_problems():
     with pytest.raises(hl.HLError) as ei:
         hl.Batch([a, b])
     assert ei.value.status == hl.HL_ERR_ARG
-    w = hl.Plan(2, 2, (8, 8), boundary="walls")
-    with pytest.raises(hl.HLError) as ei:
-        hl.Batch([a, w])
-    assert ei.value.status == hl.HL_ERR_UNSUPPORTED
     c = hl.Plan(2, 2, (8, 8))
     k = inputs.kappa_sines(2, 2, (8, 8), (1.0, 1.0), (0.1, 0.1), (1, 1), "primal")
     c.set_kappa(k, k)
@@ -204,3 +209,37 @@ def test_batch_sources_reject_bad_input():
     assert ei.value.status == hl.HL_ERR_UNSUPPORTED
     batch.close()
     bc.close()
+
+
+def test_batch_sources_on_walled_shots_equal_per_plan_steps():
+    """Walled shots with sources in one batch: the per-shot ghost refresh, the
+    batched half-steps and the source launch equal each plan's own steps."""
+    _say("[batch] walled shots with sources 2D m=2 fp64")
+    d, m = 2, 2
+    rng = np.random.default_rng(515)
+    plans, states = _shots(d, m, "fp64", [(30, 22), (17, 40)], rng, False, (0, 1))
+    srcs, gbuf, amps = [], [], []
+    for plan in plans:
+        K = plan.cells
+        G = inputs.gaussian_pulse(d, m, tuple(k + 1 for k in K), (1.0,) * d, tuple(rng.uniform(0.3, 0.7, d)),
+                                  3.0 / max(K))
+        mag = np.abs(G).reshape(G.shape[:d] + (-1,)).max(-1)
+        mask = mag > 1e-12 * mag.max()
+        Gs = np.zeros_like(G)
+        Gs[mask] = G[mask]
+        srcs.append((np.argwhere(mask), G[mask]))
+        gbuf.append(plan.source_buffer(Gs))
+        amps.append(rng.normal(size=24) * plan.dt)
+    ref = [(p.clone(), u.clone()) for p, u in states]
+    batch = hl.Batch(plans)
+    batch.set_sources(srcs, amps)
+    batch.step([p for p, _ in states], [u for _, u in states], 20)
+    for n in range(20):
+        for i, (plan, (p, u)) in enumerate(zip(plans, ref)):
+            plan.p_half(p, u)
+            plan.add_source(p, gbuf[i], amps[i][n])
+            plan.u_half(u, p)
+    torch.cuda.synchronize()
+    for (p, u), (pr, ur) in zip(states, ref):
+        assert torch.equal(p, pr) and torch.equal(u, ur)
+    batch.close()
