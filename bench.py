@@ -110,8 +110,7 @@ def roofline(res, d, prec="fp64", workload="standing_mode_2d_m3_1024"):
 
 def run_3d(hl, torch, steps, K=256, m=2):
     """3D m=2 256^3 Gaussian pulse (start-up from u = 0), FP32 bulk state:
-    steps timed (the workload runs 500; a shorter timed window of the same
-    per-step work keeps the bench within minutes).  Reported beside the 2D
+    `steps` steps timed (the workload's 500 by default).  Reported beside the 2D
     headline with its own roofline (3D step: 12 (m+1)^3 coefficients read +
     written per half-step pair, p: 5 nc, u: 7 nc per node).  Every precision
     runs the same start-up, 3 untimed and `steps` timed steps; the pressure
@@ -480,12 +479,12 @@ def main():
     ap.add_argument("--no-comp", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
-    ap.add_argument("--steps-3d", type=int, default=50)
+    ap.add_argument("--steps-3d", type=int, default=500)
     ap.add_argument("--no-walls", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-varkappa", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--steps-batch", type=int, default=48)
+    ap.add_argument("--steps-batch", type=int, default=2000)
     ap.add_argument("--steps-varkappa", type=int, default=50)
     ap.add_argument("--steps-adjoint", type=int, default=100)
     ap.add_argument("--no-kgrad", action="store_true")
