@@ -245,8 +245,10 @@ hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* 
  * step) for each candidate shape (1D: 256, 128, 64; 2D/3D: 64x4, 64x2, 64x1,
  * 128x2, 128x1, 256x1, 32x8, in 3D each with y-groups 1, 2, 4) on copies of
  * (p, u) in device buffers it allocates for the call and frees, keeps the
- * fastest and reports it through hl_plan_info; p and u are not modified.  Batches launch every shot with the
- * default shape.  Synchronous. */
+ * fastest and reports it through hl_plan_info; p and u are not modified.  A
+ * batch launches its shots with their common shape when they all have the
+ * same one (read when hl_batch_step builds its descriptors), else with the
+ * default.  Synchronous. */
 hl_status hl_set_tile(hl_plan_t plan, int32_t tx, int32_t ty, int32_t ygroup);
 hl_status hl_tune(hl_plan_t plan, const void* p, const void* u, int32_t reps, void* stream);
 

@@ -163,6 +163,7 @@ struct hl_plan_s {
   int32_t pext[3], uext[3], uoff;
   int64_t pnodes, unodes;
   hl::Grid gp, gu;       // pressure / velocity half-step launch grids
+  int32_t ygroup_req = 0; // 3D tile rows per group asked for (the grids clamp it to their extent)
   hl::KernelSet ks;
   void* dtab = nullptr;
   void* dadj = nullptr;        // adjoint blocks (B^T then A^T), or NULL
@@ -209,6 +210,7 @@ struct hl_batch_s {
   size_t cap = 0;                     // bytes allocated for each
   std::vector<void*> bp, bu;          // buffers the descriptors describe
   std::vector<hl::PlanView> views;    // per shot (walled shots: the ghost refresh)
+  int32_t tile[3] = {0, 0, 0};        // workgroup shape and 3D y-group of the batched launches
   bool walls = false;                 // some shot has reflecting walls
   int pblocks = 0, ublocks = 0;
   hipStream_t cap_stream = nullptr;   // graph of kGraphChunk batched steps
@@ -957,6 +959,7 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
     delete pl;
     return fail(HL_ERR_UNSUPPORTED, "hl_plan: (d, m, precision) not built");
   }
+  pl->ygroup_req = kYGroup3;
   if (!build_grids(pl, pl->ks.tile[0], pl->ks.tile[1], kYGroup3, &pl->gp, &pl->gu)) {
     delete pl;
     return fail(HL_ERR_UNSUPPORTED, "hl_plan: grid too large for the launch");
@@ -1300,6 +1303,7 @@ hl_status hl_set_tile(hl_plan_t plan, int32_t tx, int32_t ty, int32_t ygroup) {
   drop_graph(plan);
   plan->gp = gp;
   plan->gu = gu;
+  plan->ygroup_req = ygroup == 0 ? kYGroup3 : ygroup;
   return HL_OK;
 }
 
@@ -1581,12 +1585,21 @@ hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_
     batch->gexec = nullptr;
     std::vector<hl::PlanView> views((size_t)n);
     std::vector<hl::BatchShot> shots((size_t)n);
+    // the batched launch has one workgroup shape: the shots' own tile when
+    // they all share one (hl_set_tile / hl_tune), else the default
+    bool common = true;
+    const hl_plan_s* p0 = batch->plans[0];
+    for (int i = 1; i < n; ++i) {
+      const hl_plan_s* pi = batch->plans[i];
+      common = common && pi->gp.tx == p0->gp.tx && pi->gp.ty == p0->gp.ty && pi->ygroup_req == p0->ygroup_req;
+    }
+    batch->tile[0] = common ? p0->gp.tx : batch->ks.tile[0];
+    batch->tile[1] = common ? p0->gp.ty : batch->ks.tile[1];
+    batch->tile[2] = common ? p0->ygroup_req : kYGroup3;
     for (int i = 0; i < n; ++i) {
-      // the batched launch has one workgroup shape: every shot uses the
-      // kernel set's default tile, whatever its plan was tuned to
       const hl_plan_s* pl = batch->plans[i];
       views[i] = view(pl);
-      if (!build_grids(pl, batch->ks.tile[0], batch->ks.tile[1], kYGroup3, &views[i].gp, &views[i].gu))
+      if (!build_grids(pl, batch->tile[0], batch->tile[1], batch->tile[2], &views[i].gp, &views[i].gu))
         return fail(HL_ERR_UNSUPPORTED, "hl_batch_step: grid too large for the launch");
       shots[i] = hl::BatchShot{&views[i], p[i], u[i]};
     }
@@ -1619,7 +1632,8 @@ hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_
     // walled shots: refresh their ghost velocity before the pressure half-step
     for (int i = 0; i < n && le == hipSuccess && batch->walls; ++i)
       if (batch->plans[i]->walls) le = batch->ks.ghost(batch->views[i], u[i], st);
-    if (le == hipSuccess) le = batch->ks.p_batch(batch->dp, n, batch->pblocks, var, st);
+    const dim3 block((unsigned)batch->tile[0], (unsigned)batch->tile[1], 1);
+    if (le == hipSuccess) le = batch->ks.p_batch(batch->dp, n, batch->pblocks, var, block, st);
     if (le == hipSuccess && batch->src) {
       le = batch->ks.batch_src(batch->d_pbase, batch->d_ent, batch->d_val, batch->d_amps, batch->namps,
                                batch->d_counter, batch->nent, st);
@@ -1628,7 +1642,7 @@ hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_
         le = hipGetLastError();
       }
     }
-    if (le == hipSuccess) le = batch->ks.u_batch(batch->du, n, batch->ublocks, var, st);
+    if (le == hipSuccess) le = batch->ks.u_batch(batch->du, n, batch->ublocks, var, block, st);
     return le;
   };
   int64_t k = 0;

@@ -40,7 +40,7 @@ struct BatchShot {
 };
 typedef void (*BatchDescFn)(const BatchShot* shots, int n, bool var, std::vector<unsigned char>* pdesc,
                             std::vector<unsigned char>* udesc, int* pblocks, int* ublocks);
-typedef hipError_t (*BatchHalfFn)(const void* desc, int n, int blocks, bool var, hipStream_t);
+typedef hipError_t (*BatchHalfFn)(const void* desc, int n, int blocks, bool var, dim3 block, hipStream_t);
 // Variable-kappa adjoint: the per-node gradient kernels (bar: adjoint field of
 // the half-step's output, fwd: the forward field it reads, gk: FP64 kappa
 // gradient accumulators, scr: scratch of d (2m+2)^d planes) and the gathers
@@ -308,22 +308,22 @@ void batch_desc(const BatchShot* shots, int n, bool var, std::vector<unsigned ch
 }
 
 template <int D, int M, class S, bool P>
-hipError_t launch_batch(const void* desc, int n, int blocks, bool var, hipStream_t s) {
+hipError_t launch_batch(const void* desc, int n, int blocks, bool var, dim3 block, hipStream_t s) {
   const ShotHalf<S>* d = static_cast<const ShotHalf<S>*>(desc);
   if (var) {
     if constexpr (kVarBuilt<D, M, S>) {
       if (P)
-        hipLaunchKernelGGL((p_half_batch<D, M, S, true>), dim3((unsigned)blocks), block_shape<D>(), 0, s, d, n);
+        hipLaunchKernelGGL((p_half_batch<D, M, S, true>), dim3((unsigned)blocks), block, 0, s, d, n);
       else
-        hipLaunchKernelGGL((u_half_batch<D, M, S, true>), dim3((unsigned)blocks), block_shape<D>(), 0, s, d, n);
+        hipLaunchKernelGGL((u_half_batch<D, M, S, true>), dim3((unsigned)blocks), block, 0, s, d, n);
     } else {
       return hipErrorInvalidValue;
     }
   } else {
     if (P)
-      hipLaunchKernelGGL((p_half_batch<D, M, S, false>), dim3((unsigned)blocks), block_shape<D>(), 0, s, d, n);
+      hipLaunchKernelGGL((p_half_batch<D, M, S, false>), dim3((unsigned)blocks), block, 0, s, d, n);
     else
-      hipLaunchKernelGGL((u_half_batch<D, M, S, false>), dim3((unsigned)blocks), block_shape<D>(), 0, s, d, n);
+      hipLaunchKernelGGL((u_half_batch<D, M, S, false>), dim3((unsigned)blocks), block, 0, s, d, n);
   }
   return hipGetLastError();
 }

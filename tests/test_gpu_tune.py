@@ -87,3 +87,28 @@ def test_set_tile_rejects_bad_shapes():
     p1 = hl.Plan(1, 1, (16,))
     with pytest.raises(hl.HLError):
         p1.set_tile(64, 2)
+
+
+def test_batch_uses_the_shots_common_tile():
+    """Shots tuned to one common shape are batched with it (bit-identical to
+    their own steps); mixed shapes fall back to the default."""
+    _say("[tune] batch with a common tile 2D m=3 fp32")
+    rng = np.random.default_rng(21)
+    for shapes in ([(256, 1, 0)] * 3, [(32, 8, 0), (128, 2, 0), (64, 4, 0)]):
+        plans, states = [], []
+        for K, (tx, ty, yg) in zip([(90, 40), (64, 33), (17, 70)], shapes):
+            plan = hl.Plan(2, 3, K, cfl=0.5, precision="fp32")
+            plan.set_tile(tx, ty, yg)
+            p, u = plan.alloc()
+            plan.init(p, u, inputs.random_data(rng, 2, 3, K), inputs.random_data(rng, 2, 3, K, ncomp=2))
+            plans.append(plan)
+            states.append((p, u))
+        ref = [(p.clone(), u.clone()) for p, u in states]
+        batch = hl.Batch(plans)
+        batch.step([p for p, _ in states], [u for _, u in states], 18)
+        for plan, (p, u) in zip(plans, ref):
+            plan.step(p, u, 18)
+        torch.cuda.synchronize()
+        for (p, u), (pr, ur) in zip(states, ref):
+            assert torch.equal(p, pr) and torch.equal(u, ur)
+        batch.close()
