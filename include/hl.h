@@ -198,7 +198,9 @@ hl_status hl_add_source(hl_plan_t plan, void* p, const void* g, double a, void* 
  * each wall.  Each half-step then runs
  * the Cauchy-Kowalevsky recurrence d_t^{2k+1} p = -(kappa Lap)^k (kappa div u),
  * d_t^{2k+1} u = -grad (kappa Lap)^k p on the cell polynomials, every product
- * truncated to degree 2m+1 per variable, k = 0..floor(d (2m+1)/2).  The
+ * truncated to degree 2m+1 per variable, k = 0..d m (where the
+ * constant-coefficient series ends; the paper's variable-speed case is 1D, so
+ * this length is a reading for d >= 2).  The
  * plan's c must be the largest speed (it sets the CFL check and dt).  Both
  * pointers NULL: back to the plan's constant kappa = c^2.  Built for
  * d = 1 (all m), d = 2 (m <= 3) and d = 3 (m <= 1), HL_FP64 and HL_FP32,

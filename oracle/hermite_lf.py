@@ -521,15 +521,21 @@ def kappa_gradient(prob: Problem, P0: np.ndarray, U0: np.ndarray, Pbn: np.ndarra
 # is garbled): every product is a product of cell polynomials truncated to
 # degree 2m+1 per variable, T[.]; kappa is expanded about the cell centre,
 # i.e. about the primal node for the pressure half-step and the dual node for
-# the velocity half-step; the series runs over k = 0..kmax with
-# kmax = floor(d (2m+1) / 2), the last k at which Lap^k of a degree-(2m+1)
-# cell polynomial can be nonzero (so constant kappa data reproduce the
-# constant-coefficient step exactly):
+# the velocity half-step.  With variable kappa the series does not terminate
+# (every product with kappa refills the degrees a Laplacian removed), so its
+# length is a choice; the one taken is k = 0..kmax with kmax = d m, the last k
+# at which Lap^k of a cell polynomial of degree 2m+1 in each variable can be
+# nonzero (Lap^k is a sum of D_1^{2 i_1} .. D_d^{2 i_d}, i_1 + .. + i_d = k,
+# and D_l^{2 i} kills the polynomial once 2 i > 2m+1).  This is where the
+# constant-coefficient series ends, so constant kappa data reproduce the
+# constant step exactly, and in 1D it is the paper's sum over odd time
+# derivatives up to order 2m+1.  The paper's variable-speed experiments are
+# 1D only, so for d >= 2 the length is unpinned by the paper:
 #     P <- P - sum_k w_k r_k,  r_0 = T[kappa div c],  r_k = T[kappa Lap r_{k-1}],
 #     U_i <- U_i - sum_k w_k D_i g_k,  g_0 = c,  g_k = T[kappa Lap g_{k-1}].
 
 def kmax_var(d: int, m: int) -> int:
-    return (d * (2 * m + 1)) // 2
+    return d * m
 
 
 def _tmul(a: np.ndarray, b: np.ndarray, d: int, ns: int) -> np.ndarray:

@@ -197,6 +197,9 @@ struct hl_plan_s {
   hipGraphExec_t gexec = nullptr;
   const void* graph_p = nullptr;  // buffers the graph was captured for
   const void* graph_u = nullptr;
+  // bumped by every call that changes what a batch descriptor bakes in
+  // (kappa buffers, launch grids): hl_set_kappa, hl_set_tile (and hl_tune)
+  uint64_t gen = 0;
 };
 
 // A batch of shots (plans of the same d, m and precision) advanced together.
@@ -209,6 +212,7 @@ struct hl_batch_s {
   void* du = nullptr;
   size_t cap = 0;                     // bytes allocated for each
   std::vector<void*> bp, bu;          // buffers the descriptors describe
+  std::vector<uint64_t> gens;         // the member plans' generations they were built at
   std::vector<hl::PlanView> views;    // per shot (walled shots: the ghost refresh)
   int32_t tile[3] = {0, 0, 0};        // workgroup shape and 3D y-group of the batched launches
   bool walls = false;                 // some shot has reflecting walls
@@ -1178,6 +1182,7 @@ hl_status hl_set_kappa(hl_plan_t plan, const double* kappa_p, const double* kapp
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hl_set_kappa: pending work failed");
   drop_graph(plan);
+  ++plan->gen;
   if (!kappa_p) {  // back to the constant kappa of the plan
     plan->var_kappa = false;
     for (void** q : {&plan->dkap_p, &plan->dkap_u}) {
@@ -1301,6 +1306,7 @@ hl_status hl_set_tile(hl_plan_t plan, int32_t tx, int32_t ty, int32_t ygroup) {
   hipError_t e = hipDeviceSynchronize();  // launches in flight keep their own grid copies; graphs are rebuilt
   if (e != hipSuccess) return hip_fail(e, "hl_set_tile: pending work failed");
   drop_graph(plan);
+  ++plan->gen;
   plan->gp = gp;
   plan->gu = gu;
   plan->ygroup_req = ygroup == 0 ? kYGroup3 : ygroup;
@@ -1576,8 +1582,9 @@ hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_
     return fail(HL_ERR_UNSUPPORTED, "hl_batch_step: variable kappa is not built for this (d, m, precision)");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipSuccess;
-  const bool same = var == batch->var && batch->bp.size() == (size_t)n &&
-                    std::equal(batch->bp.begin(), batch->bp.end(), p) && std::equal(batch->bu.begin(), batch->bu.end(), u);
+  bool same = var == batch->var && batch->bp.size() == (size_t)n && batch->gens.size() == (size_t)n &&
+              std::equal(batch->bp.begin(), batch->bp.end(), p) && std::equal(batch->bu.begin(), batch->bu.end(), u);
+  for (int i = 0; i < n && same; ++i) same = batch->gens[i] == batch->plans[i]->gen;
   if (!same) {
     // descriptors for these buffers; wait for work that may still read the old ones
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hl_batch_step: pending work failed");
@@ -1624,6 +1631,8 @@ hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_
     }
     batch->bp.assign(p, p + n);
     batch->bu.assign(u, u + n);
+    batch->gens.resize((size_t)n);
+    for (int i = 0; i < n; ++i) batch->gens[i] = batch->plans[i]->gen;
     batch->views = views;
     batch->var = var;
   }

@@ -668,8 +668,10 @@ __global__ void __launch_bounds__(256) adjoint_half(typename S::View out, typena
 // u_t = -grad p the odd time derivatives are
 //   d_t^{2k+1} p = -(kappa Lap)^k (kappa div u),   d_t^{2k+1} u = -grad (kappa Lap)^k p,
 // evaluated on the cell polynomials with every product truncated to degree
-// 2m+1 per variable, k = 0..kmax, kmax = floor(d (2m+1) / 2) (the last k at
-// which Lap^k of a cell polynomial can be nonzero):
+// 2m+1 per variable, k = 0..kmax, kmax = d m (the last k at which Lap^k of a
+// polynomial of degree 2m+1 in each variable can be nonzero, i.e. where the
+// constant-coefficient series ends; with variable kappa the series would go
+// on, and this length is a reading for d >= 2):
 //   P <- P - sum_k w_k r_k,   r_0 = T[kappa div c],  r_k = T[kappa Lap r_{k-1}]
 //   U_i <- U_i - sum_k w_k D_i g_k,   g_0 = c,  g_k = T[kappa Lap g_{k-1}].
 // No operator can be merged into a constant table here (kappa differs per
@@ -680,7 +682,7 @@ template <int D, int M>
 struct VK {
   static constexpr int N2 = 2 * M + 2, MP = M + 1;
   static constexpr int NP = ipow(N2, D);            // cell polynomial coefficients
-  static constexpr int KMAX = (D * (2 * M + 1)) / 2;
+  static constexpr int KMAX = D * M;
 };
 
 // The series is accumulated as t_k = w_k r_k with t_k = (w_k / w_{k-1})

@@ -119,6 +119,36 @@ def gaussian_pulse(d, m, K, length, center, width):
     return outer(fac)
 
 
+def pulse_exact_3d(points, center, width, t, length=1.0, images=2):
+    """Exact pressure at time t for p_t = -div u, u_t = -grad p in 3D with
+    p(0) = exp(-r^2/width^2), u(0) = 0 (so p_t(0) = 0), unit speed.  The
+    radial solution r p(r, t) solves the 1D wave equation (spherical means),
+        p(r, t) = [(r - t) G(r - t) + (r + t) G(r + t)] / (2 r),
+        G(s) = exp(-s^2/width^2),  p(0, t) = (1 - 2 t^2/width^2) G(t),
+    and the periodic box's solution is its sum over the images of the centre
+    within `images` box lengths per axis (the Gaussian's overlap with the box
+    boundary, exp(-(L/2w)^2), is below rounding for the widths used here).
+    points: array (..., 3) of positions."""
+    pts = np.asarray(points, dtype=np.float64)
+    c = np.asarray(center, dtype=np.float64)
+    out = np.zeros(pts.shape[:-1], dtype=np.float64)
+    w2 = float(width) ** 2
+    rng = range(-images, images + 1)
+    for n0 in rng:
+        for n1 in rng:
+            for n2 in rng:
+                dx = pts - (c + length * np.array([n0, n1, n2], dtype=np.float64))
+                r = np.sqrt(np.sum(dx * dx, axis=-1))
+                a, b = r - t, r + t
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    v = (a * np.exp(-a * a / w2) + b * np.exp(-b * b / w2)) / (2.0 * r)
+                small = r < 1e-12
+                if np.any(small):
+                    v[small] = (1.0 - 2.0 * t * t / w2) * np.exp(-t * t / w2)
+                out += v
+    return out
+
+
 def point_source(d, m, K, length, center, width):
     """A compactly supported stand-in for a point source: the Gaussian of
     gaussian_pulse with a narrow width, kept on the primal nodes where its data

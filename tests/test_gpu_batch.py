@@ -80,6 +80,38 @@ def test_batch_equals_per_plan_steps(d, m, prec, sizes, var, walls):
     batch.close()
 
 
+def test_batch_follows_member_kappa_and_tile_changes():
+    """A member plan's hl_set_kappa (free + new buffers) or hl_set_tile between
+    two batched steps on the same buffers: the batch rebuilds its
+    descriptors and stays bit-identical to per-plan stepping."""
+    _say("[batch] kappa/tile changes of a member between batched steps")
+    d, m, sizes = 2, 2, [(40, 24), (17, 9)]
+    rng = np.random.default_rng(77)
+    plans, states = _shots(d, m, "fp64", sizes, rng, var=True)
+    ref = [(p.clone(), u.clone()) for p, u in states]
+    batch = hl.Batch(plans)
+
+    def both(n):
+        batch.step([p for p, _ in states], [u for _, u in states], n)
+        for plan, (p, u) in zip(plans, ref):
+            plan.step(p, u, n)
+        torch.cuda.synchronize()
+        for (p, u), (pr, ur) in zip(states, ref):
+            assert torch.equal(p, pr) and torch.equal(u, ur)
+
+    both(17)                                            # graph + eager tail
+    K = sizes[1]
+    kp = inputs.kappa_sines(d, m, K, (1.0,) * d, (0.15, 0.1), (2, 1), "primal")
+    ku = inputs.kappa_sines(d, m, K, (1.0,) * d, (0.15, 0.1), (2, 1), "dual")
+    plans[1].set_kappa(None, None)                      # frees the member's kappa buffers
+    plans[1].set_kappa(kp, ku)                          # new buffers, new data
+    both(17)
+    plans[0].set_tile(128, 2, 0)
+    plans[1].set_tile(128, 2, 0)                        # common tile: the batch launches it
+    both(3)
+    batch.close()
+
+
 def test_batch_rejects_mixed_problems():
     a = hl.Plan(2, 2, (8, 8))
     b = hl.Plan(2, 3, (8, 8))

@@ -126,3 +126,37 @@ def test_variable_speed_1d_converges_at_the_paper_rates(m):
         errs.append(np.sqrt(np.mean((coarse - fine[:: 128 // K]) ** 2)))
     rate = np.log2(errs[0] / errs[1])
     assert abs(rate - _paper_rate(m)) <= 0.5, (errs, rate, _paper_rate(m))
+
+
+@pytest.mark.parametrize("d,m", [(1, 3), (2, 1), (2, 3), (3, 1), (3, 2)])
+def test_laplacian_powers_of_a_cell_polynomial_end_at_d_m(d, m):
+    """Lap^k of a polynomial of degree 2m+1 in each of d variables vanishes
+    for k > d m and not before (each D_l^2 lowers one variable's degree by
+    two), so the variable-kappa series length kmax_var = d m is the last k
+    at which the constant-coefficient series has a nonzero term."""
+    rng = np.random.default_rng(40 + 10 * d + m)
+    c = rng.uniform(-1.0, 1.0, size=(1,) + (2 * m + 2,) * d)
+    h = rng.uniform(0.5, 2.0, size=d)
+    assert H.kmax_var(d, m) == d * m
+    for _ in range(d * m):
+        c = H._laplacian(c, h, d, 1)
+    assert np.abs(c).max() > 0.0                   # Lap^{dm} of a full cell polynomial
+    assert not np.any(H._laplacian(c, h, d, 1))    # Lap^{dm+1} == 0 exactly
+
+
+@pytest.mark.parametrize("d,m,K", [(2, 1, (4, 3)), (2, 2, (3, 3)), (3, 1, (3, 3, 2))])
+def test_variable_kappa_updates_sum_exactly_kmax_terms(d, m, K, monkeypatch):
+    """With non-constant kappa the recurrence does not terminate, so the
+    series length changes the result: the half-steps sum k = 0..kmax_var
+    (one term fewer or more gives a different update)."""
+    rng = np.random.default_rng(60 + 10 * d + m)
+    L = (1.0,) * d
+    prob = oracle.Problem(d, m, K, L, 0.0, 1.0).with_dt(0.5 / max(K) / np.sqrt(1.6))
+    Kp = inputs.kappa_sines(d, m, K, L, (0.35, 0.25, 0.2)[:d], (1, 1, 1)[:d], "primal")
+    Ku = inputs.kappa_sines(d, m, K, L, (0.35, 0.25, 0.2)[:d], (1, 1, 1)[:d], "dual")
+    P, U = inputs.random_data(rng, d, m, K), inputs.random_data(rng, d, m, K, ncomp=d)
+    ref_p, ref_u = H.p_half_var(prob, P, U, Kp), H.u_half_var(prob, U, P, Ku)
+    for km in (d * m - 1, d * m + 1):
+        monkeypatch.setattr(H, "kmax_var", lambda dd, mm, km=km: km)
+        assert np.abs(H.p_half_var(prob, P, U, Kp) - ref_p).max() > 1e-14 * np.abs(ref_p).max()
+        assert np.abs(H.u_half_var(prob, U, P, Ku) - ref_u).max() > 1e-14 * np.abs(ref_u).max()

@@ -38,3 +38,19 @@ def tol(prec, d, m):
         return (COMP_TOL, COMP_TOL)
     t = 256.0 * np.sqrt((2 * m + 2) ** d) * 2.0 ** -24
     return (t, 4 * t)
+
+
+def fp32_steps(d, m, nhalf):
+    """FP32 after `nhalf` half-steps of smooth data (closed-form fields well
+    resolved by the grid, nu <= 1).  Each half-step adds to the stored state
+    x the sum of n = (2m+2)^d rounded products whose total is the increment;
+    for smooth data the products and the increment are no larger than x, so
+    one half-step contributes at most u (rounding the stored result) plus
+    sqrt(n) u (the sum, random rounding, tables rounded to FP32), relative
+    to the state, u = 2^-24.  The scheme is neutral (its step matrix has
+    unit-modulus eigenvalues, nothing is damped), so the contributions of
+    the half-steps add up rather than decay: bound nhalf (1 + sqrt(n)) u,
+    times 4 for the spread of the scaled coefficients' sizes; max |diff|
+    4x that."""
+    t = 4.0 * nhalf * (1.0 + np.sqrt((2 * m + 2) ** d)) * 2.0 ** -24
+    return (t, 4 * t)
