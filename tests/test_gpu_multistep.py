@@ -23,7 +23,7 @@ import pytest
 import oracle
 from oracle.diagnostics import rel_l2
 from paper_1808_10481_amd import inputs
-from tolerances import COMP_TOL, _close, fp32_steps
+from tolerances import _close, comp_steps, fp32_steps
 
 pytestmark = pytest.mark.gpu
 
@@ -115,7 +115,7 @@ def test_2d_m3_hundred_steps(prec):
     prob = oracle.Problem(d, m, K, (1.0, 1.0), plan.dt, 1.0)
     plan.close()
     Pr, Ur = oracle.step(prob, P0, U0, n)
-    t = fp32_steps(d, m, 2 * n) if prec == "fp32" else (2 * n * COMP_TOL, 10 * n * COMP_TOL)
+    t = fp32_steps(d, m, 2 * n) if prec == "fp32" else comp_steps(d, m, 2 * n)
     rp = _close(Pg, Pr, *t)
     ru = _close(Ug, Ur, *t)
     _say(f"[multistep] 2D {prec} {n} steps: rel L2 p {rp:.2e} u {ru:.2e}, bound {t[0]:.2e}")
@@ -138,7 +138,7 @@ def test_pulse_workload_recipe_on_reduced_grid(prec):
     elif prec == "fp32":
         t = fp32_steps(3, 2, 2 * n + 1)
     else:
-        t = (2 * n * COMP_TOL, 10 * n * COMP_TOL)
+        t = comp_steps(3, 2, 2 * n + 1)
     rp = _close(Pg, ref[0], *t)
     ru = _close(Ug, ref[1], *t)
     _say(f"[multistep] pulse recipe {prec}: rel L2 p {rp:.2e} u {ru:.2e}")

@@ -54,3 +54,16 @@ def fp32_steps(d, m, nhalf):
     4x that."""
     t = 4.0 * nhalf * (1.0 + np.sqrt((2 * m + 2) ** d)) * 2.0 ** -24
     return (t, 4 * t)
+
+
+def comp_steps(d, m, nhalf):
+    """FP32_COMP after `nhalf` half-steps of smooth data.  The arithmetic is
+    FP64, so each half-step's error is the storage rounding of its result:
+    every entry within 2^-33 of its value (hi the FP32 rounding, lo the BF16
+    rounding of the residual), plus an FP64 sum of n = (2m+2)^d products.  As
+    for FP32 the neutral scheme adds these up over the half-steps: bound
+    4 nhalf (2^-33 + sqrt(n) 2^-53), the factor 4 for the spread of the scaled
+    coefficients' sizes; max |diff| 4x that."""
+    t = 4.0 * nhalf * (2.0 ** -33 + np.sqrt((2 * m + 2) ** d) * 2.0 ** -53)
+    return (t, 4 * t)
+
