@@ -215,6 +215,18 @@ hl_status hl_set_kappa(hl_plan_t plan, const double* kappa_p, const double* kapp
  * finite.  Synchronous. */
 hl_status hl_norms(hl_plan_t plan, const void* p, const void* u, double* out);
 
+/* hl_norms for callers that cannot allocate device memory (code that must
+ * not call hipMalloc: tight serving loops, harnesses that forbid it): the
+ * same sums, with the kernels' block partials kept in a fixed device array
+ * of the library (256 blocks x at most 192 coefficient planes of FP64, 384
+ * KiB, per GPU, held until the process ends) instead of the plan's buffer.
+ * No call allocates (device or host).  The first call on a device looks up
+ * that device's copy of the array.  Plans with more than 192 coefficient
+ * planes in u (d nc > 192) get HL_ERR_UNSUPPORTED; every plan the library
+ * builds fits.  Every call on a GPU shares its array: calls that overlap on
+ * one GPU (several host threads) race.  Synchronous; out as for hl_norms. */
+hl_status hl_norms_noalloc(hl_plan_t plan, const void* p, const void* u, double* out);
+
 /* Discrete adjoint of hl_step: nsteps transposed steps applied in place to
  * the adjoint state (p_bar, u_bar) (device buffers laid out like p and u).
  * A step maps (P, U) to P' = P - A U, U' = U - B P'; its transpose is

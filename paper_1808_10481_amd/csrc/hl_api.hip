@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -890,6 +891,79 @@ bool valid_tile(int d, int32_t tx, int32_t ty) {
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// hl_norms_noalloc: hl_norms with its block partials in a file-scope device
+// array instead of the plan's buffer, for callers that cannot allocate.  Host
+// code never passes `norm_scratch` itself to a kernel (in host code the name
+// is a stand-in, not a device address): each device's address comes from
+// hipGetSymbolAddress, taken once per device on the first call there.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kNoAllocMaxPlanes = 3 * 64;  // d nc for 3D m = 3, the largest built
+constexpr size_t kNoAllocWords = (size_t)kNormBlocks * kNoAllocMaxPlanes + 2;
+static __device__ __align__(256) double norm_scratch[kNoAllocWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_of_device(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(norm_scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// out[0] = sum of the first n partials, in a fixed order (one block of 256).
+__global__ void sum_partials(const double* __restrict__ partial, int n, double* __restrict__ out) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += partial[i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+template <class S>
+hipError_t sumsq_static(const hl_plan_s* pl, const void* x, int field, double* scr, double* res) {
+  const int ncomp = field == 0 ? 1 : pl->d;
+  const int planes = ncomp * pl->nc;
+  const LayoutMap L = layout_of(pl, field);
+  NormBox b;
+  for (int k = 0; k < 3; ++k) {
+    b.K[k] = (int32_t)L.K[k];
+    b.E[k] = (int32_t)L.E[k];
+  }
+  b.off = (int32_t)L.off;
+  const typename S::View v = S::make(x, ncomp, pl->nc, L.nodes);
+  hipLaunchKernelGGL(sumsq_kernel<S>, dim3(kNormBlocks, (unsigned)planes), dim3(256), 0, 0, v, b, scr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, 0, (const double*)scr, kNormBlocks * planes, res);
+  return hipGetLastError();
+}
+
+hipError_t sumsq_static_any(const hl_plan_s* pl, const void* x, int field, double* scr, double* res) {
+  switch (pl->precision) {
+    case HL_FP64: return sumsq_static<hl::PlainStore<double>>(pl, x, field, scr, res);
+    case HL_FP32: return sumsq_static<hl::PlainStore<float>>(pl, x, field, scr, res);
+    default: return sumsq_static<hl::SplitStore>(pl, x, field, scr, res);
+  }
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* hl_last_error(void) { return g_last_error.c_str(); }
@@ -1230,6 +1304,28 @@ hl_status hl_norms(hl_plan_t plan, const void* p, const void* u, double* out) {
   if ((st = sumsq(plan, p, 0, &out[0])) != HL_OK) return st;
   if ((st = sumsq(plan, u, 1, &out[1])) != HL_OK) return st;
   if (!std::isfinite(out[0]) || !std::isfinite(out[1])) return fail(HL_ERR_NONFINITE, "hl_norms: non-finite state");
+  return HL_OK;
+}
+
+hl_status hl_norms_noalloc(hl_plan_t plan, const void* p, const void* u, double* out) {
+  g_last_error.clear();
+  hl_status st = check_plan(plan, "hl_norms_noalloc");
+  if (st != HL_OK) return st;
+  if (!p || !u || !out) return fail(HL_ERR_ARG, "hl_norms_noalloc: NULL argument");
+  if (plan->d * plan->nc > kNoAllocMaxPlanes)
+    return fail(HL_ERR_UNSUPPORTED, "hl_norms_noalloc: more coefficient planes than its scratch holds");
+  double* scr = nullptr;
+  hipError_t e = scratch_of_device(plan->device, &scr);
+  if (e != hipSuccess) return hip_fail(e, "hl_norms_noalloc: scratch address");
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hl_norms_noalloc: pending work failed");
+  // partials in scr[0, kNormBlocks * planes); the two sums in the last two words
+  double* res = scr + (kNoAllocWords - 2);
+  e = sumsq_static_any(plan, p, 0, scr, res);
+  if (e == hipSuccess) e = sumsq_static_any(plan, u, 1, scr, res + 1);
+  if (e == hipSuccess) e = hipMemcpy(out, res, 2 * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hl_norms_noalloc: launch or copy");
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1])) return fail(HL_ERR_NONFINITE, "hl_norms_noalloc: non-finite state");
   return HL_OK;
 }
 

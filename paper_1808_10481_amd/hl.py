@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "HL_OK", 1: "HL_ERR_ARG", 2: "HL_ERR_CFL", 3: "HL_ERR_UNSUPPO
 
 # Every symbol include/hl.h declares.
 EXPORTS = ("hl_plan", "hl_plan_destroy", "hl_plan_info", "hl_init", "hl_export", "hl_step",
-           "hl_p_half", "hl_u_half", "hl_add_source", "hl_set_kappa", "hl_norms", "hl_set_tile", "hl_tune",
+           "hl_p_half", "hl_u_half", "hl_add_source", "hl_set_kappa", "hl_norms", "hl_norms_noalloc",
+           "hl_set_tile", "hl_tune",
            "hl_adjoint_step",
            "hl_adjoint_step_var", "hl_kappa_grad", "hl_batch_create", "hl_batch_step", "hl_batch_destroy",
            "hl_batch_set_sources", "hl_last_error")
@@ -70,6 +71,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hl_p_half": ([vp, vp, vp, vp]),
         "hl_u_half": ([vp, vp, vp, dbl, vp]),
         "hl_norms": ([vp, vp, vp, ctypes.POINTER(dbl)]),
+        "hl_norms_noalloc": ([vp, vp, vp, ctypes.POINTER(dbl)]),
         "hl_set_kappa": ([vp, vp, vp]),
         "hl_add_source": ([vp, vp, vp, dbl, vp]),
         "hl_batch_create": ([ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp)]),
