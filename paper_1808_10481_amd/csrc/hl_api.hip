@@ -557,6 +557,32 @@ hl_status build_tables(hl_plan_s* pl, std::vector<double>& tab, WeightMode wm) {
           }
       t_end = t;
     }
+    if (ks.fu_off >= 0) {
+      // fully merged velocity table Fu[a][o] = sum_b W_q(o, b) H[b_x][R_ax] H[b_y][R_ay] H[b_z][R_az]
+      // (the upper corner's coefficient; the kernel's butterfly gives the
+      // others their sign): every contributing b must share the parity of o
+      int t = ks.fu_off;
+      for (int a = 0; a < pl->nc; ++a) {
+        const int ad[3] = {a % MP, (a / MP) % MP, a / (MP * MP)};
+        for (size_t o = 0; o < out_g.size(); ++o) {
+          const int orow = out_g[o][0] + N2 * (out_g[o][1] + N2 * out_g[o][2]);
+          double v = 0.0;
+          for (int bz = 0; bz < N2; ++bz)
+            for (int by = 0; by < N2; ++by)
+              for (int bx = 0; bx < N2; ++bx) {
+                const double w = Wq[(size_t)orow * P.size + bx + N2 * (by + N2 * bz)];
+                if (w == 0.0) continue;
+                const int bd[3] = {bx, by, bz};
+                for (int k = 0; k < 3; ++k)
+                  if (((bd[k] - out_g[o][k]) & 1) != 0)
+                    return fail(HL_ERR_ARG, "internal: fully merged velocity table mixes sigma and delta terms");
+                v += w * H[bx * N2 + MP + ad[0]] * H[by * N2 + MP + ad[1]] * H[bz * N2 + MP + ad[2]];
+              }
+          tab[t++] = v;
+        }
+      }
+      t_end = t;
+    }
     if (t_end != ks.table_words) return fail(HL_ERR_ARG, "internal: 3D table size mismatch");
     return HL_OK;
   }

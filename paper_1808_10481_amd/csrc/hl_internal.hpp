@@ -69,6 +69,7 @@ struct KernelSet {
   int p_off[3];          // offsets of the pressure merged tables, per component
   int u_off;             // offset of the velocity (Q) merged table
   int f_off;             // offset of the fully merged 3D pressure table, or -1
+  int fu_off;            // offset of the fully merged 3D velocity table, or -1
   int ng;                // size of the velocity output set G
   int tile[3];           // tile extent in x, y and z
 };
@@ -102,10 +103,13 @@ inline void fill_layout(KernelSet* ks) {
   ks->table_words = TL::TOTAL;
   for (int i = 0; i < 3; ++i) ks->p_off[i] = i < D ? TL::p_off(i) : -1;
   ks->u_off = TL::U_OFF;
-  if constexpr (D == 3)
+  if constexpr (D == 3) {
     ks->f_off = TL::FULL_P ? TL::F_OFF : -1;
-  else
+    ks->fu_off = TL::FULL_U ? TL::FU_OFF : -1;
+  } else {
     ks->f_off = -1;
+    ks->fu_off = -1;
+  }
   ks->ng = GSet<D, M>::NG;
   ks->tile[0] = TileShape<D>::X;
   ks->tile[1] = TileShape<D>::Y;

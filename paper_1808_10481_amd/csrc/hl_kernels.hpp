@@ -54,6 +54,11 @@
 #ifndef HL_WAVES_PER_EU
 #define HL_WAVES_PER_EU 0
 #endif
+// 3D velocity half-step for m <= 2 through the fully merged table (1) or the
+// explicit x pass plus the (y, z) merged table (0).
+#ifndef HL_U3_FULL
+#define HL_U3_FULL 1
+#endif
 // 3D tile extent in x and y (x * y = 256 work-items).
 #ifndef HL_TILE3_X
 #define HL_TILE3_X 64
@@ -166,12 +171,25 @@ __device__ __forceinline__ void corner_nodes(const Grid& g, const int32_t* j, ui
     cn[e] = node_index<D>((e & 1) ? hi[0] : lo[0], (e & 2) ? hi[1] : lo[1], (e & 4) ? hi[2] : lo[2], g.sext);
 }
 
+// entry <- f(entry) at node n0 of plane pl.  3D kernels address their planes
+// through buffer descriptors (scalar plane base, 32-bit per-lane offset), the
+// others through plain pointers.
+template <int D, class S, class F>
+__device__ __forceinline__ void update_entry(const typename S::View& v, int pl, uint32_t n0, F f) {
+  if constexpr (D == 3) {
+    const typename S::Planes pr = S::planes(v, pl);
+    S::bstore(pr, n0, f(S::bload(pr, n0)));
+  } else {
+    S::update(v, pl, n0, f);
+  }
+}
+
 // p -= acc at node n0.
 template <int D, int M, class S>
 __device__ __forceinline__ void finish_pressure(const typename S::View& p, uint32_t n0, const typename S::C* acc) {
   using T = typename S::C;
 #pragma unroll
-  for (int s = 0; s < Dims<D, M>::NC; ++s) S::update(p, s, n0, [&](T x) { return x - acc[s]; });
+  for (int s = 0; s < Dims<D, M>::NC; ++s) update_entry<D, S>(p, s, n0, [&](T x) { return x - acc[s]; });
 }
 
 // u_i[s] -= wscale * (s_i + 1) / h_i * Q[s + e_i]   (Q on the set G)
@@ -187,7 +205,7 @@ __device__ __forceinline__ void finish_velocity(const typename S::View& u, uint3
     for (int s = 0; s < NC; ++s) {
       const T a = -(T)(digit(s, MP, i) + 1) * f;
       const T q = Q[kGIndex<D, M>.g[i][s]];
-      S::update(u, i * NC + s, n0, [&](T x) { return fma(a, q, x); });
+      update_entry<D, S>(u, i * NC + s, n0, [&](T x) { return fma(a, q, x); });
     }
   }
 }
@@ -501,6 +519,62 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_3d(typename S::Vi
     p_half_3d_body<M, S, const typename S::C* __restrict__>(p, u, tab, g, blockIdx.x);
 }
 
+// Velocity half-step, 3D, m <= 2: the x interpolation merged into the table
+// as well (as for the pressure half-step).  Per datum a of the primal corners
+// the 8 corner values are combined into the sigma/delta products X[k] (x, y
+// and z, k = k_x + 2 k_y + 4 k_z); member o of G takes the product whose
+// parity in each dimension is that of o_k + a_k, times Fu[a][o].  Per node:
+// 8 loads, 24 add/sub and |G| FMA per datum (27 x 77 VALU at m = 2) against
+// the explicit x pass plus the (y, z) merged table (about 2700 VALU).
+template <int M, class S, typename TP>
+__device__ __forceinline__ void u3_full_Q(const typename S::View& p, const uint32_t* cn, TP tab,
+                                          typename S::C* Q) {
+  using T = typename S::C;
+  using TL = TableLayout<3, M>;
+  constexpr int MP = M + 1, NC = Dims<3, M>::NC, NG = GSet<3, M>::NG;
+#pragma unroll
+  for (int o = 0; o < NG; ++o) Q[o] = T(0);
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    // keep the scalar table loads of one datum together (SGPR pressure)
+    __builtin_amdgcn_sched_barrier(0);
+    const typename S::Planes pr = S::planes(p, a);
+    T v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = S::bload(pr, cn[e]);
+    T X[8];  // [k_x + 2 k_y + 4 k_z]
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // x: corners (2q, 2q+1)
+      X[2 * q] = v[2 * q + 1] + v[2 * q];
+      X[2 * q + 1] = v[2 * q + 1] - v[2 * q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = X[q];
+#pragma unroll
+    for (int kz = 0; kz < 2; ++kz)  // y: pairs (kx + 4 kz, kx + 2 + 4 kz)
+#pragma unroll
+      for (int kx = 0; kx < 2; ++kx) {
+        const T lo = v[kx + 4 * kz], hi = v[kx + 2 + 4 * kz];
+        X[kx + 4 * kz] = hi + lo;
+        X[kx + 2 + 4 * kz] = hi - lo;
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // z: pairs (q, q + 4)
+      const T lo = X[q], hi = X[q + 4];
+      v[q] = hi + lo;
+      v[q + 4] = hi - lo;
+    }
+    const int ax = a % MP, ay = (a / MP) % MP, az = a / (MP * MP);
+#pragma unroll
+    for (int o = 0; o < NG; ++o) {
+      if (o == NG / 2) __builtin_amdgcn_sched_barrier(0);  // two halves of the datum's table loads
+      const int k = ((kGSet<3, M>.dig[o][0] + ax) & 1) + 2 * ((kGSet<3, M>.dig[o][1] + ay) & 1) +
+                    4 * ((kGSet<3, M>.dig[o][2] + az) & 1);
+      Q[o] = fma(tab[TL::FU_OFF + a * NG + o], v[k], Q[o]);
+    }
+  }
+}
+
 template <int M, class S, typename TP>
 __device__ __forceinline__ void u_half_3d_body(typename S::View u, typename S::View p,
                                                TP tab, Grid g,
@@ -516,17 +590,21 @@ __device__ __forceinline__ void u_half_3d_body(typename S::View u, typename S::V
   uint32_t cn[8];
   corner_nodes<3>(g, j, cn);  // dual q = j - 1 + e (p) or primal j = q + e (u)
   T Q[NG];
+  if constexpr (TL::FULL_U && HL_U3_FULL) {
+    u3_full_Q<M, S>(p, cn, tab, Q);
+  } else {
 #pragma unroll
-  for (int o = 0; o < NG; ++o) Q[o] = T(0);
+    for (int o = 0; o < NG; ++o) Q[o] = T(0);
 #pragma unroll
-  for (int az = 0; az < MP; ++az)
+    for (int az = 0; az < MP; ++az)
 #pragma unroll
-    for (int ay = 0; ay < MP; ++ay) {
-      const int blk = ay + MP * az;
-      T X[2][2][N2];
-      xlines<M, 0, S>(p, MP * blk, cn, X);
-      merge3<M, true, 0, 0>(tab + TL::U_OFF + blk * NNZ, ay, az, X, Q);
-    }
+      for (int ay = 0; ay < MP; ++ay) {
+        const int blk = ay + MP * az;
+        T X[2][2][N2];
+        xlines<M, 0, S>(p, MP * blk, cn, X);
+        merge3<M, true, 0, 0>(tab + TL::U_OFF + blk * NNZ, ay, az, X, Q);
+      }
+  }
   const T ih[3] = {ih0, ih1, ih2};
   finish_velocity<3, M, S>(u, out_index<3>(g, j), Q, wscale, ih);
 }

@@ -360,7 +360,8 @@ struct TableLayout {
 
 // 3D: one pressure table per component (derivative dimension), then Q; for
 // m <= 2 then the fully merged pressure table (x merged too):
-// F[i][a][o], component i, datum a, output o, (m+1)^3 x (m+1)^3 per component.
+// F[i][a][o], component i, datum a, output o, (m+1)^3 x (m+1)^3 per component,
+// and the fully merged velocity table Fu[a][o] over the members o of G.
 template <int M>
 struct TableLayout<3, M> {
   static constexpr int PG = merge3_size<M, false>();
@@ -371,7 +372,10 @@ struct TableLayout<3, M> {
   static constexpr bool FULL_P = M <= 2;
   static constexpr int NC = (M + 1) * (M + 1) * (M + 1);
   static constexpr int F_OFF = U_OFF + merge3_size<M, true>();
-  static constexpr int TOTAL = F_OFF + (FULL_P ? 3 * NC * NC : 0);
+  // m <= 2: the fully merged velocity table Fu[a][o], datum a, member o of G
+  static constexpr bool FULL_U = M <= 2;
+  static constexpr int FU_OFF = F_OFF + (FULL_P ? 3 * NC * NC : 0);
+  static constexpr int TOTAL = FU_OFF + (FULL_U ? NC * GSet<3, M>::NG : 0);
 };
 
 }  // namespace hl

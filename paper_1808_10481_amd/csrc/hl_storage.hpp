@@ -92,6 +92,15 @@ struct PlainStore {
     else
       return __builtin_bit_cast(W, __builtin_amdgcn_raw_buffer_load_b64(p.r, off, 0u, 0));
   }
+  __device__ static __forceinline__ void bstore(const Planes& p, uint32_t node, C x) {
+    const uint32_t off = node * (uint32_t)sizeof(W);
+    if constexpr (sizeof(W) == 4) {
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), p.r, off, 0u, 0);
+    } else {
+      typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), p.r, off, 0u, 0);
+    }
+  }
 };
 
 template <int AS = 0>
@@ -157,6 +166,12 @@ struct SplitStoreT {
     const float hi = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(p.hi, node * 4u, 0u, 0));
     const uint16_t lo = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(p.lo, node * 2u, 0u, 0);
     return widen(hi, lo);
+  }
+  // The same rounding as update / store: hi = FP32 of x, lo = BF16 of x - hi.
+  __device__ static __forceinline__ void bstore(const Planes& p, uint32_t node, C x) {
+    const float hi = (float)x;
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, hi), p.hi, node * 4u, 0u, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(to_bf16((float)(x - (double)hi)), p.lo, node * 2u, 0u, 0);
   }
 };
 
