@@ -78,14 +78,21 @@ def _rel_state(a, b):
     return float(np.sqrt(num / den))
 
 
+# The sources the profiled half-step kernels are compiled from: their code
+# (hl_kernels.hpp), the table layout and storage policies they use, and the
+# translation units that instantiate them.  A traffic record stays valid while
+# these are unchanged.
+KERNEL_SOURCES = ("hl_kernels.hpp", "hl_layout.hpp", "hl_storage.hpp", "hl_kernels_d2_fp64.hip",
+                  "hl_kernels_d2_fp32.hip", "hl_kernels_d2_comp.hip", "hl_kernels_d3_fp64.hip",
+                  "hl_kernels_d3_fp32.hip", "hl_kernels_d3_comp.hip")
+
+
 def _source_sha256():
-    import glob
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1808_10481_amd", "csrc", "*")))
-    for f in files + [os.path.join(ROOT, "include", "hl.h")]:
-        h.update(os.path.basename(f).encode())
-        h.update(open(f, "rb").read())
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        h.update(open(os.path.join(ROOT, "paper_1808_10481_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
 

@@ -243,9 +243,17 @@ hl_status hl_norms_noalloc(hl_plan_t plan, const void* p, const void* u, double*
  *   with -dt in reverse order; exact in exact arithmetic) in buffers of its
  *   own, allocated on first use (p and u are not modified), and accumulates
  *   each step's contribution in FP64.
- * Built for periodic plans in HL_FP64 and HL_FP32 with (m+1)^d <= 27 (d = 1
- * all m, d = 2 m <= 4, d = 3 m <= 2); HL_ERR_UNSUPPORTED otherwise.
- * Asynchronous. */
+ * Reflecting walls (HL_WALLS, Sec. 5): the step is P' = P - A G U,
+ * U' = U - B P' with G the ghost refresh of u (each ghost node the signed
+ * mirror of an interior node), so the transpose is p_bar <- p_bar - B^T u_bar,
+ * then u_bar <- u_bar - G^T A^T p_bar: A^T p_bar is formed on every slot of
+ * the padded velocity array (in a plan-owned scratch array, allocated on
+ * first use) and G^T adds each ghost slot, with its mirror sign, into the
+ * node it mirrors.  The adjoint variables are the K dual nodes: the ghost
+ * slots of u_bar are cleared first and stay zero.  The kappa gradient
+ * (grad_kappa != NULL) is built for periodic plans only.
+ * Built in HL_FP64 and HL_FP32 with (m+1)^d <= 27 (d = 1 all m, d = 2 m <= 4,
+ * d = 3 m <= 2); HL_ERR_UNSUPPORTED otherwise.  Asynchronous. */
 hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* p,
                           const void* u, void* grad_kappa, int64_t nsteps, void* stream);
 

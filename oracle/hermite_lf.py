@@ -464,17 +464,86 @@ def u_half_adjoint(prob: Problem, Ub: np.ndarray, Pb: np.ndarray, A=None) -> np.
     return out.reshape(Ub.shape)
 
 
+# Reflecting walls.  The walled step is P' = P - A G U, U' = U - B P', with G
+# the ghost padding of U (ghost_pad, linear) and A, B the same per-corner
+# blocks (the cell updates do not depend on position); its transpose is
+#     Pb = Pb' - B^T Ub',    Ub = Ub' - G^T A^T Pb,
+# where B^T only gathers from the K dual nodes, A^T is evaluated on the whole
+# padded dual array (primal corners outside [0, K] contribute nothing) and
+# G^T folds each ghost's value back into the node it mirrors.
+
+def ghost_pad_adjoint(prob: Problem, W: np.ndarray) -> np.ndarray:
+    """Transpose of ghost_pad: W on the padded dual array (d,) + (K+2,)*d +
+    coef to the K dual nodes.  ghost_pad overwrites, for each component and
+    each dimension k in turn, the two ghost slices of dimension k with flipped
+    copies of their neighbouring slices; the transpose undoes these copies in
+    reverse order, adding each ghost slice (flipped) into its source slice and
+    clearing it, then keeps the interior."""
+    d, m = prob.d, prob.m
+    K = tuple(prob.K)
+    W = np.array(W, dtype=np.float64, copy=True)
+    for i in range(d):
+        for k in reversed(range(d)):
+            shape = [1] * (2 * d)
+            shape[d + k] = m + 1
+            flip = (mirror_sign(i, k) * (-1.0) ** np.arange(m + 1)).reshape(shape)
+            for g, src in ((K[k] + 1, K[k]), (0, 1)):   # reverse of ghost_pad's (lo, hi) order
+                gs = [slice(None)] * d
+                ss = [slice(None)] * d
+                gs[k], ss[k] = g, src
+                W[(i,) + tuple(ss)] += flip[0] * W[(i,) + tuple(gs)]
+                W[(i,) + tuple(gs)] = 0.0
+    return W[(slice(None),) + tuple(slice(1, k + 1) for k in K)]
+
+
+def p_half_adjoint_walls(prob: Problem, Pb: np.ndarray, Ub: np.ndarray, B=None) -> np.ndarray:
+    """Pb - B^T Ub on the walled box: the primal node j (0..K per dimension)
+    receives B[e]^T Ub[j - e] from the dual nodes j - e inside [0, K-1]."""
+    d, nc = prob.d, prob.nc
+    K = tuple(prob.K)
+    B = u_operator_blocks(prob) if B is None else B
+    Ubf = Ub.reshape((d,) + K + (nc,))
+    pad = np.zeros((d,) + tuple(k + 1 for k in K) + (nc,))   # Ub at q = j - e, zero outside
+    out = Pb.reshape(tuple(k + 1 for k in K) + (nc,)).copy()
+    for e in itertools.product((0, 1), repeat=d):
+        pad[...] = 0.0
+        pad[(slice(None),) + tuple(slice(e[k], e[k] + K[k]) for k in range(d))] = Ubf
+        out -= np.einsum("isa,i...s->...a", B[e], pad)
+    return out.reshape(Pb.shape)
+
+
+def u_half_adjoint_walls(prob: Problem, Ub: np.ndarray, Pb: np.ndarray, A=None) -> np.ndarray:
+    """Ub - G^T A^T Pb on the walled box: A^T Pb at every padded dual node
+    (q = -1..K per dimension, index q + 1) from the primal nodes q + 1 - e
+    inside [0, K], then the ghost fold G^T."""
+    d, nc = prob.d, prob.nc
+    K = tuple(prob.K)
+    A = p_operator_blocks(prob) if A is None else A
+    Pbf = Pb.reshape(tuple(k + 1 for k in K) + (nc,))
+    W = np.zeros((d,) + tuple(k + 2 for k in K) + (nc,))
+    for e in itertools.product((0, 1), repeat=d):
+        # padded index r = q + 1 takes Pb[q + 1 - e] = Pb[r - e], r - e in [0, K]
+        src = np.zeros(tuple(k + 2 for k in K) + (nc,))
+        src[tuple(slice(e[k], e[k] + K[k] + 1) for k in range(d))] = Pbf
+        W += np.einsum("sia,...s->i...a", A[e], src)
+    cshape = (prob.m + 1,) * d
+    Wt = ghost_pad_adjoint(prob, W.reshape((d,) + tuple(k + 2 for k in K) + cshape))
+    return (Ub.reshape((d,) + K + cshape) - Wt).reshape(Ub.shape)
+
+
 def adjoint_step(prob: Problem, Pb: np.ndarray, Ub: np.ndarray, nsteps: int = 1):
-    """Transpose of `step` (periodic grid): nsteps times Pb <- Pb - B^T Ub,
-    then Ub <- Ub - A^T Pb."""
-    if prob.walls:
-        raise NotImplementedError("the adjoint is built for the periodic grid")
+    """Transpose of `step`: nsteps times Pb <- Pb - B^T Ub, then Ub <- Ub -
+    A^T Pb (periodic), or Ub <- Ub - G^T A^T Pb (reflecting walls)."""
     A, B = p_operator_blocks(prob), u_operator_blocks(prob)
     Pb = np.array(Pb, dtype=np.float64, copy=True)
     Ub = np.array(Ub, dtype=np.float64, copy=True)
     for _ in range(int(nsteps)):
-        Pb = p_half_adjoint(prob, Pb, Ub, B)
-        Ub = u_half_adjoint(prob, Ub, Pb, A)
+        if prob.walls:
+            Pb = p_half_adjoint_walls(prob, Pb, Ub, B)
+            Ub = u_half_adjoint_walls(prob, Ub, Pb, A)
+        else:
+            Pb = p_half_adjoint(prob, Pb, Ub, B)
+            Ub = u_half_adjoint(prob, Ub, Pb, A)
     return Pb, Ub
 
 

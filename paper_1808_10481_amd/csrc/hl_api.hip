@@ -182,6 +182,7 @@ struct hl_plan_s {
   double* gkp = nullptr;
   double* gku = nullptr;
   void* vscr = nullptr;
+  void* wscr = nullptr;  // walls adjoint: A^T p_bar on the padded velocity array (kept zeroed)
   void* tab_dk = nullptr;
   void* tab_rev = nullptr;
   void* fp = nullptr;
@@ -1099,7 +1100,7 @@ hl_status hl_plan(const hl_problem* prob, hl_plan_t* out) {
     delete pl;
     return hip_fail(e, "hl_plan: table upload");
   }
-  if (pl->ks.adj_p && !pl->walls) {
+  if (pl->ks.adj_p) {
     std::vector<double> tp, tu;
     build_adjoint_tables(pl, tp, tu, WeightMode{pl->dt, false});
     pl->adj_u_off = tp.size();
@@ -1135,7 +1136,7 @@ hl_status hl_plan_destroy(hl_plan_t plan) {
   if (plan->dtab) (void)hipFree(plan->dtab);
   if (plan->dadj) (void)hipFree(plan->dadj);
   for (void* q : {plan->dkap_p, plan->dkap_u, plan->tab_dk, plan->tab_rev, plan->fp, plan->fu, plan->sp, plan->su,
-                  (void*)plan->gpart, (void*)plan->gkp, (void*)plan->gku, plan->vscr})
+                  (void*)plan->gpart, (void*)plan->gkp, (void*)plan->gku, plan->vscr, plan->wscr})
     if (q) (void)hipFree(q);
   if (plan->dpartial) (void)hipFree(plan->dpartial);
   delete plan;
@@ -1360,7 +1361,8 @@ hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* 
   g_last_error.clear();
   hl_status st = check_plan(plan, "hl_adjoint_step");
   if (st != HL_OK) return st;
-  if (plan->walls) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: built for periodic plans only");
+  if (plan->walls && grad_kappa)
+    return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: the kappa gradient is built for periodic plans only");
   if (plan->var_kappa) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: built for constant kappa only");
   if (grad_kappa && (!p || !u)) return fail(HL_ERR_ARG, "hl_adjoint_step: the gradient needs the forward state p, u");
   if (!plan->dadj) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: not built for this (d, m, precision)");
@@ -1373,6 +1375,31 @@ hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* 
   hl::PlanView vb = v, va = v;
   vb.adj_tab = tab;                                            // B^T blocks
   va.adj_tab = tab + plan->adj_u_off * (size_t)plan->tab_bytes;  // A^T blocks
+  if (plan->walls) {
+    // A^T on the whole padded velocity array (K + 2 slots per dimension),
+    // primal corners j = r - 1 + e from the K + 1 primal nodes
+    hl::Grid gf;
+    const int32_t tile[3] = {plan->gu.tx, plan->gu.ty, 1};
+    if (!make_grid(plan, tile, plan->gu.ygroup, plan->uext, plan->uext, 0, plan->pext, -1, plan->unodes,
+                   plan->pnodes, &gf))
+      return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: grid too large for the launch");
+    if (!plan->wscr) {
+      const size_t ub = (size_t)plan->d * plan->nc * plan->unodes * plan->word_bytes;
+      hipError_t e = hipMalloc(&plan->wscr, ub);
+      if (e == hipSuccess) e = hipMemset(plan->wscr, 0, ub);  // the fold leaves it zeroed after each use
+      if (e != hipSuccess) {
+        if (plan->wscr) (void)hipFree(plan->wscr);
+        plan->wscr = nullptr;
+        return fail(HL_ERR_NOMEM, std::string("hl_adjoint_step: wall scratch: ") + hipGetErrorString(e));
+      }
+    }
+    hipError_t e = plan->ks.ghost_zero(v, u_bar, s);
+    for (int64_t n = 0; n < nsteps && e == hipSuccess; ++n) {
+      e = plan->ks.adj_p(vb, p_bar, u_bar, s);                              // Pb -= B^T Ub
+      if (e == hipSuccess) e = plan->ks.adj_u_walls(va, gf, u_bar, p_bar, plan->wscr, s);  // Ub -= G^T A^T Pb
+    }
+    return e == hipSuccess ? HL_OK : hip_fail(e, "hl_adjoint_step: launch");
+  }
   if (!grad_kappa) {
     for (int64_t n = 0; n < nsteps; ++n) {
       hipError_t e = plan->ks.adj_p(vb, p_bar, u_bar, s);      // Pb -= B^T Ub

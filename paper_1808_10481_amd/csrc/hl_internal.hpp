@@ -9,7 +9,7 @@
 #include <vector>
 
 #include "hl.h"
-#include "hl_kernels.hpp"
+#include "hl_kernels_ext.hpp"
 
 namespace hl {
 
@@ -31,6 +31,11 @@ typedef hipError_t (*UHalfFn)(const PlanView&, void* u, const void* p, double ws
 typedef hipError_t (*GhostFn)(const PlanView&, void* u, hipStream_t);
 // Transposed half-steps: pb -= B^T ub (AdjFn p), ub -= A^T pb (AdjFn u).
 typedef hipError_t (*AdjFn)(const PlanView&, void* out, const void* in, hipStream_t);
+// Walls: ub -= G^T A^T pb through a zeroed scratch array shaped like u (left
+// zeroed), and the ghost-shell clear of an adjoint velocity.
+typedef hipError_t (*AdjWallFn)(const PlanView&, const Grid& gfull, void* ub, const void* pb, void* scr,
+                                hipStream_t);
+typedef hipError_t (*GhostZeroFn)(const PlanView&, void* u, hipStream_t);
 // Batched shots: descriptor images of the p and u half-steps of every shot
 // (built where the storage type is known) and the two batched launches.
 struct BatchShot {
@@ -58,6 +63,8 @@ struct KernelSet {
   UHalfFn u_half;
   GhostFn ghost;         // ghost-shell refresh of a wall-bounded velocity array
   AdjFn adj_p, adj_u;    // transposed half-steps, NULL where not built
+  AdjWallFn adj_u_walls; // walls: ub -= G^T A^T pb, NULL where not built
+  GhostZeroFn ghost_zero;
   PHalfFn p_half_var;    // variable-kappa half-steps, NULL where not built
   UHalfFn u_half_var;
   VarGradFn grad_p_var, grad_u_var;      // variable-kappa adjoint, NULL where not built
@@ -183,6 +190,33 @@ hipError_t launch_adjoint(const PlanView& pv, void* out, const void* in, hipStre
   const typename S::View vi = S::make(in, PTYPE ? D : 1, NC, g.snodes);
   hipLaunchKernelGGL((adjoint_half<D, M, S, PTYPE>), grid_shape(g), block_shape(g), 0, s, vo, vi,
                      (const T*)pv.adj_tab, g);
+  return hipGetLastError();
+}
+
+template <int D, int M, class S>
+hipError_t launch_adj_u_walls(const PlanView& pv, const Grid& gf, void* ub, const void* pb, void* scr,
+                              hipStream_t s) {
+  using T = typename S::C;
+  constexpr int NC = Dims<D, M>::NC;
+  const typename S::View vs = S::make(scr, D, NC, gf.onodes);
+  hipLaunchKernelGGL((adjoint_walls_at<D, M, S>), grid_shape(gf), block_shape(gf), 0, s, vs,
+                     S::make(pb, 1, NC, gf.snodes), (const T*)pv.adj_tab, gf);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t interior = 1;
+  for (int k = 0; k < D; ++k) interior *= pv.uext[k] - 2;
+  hipLaunchKernelGGL((ghost_fold<D, M, S>), dim3((unsigned)((interior + 255) / 256)), dim3(256), 0, s,
+                     S::make(ub, D, NC, gf.onodes), vs, pv.uext[0], pv.uext[1], pv.uext[2]);
+  return hipGetLastError();
+}
+
+template <int D, int M, class S>
+hipError_t launch_ghost_zero(const PlanView& pv, void* u, hipStream_t s) {
+  constexpr int NC = Dims<D, M>::NC;
+  int64_t nodes = 1;
+  for (int k = 0; k < D; ++k) nodes *= pv.uext[k];
+  hipLaunchKernelGGL((ghost_zero<D, M, S>), dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0, s,
+                     S::make(u, D, NC, nodes), pv.uext[0], pv.uext[1], pv.uext[2]);
   return hipGetLastError();
 }
 
@@ -358,10 +392,14 @@ inline bool make_set(KernelSet* out) {
   out->ghost = &launch_ghost<D, M, S>;
   out->adj_p = nullptr;
   out->adj_u = nullptr;
+  out->adj_u_walls = nullptr;
+  out->ghost_zero = nullptr;
   // adjoint: FP64 and FP32 storage, nc <= 27 (1D all m, 2D m <= 4, 3D m <= 2)
   if constexpr (kPlain<S> && Dims<D, M>::NC <= kAdjointMaxNC) {
     out->adj_p = &launch_adjoint<D, M, S, true>;
     out->adj_u = &launch_adjoint<D, M, S, false>;
+    out->adj_u_walls = &launch_adj_u_walls<D, M, S>;
+    out->ghost_zero = &launch_ghost_zero<D, M, S>;
   }
   out->p_half_var = nullptr;
   out->u_half_var = nullptr;

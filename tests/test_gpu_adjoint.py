@@ -1,6 +1,6 @@
 """GPU parity of the discrete adjoint (hl_adjoint_step) against the oracle's
-transpose, the dot-product identity at a larger size, the autograd wrapper,
-and the cases reported unsupported."""
+transpose, periodic and with reflecting walls, the dot-product identity at a
+larger size, the autograd wrapper, and the cases reported unsupported."""
 
 import ctypes
 import sys
@@ -100,7 +100,70 @@ def test_autograd_backward_is_the_adjoint():
     _close(Ug, Ur, 1e-12 * n, 1e-11 * n)
 
 
-@pytest.mark.parametrize("kw", [dict(d=2, m=2, cells=(8, 8), boundary="walls"),
+WALL_CASES = [(1, 2, (9,)), (2, 1, (11, 6)), (2, 3, (7, 5)), (3, 1, (5, 4, 3)), (3, 2, (4, 3, 3)), (3, 2, (2, 2, 2))]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("d,m,K", WALL_CASES)
+def test_walls_adjoint_matches_oracle(d, m, K, prec):
+    """The walled transpose: B^T from the K dual nodes, A^T on the padded
+    array and the ghost fold, against the oracle's (pinned by the dot-product
+    identity with the oracle's walled step)."""
+    _say(f"[adjoint] walls d={d} m={m} K={K} {prec}")
+    rng = np.random.default_rng(500 + 10 * d + m)
+    kappa = 1.3
+    plan = hl.Plan(d, m, K, cfl=0.6, c=np.sqrt(kappa), precision=prec, boundary="walls")
+    prob = oracle.Problem(d, m, tuple(K), (1.0,) * d, plan.dt, kappa, "walls")
+    ps, us = plan.host_shapes()
+    pb, ub = plan.alloc()
+    plan.init(pb, ub, rng.uniform(-1, 1, ps), rng.uniform(-1, 1, us))
+    Pb_in, Ub_in = plan.export(pb, ub)
+    n = 3
+    plan.adjoint_step(pb, ub, n)
+    Pg, Ug = plan.export(pb, ub)
+    Pr, Ur = oracle.adjoint_step(prob, Pb_in, Ub_in, n)
+    t2, tm = tol(prec, d, m)
+    _close(Pg, Pr, n * t2, n * tm)
+    _close(Ug, Ur, n * t2, n * tm)
+
+
+def test_walls_dot_product_identity_2d_m3_128():
+    """<step^n x, y> = <x, adjoint^n y> with walls, 2D m=3 128 x 96, FP64,
+    on the exported states (the K dual nodes are the variables)."""
+    _say("[adjoint] walls dot-product identity 2D m=3")
+    d, m, K, n = 2, 3, (128, 96), 12
+    rng = np.random.default_rng(13)
+    plan = hl.Plan(d, m, K, cfl=0.8, precision="fp64", boundary="walls")
+    ps, us = plan.host_shapes()
+    X = (rng.uniform(-1, 1, ps), rng.uniform(-1, 1, us))
+    Y = (rng.uniform(-1, 1, ps), rng.uniform(-1, 1, us))
+    p, u = plan.alloc()
+    pb, ub = plan.alloc()
+    plan.init(p, u, *X)
+    plan.init(pb, ub, *Y)
+    plan.step(p, u, n)
+    plan.adjoint_step(pb, ub, n)
+    SX, AY = plan.export(p, u), plan.export(pb, ub)
+    lhs = np.sum(SX[0] * Y[0]) + np.sum(SX[1] * Y[1])
+    rhs = np.sum(X[0] * AY[0]) + np.sum(X[1] * AY[1])
+    scale = np.sqrt(np.sum(SX[0] ** 2) + np.sum(SX[1] ** 2)) * np.sqrt(np.sum(Y[0] ** 2) + np.sum(Y[1] ** 2))
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs)
+    plan.close()
+
+
+def test_walls_kappa_gradient_unsupported():
+    plan = hl.Plan(2, 1, (8, 8), boundary="walls")
+    p, u = plan.alloc()
+    pb, ub = plan.alloc()
+    g = torch.zeros(1, dtype=torch.float64, device="cuda")
+    st = hl.lib().hl_adjoint_step(plan._h, ctypes.c_void_p(pb.data_ptr()), ctypes.c_void_p(ub.data_ptr()),
+                                  ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                  ctypes.c_void_p(g.data_ptr()), 1, None)
+    assert st == hl.HL_ERR_UNSUPPORTED
+    plan.close()
+
+
+@pytest.mark.parametrize("kw", [dict(d=2, m=2, cells=(8, 8), boundary="walls", precision="fp32_comp"),
                                 dict(d=2, m=2, cells=(8, 8), precision="fp32_comp"),
                                 dict(d=3, m=3, cells=(4, 4, 4)), dict(d=2, m=5, cells=(8, 8))])
 def test_adjoint_unsupported_cases(kw):

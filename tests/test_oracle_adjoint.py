@@ -89,3 +89,62 @@ def test_kappa_gradient_matches_finite_differences(d, m, K, n):
     Pr, Ur = H.adjoint_step(prob, Pb, Ub, n)
     assert np.allclose(Pa, Pr, rtol=0, atol=1e-12 * np.abs(Pr).max())
     assert np.allclose(Ua, Ur, rtol=0, atol=1e-12 * np.abs(Ur).max())
+
+
+# Reflecting walls: the adjoint of the walled step (ghost padding, then the
+# pressure half-step, then the velocity half-step) against the same identity.
+
+def _walled(d, m, K, nu=0.6, kappa=1.2):
+    pr = oracle.Problem(d, m, tuple(K), tuple(1.0 + 0.3 * k for k in range(d)), 0.0, kappa, "walls")
+    return pr.with_dt(nu * min(pr.h) / np.sqrt(kappa))
+
+
+WALL_CASES = [(1, 0, (5,)), (1, 2, (4,)), (2, 1, (4, 3)), (2, 3, (3, 2)), (3, 1, (2, 3, 2)), (3, 2, (2, 2, 3))]
+
+
+@pytest.mark.parametrize("d,m,K", WALL_CASES)
+def test_ghost_pad_adjoint_identity(d, m, K):
+    rng = np.random.default_rng(40 + d + m)
+    prob = _walled(d, m, K)
+    U = rng.uniform(-1, 1, prob.u_shape())
+    W = rng.uniform(-1, 1, (d,) + tuple(k + 2 for k in K) + (m + 1,) * d)
+    lhs = np.sum(H.ghost_pad(prob, U) * W)
+    rhs = np.sum(U * H.ghost_pad_adjoint(prob, W))
+    assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(W) * np.linalg.norm(U) * 8
+
+
+@pytest.mark.parametrize("d,m,K", WALL_CASES)
+def test_walled_dot_product_identity(d, m, K):
+    """<step(x), y> = <x, adjoint_step(y)> for the walled step on random data
+    (any data, including nonzero pressure on the walls: the step is linear)."""
+    rng = np.random.default_rng(200 + 10 * d + m)
+    prob = _walled(d, m, K)
+    P, U = rng.uniform(-1, 1, prob.p_shape()), rng.uniform(-1, 1, prob.u_shape())
+    Pb, Ub = rng.uniform(-1, 1, prob.p_shape()), rng.uniform(-1, 1, prob.u_shape())
+    for n in (1, 2):
+        P1, U1 = H.step(prob, P, U, n)
+        Pa, Ua = H.adjoint_step(prob, Pb, Ub, n)
+        lhs = np.sum(P1 * Pb) + np.sum(U1 * Ub)
+        rhs = np.sum(P * Pa) + np.sum(U * Ua)
+        scale = np.sqrt(np.sum(P1 ** 2) + np.sum(U1 ** 2)) * np.sqrt(np.sum(Pb ** 2) + np.sum(Ub ** 2))
+        assert abs(lhs - rhs) <= 1e-12 * scale, (n, lhs, rhs)
+
+
+def test_walled_adjoint_with_a_planted_sign_error_fails():
+    """The identity sees a wrong mirror parity in the ghost fold."""
+    d, m, K = 2, 2, (3, 3)
+    rng = np.random.default_rng(9)
+    prob = _walled(d, m, K)
+    P, U = rng.uniform(-1, 1, prob.p_shape()), rng.uniform(-1, 1, prob.u_shape())
+    Pb, Ub = rng.uniform(-1, 1, prob.p_shape()), rng.uniform(-1, 1, prob.u_shape())
+    P1, U1 = H.step(prob, P, U, 1)
+    orig = H.mirror_sign
+    try:
+        H.mirror_sign = lambda i, k: -orig(i, k)
+        # only the adjoint's fold sees the planted sign (the forward result is already computed)
+        Pa, Ua = H.adjoint_step(prob, Pb, Ub, 1)
+    finally:
+        H.mirror_sign = orig
+    lhs = np.sum(P1 * Pb) + np.sum(U1 * Ub)
+    rhs = np.sum(P * Pa) + np.sum(U * Ua)
+    assert abs(lhs - rhs) > 1e-6 * abs(lhs)
