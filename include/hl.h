@@ -250,8 +250,9 @@ hl_status hl_norms_noalloc(hl_plan_t plan, const void* p, const void* u, double*
  * the padded velocity array (in a plan-owned scratch array, allocated on
  * first use) and G^T adds each ghost slot, with its mirror sign, into the
  * node it mirrors.  The adjoint variables are the K dual nodes: the ghost
- * slots of u_bar are cleared first and stay zero.  The kappa gradient
- * (grad_kappa != NULL) is built for periodic plans only.
+ * slots of u_bar are cleared first and stay zero.  The kappa gradient walks
+ * the walled step back the same way (the ghost refresh of U_t before the
+ * pressure-side operators read it).
  * Built in HL_FP64 and HL_FP32 with (m+1)^d <= 27 (d = 1 all m, d = 2 m <= 4,
  * d = 3 m <= 2); HL_ERR_UNSUPPORTED otherwise.  Asynchronous. */
 hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* p,

@@ -550,7 +550,8 @@ def adjoint_step(prob: Problem, Pb: np.ndarray, Ub: np.ndarray, nsteps: int = 1)
 def kappa_gradient(prob: Problem, P0: np.ndarray, U0: np.ndarray, Pbn: np.ndarray, Ubn: np.ndarray,
                    nsteps: int):
     """d/dkappa of <Pbn, P_n> + <Ubn, U_n> for n steps from (P0, U0), and the
-    adjoint state (Pb_0, Ub_0) (periodic grid).
+    adjoint state (Pb_0, Ub_0) (periodic grid or reflecting walls; with walls
+    A stands for A G, the ghost padding included in the pressure half-step).
 
     With P' = P - A U, U' = U - B P' and the adjoint lambda_{t+1} = (Pb', Ub')
     of the state after step t, the step's kappa-derivative contributes
@@ -564,6 +565,7 @@ def kappa_gradient(prob: Problem, P0: np.ndarray, U0: np.ndarray, Pbn: np.ndarra
         P, U = states[-1]
         P1 = p_half(prob, P, U)
         states.append((P1, u_half(prob, U, P1)))
+    padj, uadj = (p_half_adjoint_walls, u_half_adjoint_walls) if prob.walls else (p_half_adjoint, u_half_adjoint)
     Pb, Ub = np.array(Pbn, dtype=np.float64), np.array(Ubn, dtype=np.float64)
     g = 0.0
     for t in range(int(nsteps) - 1, -1, -1):
@@ -571,10 +573,10 @@ def kappa_gradient(prob: Problem, P0: np.ndarray, U0: np.ndarray, Pbn: np.ndarra
         P_1 = states[t + 1][0]
         BkP = -u_half(prob, np.zeros_like(U_t), P_1, dkappa=True)                  # B_kappa P'
         g -= np.sum(Ub * BkP)
-        Pb = p_half_adjoint(prob, Pb, Ub, B)
+        Pb = padj(prob, Pb, Ub, B)
         AkU = -p_half(prob, np.zeros_like(P_t), U_t, dkappa=True)                   # A_kappa U_t
         g -= np.sum(Pb * AkU)
-        Ub = u_half_adjoint(prob, Ub, Pb, A)
+        Ub = uadj(prob, Ub, Pb, A)
     return g, Pb, Ub
 
 

@@ -1361,8 +1361,6 @@ hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* 
   g_last_error.clear();
   hl_status st = check_plan(plan, "hl_adjoint_step");
   if (st != HL_OK) return st;
-  if (plan->walls && grad_kappa)
-    return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: the kappa gradient is built for periodic plans only");
   if (plan->var_kappa) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: built for constant kappa only");
   if (grad_kappa && (!p || !u)) return fail(HL_ERR_ARG, "hl_adjoint_step: the gradient needs the forward state p, u");
   if (!plan->dadj) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: not built for this (d, m, precision)");
@@ -1394,11 +1392,38 @@ hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* 
       }
     }
     hipError_t e = plan->ks.ghost_zero(v, u_bar, s);
+    if (!grad_kappa) {
+      for (int64_t n = 0; n < nsteps && e == hipSuccess; ++n) {
+        e = plan->ks.adj_p(vb, p_bar, u_bar, s);                              // Pb -= B^T Ub
+        if (e == hipSuccess) e = plan->ks.adj_u_walls(va, gf, u_bar, p_bar, plan->wscr, s);  // Ub -= G^T A^T Pb
+      }
+      return e == hipSuccess ? HL_OK : hip_fail(e, "hl_adjoint_step: launch");
+    }
+    // the periodic gradient's walk (below), with A G in place of A: the ghost
+    // refresh of U_t before the pressure-side operators read it
+    if ((st = ensure_gradient(plan)) != HL_OK) return st;
+    hl::PlanView vdk = v, vrev = v;
+    vdk.tab = plan->tab_dk;
+    vrev.tab = plan->tab_rev;
+    const size_t pbytes = (size_t)plan->nc * plan->pnodes * plan->tab_bytes;
+    const size_t ubytes = (size_t)plan->d * plan->nc * plan->unodes * plan->tab_bytes;
+    double* g = static_cast<double*>(grad_kappa);
+    if (e == hipSuccess) e = hipMemcpyAsync(plan->fp, p, pbytes, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(plan->fu, u, ubytes, hipMemcpyDeviceToDevice, s);
     for (int64_t n = 0; n < nsteps && e == hipSuccess; ++n) {
-      e = plan->ks.adj_p(vb, p_bar, u_bar, s);                              // Pb -= B^T Ub
+      e = hipMemsetAsync(plan->su, 0, ubytes, s);
+      if (e == hipSuccess) e = plan->ks.u_half(vdk, plan->su, plan->fp, 1.0, s);       // su = -B_kappa P'
+      if (e == hipSuccess) e = dot_into(plan, u_bar, plan->su, 1, g, s);
+      if (e == hipSuccess) e = plan->ks.u_half(v, plan->fu, plan->fp, -1.0, s);       // fu = U_t
+      if (e == hipSuccess) e = plan->ks.adj_p(vb, p_bar, u_bar, s);                    // Pb -= B^T Ub
+      if (e == hipSuccess) e = plan->ks.ghost(v, plan->fu, s);                         // G U_t
+      if (e == hipSuccess) e = hipMemsetAsync(plan->sp, 0, pbytes, s);
+      if (e == hipSuccess) e = plan->ks.p_half(vdk, plan->sp, plan->fu, s);             // sp = -A_kappa G U_t
+      if (e == hipSuccess) e = dot_into(plan, p_bar, plan->sp, 0, g, s);
+      if (e == hipSuccess) e = plan->ks.p_half(vrev, plan->fp, plan->fu, s);            // fp = P_t
       if (e == hipSuccess) e = plan->ks.adj_u_walls(va, gf, u_bar, p_bar, plan->wscr, s);  // Ub -= G^T A^T Pb
     }
-    return e == hipSuccess ? HL_OK : hip_fail(e, "hl_adjoint_step: launch");
+    return e == hipSuccess ? HL_OK : hip_fail(e, "hl_adjoint_step: gradient launch");
   }
   if (!grad_kappa) {
     for (int64_t n = 0; n < nsteps; ++n) {

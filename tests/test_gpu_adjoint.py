@@ -151,15 +151,34 @@ def test_walls_dot_product_identity_2d_m3_128():
     plan.close()
 
 
-def test_walls_kappa_gradient_unsupported():
-    plan = hl.Plan(2, 1, (8, 8), boundary="walls")
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("d,m,K,n", [(1, 3, (20,), 20), (2, 2, (14, 11), 10), (3, 1, (7, 5, 4), 5)])
+def test_walls_kappa_gradient_matches_oracle(d, m, K, n, prec):
+    """The kappa gradient with walls (the walled step walked back, the ghost
+    refresh before the pressure-side operators) and the adjoint state against
+    the oracle's (pinned by central differences of its walled step)."""
+    _say(f"[adjoint] walls kappa gradient d={d} m={m} K={K} n={n} {prec}")
+    rng = np.random.default_rng(90 + d + m)
+    kappa = 1.2
+    plan = hl.Plan(d, m, K, cfl=0.7, c=np.sqrt(kappa), precision=prec, boundary="walls")
+    prob = oracle.Problem(d, m, tuple(K), (1.0,) * d, plan.dt, kappa, "walls")
+    ps, us = plan.host_shapes()
     p, u = plan.alloc()
     pb, ub = plan.alloc()
+    plan.init(p, u, inputs.zero_on_walls(rng.uniform(-1, 1, ps), d), rng.uniform(-1, 1, us))
+    plan.init(pb, ub, rng.uniform(-1, 1, ps), rng.uniform(-1, 1, us))
+    P0, U0 = plan.export(p, u)
+    Pb, Ub = plan.export(pb, ub)
+    plan.step(p, u, n)
     g = torch.zeros(1, dtype=torch.float64, device="cuda")
-    st = hl.lib().hl_adjoint_step(plan._h, ctypes.c_void_p(pb.data_ptr()), ctypes.c_void_p(ub.data_ptr()),
-                                  ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(u.data_ptr()),
-                                  ctypes.c_void_p(g.data_ptr()), 1, None)
-    assert st == hl.HL_ERR_UNSUPPORTED
+    plan.adjoint_step(pb, ub, n, p=p, u=u, grad_kappa=g)
+    gr, Pr, Ur = oracle.kappa_gradient(prob, P0, U0, Pb, Ub, n)
+    rt = 1e-9 if prec == "fp64" else 3e-4
+    assert abs(float(g) - gr) <= rt * abs(gr), (float(g), gr)
+    Pa, Ua = plan.export(pb, ub)
+    t2, tm = tol(prec, d, m)
+    _close(Pa, Pr, n * t2, n * tm)
+    _close(Ua, Ur, n * t2, n * tm)
     plan.close()
 
 

@@ -148,3 +148,25 @@ def test_walled_adjoint_with_a_planted_sign_error_fails():
     lhs = np.sum(P1 * Pb) + np.sum(U1 * Ub)
     rhs = np.sum(P * Pa) + np.sum(U * Ua)
     assert abs(lhs - rhs) > 1e-6 * abs(lhs)
+
+
+@pytest.mark.parametrize("d,m,K,n", [(1, 2, (6,), 5), (2, 1, (4, 3), 4), (3, 1, (2, 3, 2), 2)])
+def test_walled_kappa_gradient_matches_finite_differences(d, m, K, n):
+    """The kappa derivative with walls against a central difference of the
+    oracle's walled step (dt fixed)."""
+    rng = np.random.default_rng(80 + d + m)
+    prob = _walled(d, m, K)
+    P0, U0 = rng.uniform(-1, 1, prob.p_shape()), rng.uniform(-1, 1, prob.u_shape())
+    Pb, Ub = rng.uniform(-1, 1, prob.p_shape()), rng.uniform(-1, 1, prob.u_shape())
+    g, Pa, Ua = H.kappa_gradient(prob, P0, U0, Pb, Ub, n)
+
+    def J(kappa):
+        Pn, Un = H.step(oracle.Problem(prob.d, prob.m, prob.K, prob.length, prob.dt, kappa, "walls"), P0, U0, n)
+        return np.sum(Pn * Pb) + np.sum(Un * Ub)
+
+    dk = 1e-4 * prob.kappa
+    fd = (J(prob.kappa + dk) - J(prob.kappa - dk)) / (2 * dk)
+    assert abs(g - fd) <= 1e-6 * max(abs(fd), 1e-12), (g, fd)
+    Pr, Ur = H.adjoint_step(prob, Pb, Ub, n)
+    assert np.allclose(Pa, Pr, rtol=0, atol=1e-12 * np.abs(Pr).max())
+    assert np.allclose(Ua, Ur, rtol=0, atol=1e-12 * np.abs(Ur).max())
