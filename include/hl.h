@@ -253,8 +253,10 @@ hl_status hl_norms_noalloc(hl_plan_t plan, const void* p, const void* u, double*
  * slots of u_bar are cleared first and stay zero.  The kappa gradient walks
  * the walled step back the same way (the ghost refresh of U_t before the
  * pressure-side operators read it).
- * Built in HL_FP64 and HL_FP32 with (m+1)^d <= 27 (d = 1 all m, d = 2 m <= 4,
- * d = 3 m <= 2); HL_ERR_UNSUPPORTED otherwise.  Asynchronous. */
+ * The transposed half-steps apply dense per-corner blocks of nc x nc
+ * (nc = (m+1)^d), all output rows at once up to nc = 27 and in passes of 16
+ * rows beyond.  Built in HL_FP64 and HL_FP32 for every d and m;
+ * HL_ERR_UNSUPPORTED for HL_FP32_COMP.  Asynchronous. */
 hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* p,
                           const void* u, void* grad_kappa, int64_t nsteps, void* stream);
 
@@ -296,7 +298,7 @@ hl_status hl_tune(hl_plan_t plan, const void* p, const void* u, int32_t reps, vo
  * terms) and spread the result over the neighbouring cells with a gather (no
  * atomics), through a plan-owned scratch of d (2m+2)^d planes allocated with
  * the accumulators on first use (zeroed then).  Built for periodic plans,
- * d = 1 (all m) and d = 2 (m <= 2), HL_FP64 and HL_FP32; HL_ERR_UNSUPPORTED
+ * d = 1 (all m) and d = 2 (m <= 3), HL_FP64 and HL_FP32; HL_ERR_UNSUPPORTED
  * otherwise, or without kappa data.  Asynchronous. */
 hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const void* p_next,
                               const void* u_prev, void* stream);

@@ -1556,7 +1556,7 @@ hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const vo
   if (!plan->var_kappa) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: the plan has no kappa data (hl_set_kappa)");
   if (plan->walls) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: built for periodic plans only");
   if (!plan->ks.grad_p_var)
-    return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: built for d = 1 (all m) and d = 2 (m <= 2), HL_FP64 and "
+    return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: built for d = 1 (all m) and d = 2 (m <= 3), HL_FP64 and "
                                     "HL_FP32");
   if (!p_bar || !u_bar || !p_next || !u_prev)
     return fail(HL_ERR_ARG, "hl_adjoint_step_var: NULL buffer");
@@ -1566,12 +1566,16 @@ hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const vo
       if (bufs[a] == bufs[b]) return fail(HL_ERR_ARG, "hl_adjoint_step_var: the four buffers must be distinct");
   if ((st = ensure_var_gradient(plan)) != HL_OK) return st;
   hl::PlanView v = view(plan);
+  // the gradient kernels run 64 work-items per workgroup (per-lane LDS arrays)
+  hl::PlanView v64 = v;
+  if (!build_grids(plan, 64, 1, plan->gp.ygroup, &v64.gp, &v64.gu))
+    return fail(HL_ERR_ARG, "hl_adjoint_step_var: grid too large");
   hipStream_t s = (hipStream_t)stream;
   // velocity half-step of the step being undone: gku -= d<Ub, B P'>/dkappa, z = d/dc
-  hipError_t e = plan->ks.grad_u_var(v, u_bar, p_next, plan->gku, plan->vscr, s);
+  hipError_t e = plan->ks.grad_u_var(v64, u_bar, p_next, plan->gku, plan->vscr, s);
   if (e == hipSuccess) e = plan->ks.gather_p_var(v, p_bar, plan->vscr, s);            // Pb -= B^T Ub
   // pressure half-step: gkp -= d<Pb, A U_t>/dkappa, rho = d/dc
-  if (e == hipSuccess) e = plan->ks.grad_p_var(v, p_bar, u_prev, plan->gkp, plan->vscr, s);
+  if (e == hipSuccess) e = plan->ks.grad_p_var(v64, p_bar, u_prev, plan->gkp, plan->vscr, s);
   if (e == hipSuccess) e = plan->ks.gather_u_var(v, u_bar, plan->vscr, s);            // Ub -= A^T Pb
   if (e != hipSuccess) return hip_fail(e, "hl_adjoint_step_var: launch");
   return HL_OK;
@@ -1583,7 +1587,7 @@ hl_status hl_kappa_grad(hl_plan_t plan, double* grad_p, double* grad_u, int rese
   if (st != HL_OK) return st;
   if (plan->walls) return fail(HL_ERR_UNSUPPORTED, "hl_kappa_grad: built for periodic plans only");
   if (!plan->ks.grad_p_var)
-    return fail(HL_ERR_UNSUPPORTED, "hl_kappa_grad: built for d = 1 (all m) and d = 2 (m <= 2), HL_FP64 and HL_FP32");
+    return fail(HL_ERR_UNSUPPORTED, "hl_kappa_grad: built for d = 1 (all m) and d = 2 (m <= 3), HL_FP64 and HL_FP32");
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hl_kappa_grad: pending work failed");
   if ((st = ensure_var_gradient(plan)) != HL_OK) return st;

@@ -255,6 +255,7 @@ hipError_t launch_grad_p_var(const PlanView& pv, const void* pb, const void* u, 
                              hipStream_t s) {
   constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
   const Grid& g = pv.gp;
+  if (g.tx != 64 || g.ty != 1) return hipErrorInvalidConfiguration;  // per-lane LDS arrays of 64 lanes
   hipLaunchKernelGGL((grad_p_var<D, M, S>), grid_shape(g), block_shape(g), 0, s, S::make(pb, 1, NC, g.onodes),
                      S::make(u, D, NC, g.snodes), S::make(pv.kap_p, 1, NP, g.onodes), gk,
                      S::make(scr, D, NP, g.onodes), g, var_args<S>(pv));
@@ -266,6 +267,7 @@ hipError_t launch_grad_u_var(const PlanView& pv, const void* ub, const void* p, 
                              hipStream_t s) {
   constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
   const Grid& g = pv.gu;
+  if (g.tx != 64 || g.ty != 1) return hipErrorInvalidConfiguration;  // per-lane LDS arrays of 64 lanes
   hipLaunchKernelGGL((grad_u_var<D, M, S>), grid_shape(g), block_shape(g), 0, s, S::make(ub, D, NC, g.onodes),
                      S::make(p, 1, NC, g.snodes), S::make(pv.kap_u, 1, NP, g.onodes), gk,
                      S::make(scr, 1, NP, g.onodes), g, var_args<S>(pv));
@@ -300,7 +302,7 @@ constexpr bool kPlain<PlainStore<W>> = true;
 template <int D, int M, class S>
 constexpr bool kVarBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 3) || (D == 3 && M <= 1));
 template <int D, int M, class S>
-constexpr bool kVarGradBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 2));
+constexpr bool kVarGradBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 3));
 
 template <int D, int M, class S>
 void batch_desc(const BatchShot* shots, int n, bool var, std::vector<unsigned char>* pdesc,
@@ -394,8 +396,8 @@ inline bool make_set(KernelSet* out) {
   out->adj_u = nullptr;
   out->adj_u_walls = nullptr;
   out->ghost_zero = nullptr;
-  // adjoint: FP64 and FP32 storage, nc <= 27 (1D all m, 2D m <= 4, 3D m <= 2)
-  if constexpr (kPlain<S> && Dims<D, M>::NC <= kAdjointMaxNC) {
+  // adjoint: FP64 and FP32 storage, every (d, m)
+  if constexpr (kPlain<S>) {
     out->adj_p = &launch_adjoint<D, M, S, true>;
     out->adj_u = &launch_adjoint<D, M, S, false>;
     out->adj_u_walls = &launch_adj_u_walls<D, M, S>;

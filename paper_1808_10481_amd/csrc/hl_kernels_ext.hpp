@@ -22,14 +22,33 @@ namespace hl {
 //   PTYPE = true:  out = Pb (1 component), in = Ub (D components)
 //   PTYPE = false: out = Ub (D components), in = Pb (1 component)
 // ---------------------------------------------------------------------------
-constexpr int kAdjointMaxNC = 27;  // register budget: nc inputs + nc accumulators
+// Output rows per pass: all nc at once up to nc = 27 (nc inputs plus nc
+// accumulators in registers); beyond that (2D m >= 5, 3D m = 3) passes of 16
+// rows, each re-reading the corner data (L1/L2 hits) so that the registers
+// and the unrolled code stay bounded.
+constexpr int kAdjointMaxNC = 27;
+template <int NC>
+constexpr int kAdjRows = NC <= kAdjointMaxNC ? NC : 16;
+
+// acc[r] += sum_c Tb[r][c] src[c] for the rows r0 + r < NC of one pass.
+template <int NC, int RB, typename T>
+__device__ __forceinline__ void dense_rows(const T* __restrict__ Tb, int r0, const T* src, T* acc) {
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    if (r0 + r >= NC) break;
+    // keep the scalar table loads of one row together (SGPR pressure)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[r] = fma(Tb[r * NC + c], src[c], acc[r]);
+  }
+}
 
 template <int D, int M, class S, bool PTYPE>
 __device__ __forceinline__ void adjoint_half_body(typename S::View out, typename S::View in,
                                                   const typename S::C* __restrict__ tab, Grid g, int blk) {
   using T = typename S::C;
   constexpr int NC = Dims<D, M>::NC, NO = PTYPE ? 1 : D, NI = PTYPE ? D : 1;
-  static_assert(NC <= kAdjointMaxNC, "adjoint kernels are built for nc <= 27");
+  constexpr int RB = kAdjRows<NC>, NRB = (NC + RB - 1) / RB;
   int32_t j[3];
   if (!node_of_block<D>(g, blk, j)) return;
   uint32_t cn[1 << D];
@@ -37,28 +56,27 @@ __device__ __forceinline__ void adjoint_half_body(typename S::View out, typename
   const uint32_t n0 = out_index<D>(g, j);
 #pragma unroll 1
   for (int io = 0; io < NO; ++io) {
-    T acc[NC];
-#pragma unroll
-    for (int r = 0; r < NC; ++r) acc[r] = T(0);
-#pragma unroll
-    for (int e = 0; e < (1 << D); ++e) {
 #pragma unroll 1
-      for (int ii = 0; ii < NI; ++ii) {
-        T src[NC];
+    for (int rb = 0; rb < NRB; ++rb) {
+      T acc[RB];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) src[c] = S::load(in, ii * NC + c, cn[e]);
-        const T* __restrict__ Tb = tab + ((int64_t)((e * NO + io) * NI + ii) * NC) * NC;
+      for (int r = 0; r < RB; ++r) acc[r] = T(0);
 #pragma unroll
-        for (int r = 0; r < NC; ++r) {
-          // keep the scalar table loads of one row together (SGPR pressure)
-          __builtin_amdgcn_sched_barrier(0);
+      for (int e = 0; e < (1 << D); ++e) {
+#pragma unroll 1
+        for (int ii = 0; ii < NI; ++ii) {
+          T src[NC];
 #pragma unroll
-          for (int c = 0; c < NC; ++c) acc[r] = fma(Tb[r * NC + c], src[c], acc[r]);
+          for (int c = 0; c < NC; ++c) src[c] = S::load(in, ii * NC + c, cn[e]);
+          dense_rows<NC, RB>(tab + ((int64_t)((e * NO + io) * NI + ii) * NC + rb * RB) * NC, rb * RB, src, acc);
         }
       }
-    }
 #pragma unroll
-    for (int r = 0; r < NC; ++r) S::update(out, io * NC + r, n0, [&](T x) { return x - acc[r]; });
+      for (int r = 0; r < RB; ++r) {
+        if (rb * RB + r >= NC) break;
+        S::update(out, io * NC + rb * RB + r, n0, [&](T x) { return x - acc[r]; });
+      }
+    }
   }
 }
 
@@ -86,8 +104,7 @@ template <int D, int M, class S>
 __global__ void __launch_bounds__(256) adjoint_walls_at(typename S::View scr, typename S::View pb,
                                                         const typename S::C* __restrict__ tab, Grid g) {
   using T = typename S::C;
-  constexpr int NC = Dims<D, M>::NC;
-  static_assert(NC <= kAdjointMaxNC, "adjoint kernels are built for nc <= 27");
+  constexpr int NC = Dims<D, M>::NC, RB = kAdjRows<NC>, NRB = (NC + RB - 1) / RB;
   int32_t j[3];
   if (!node_of_block<D>(g, blockIdx.x, j)) return;
   int32_t lo[3] = {0, 0, 0};
@@ -101,34 +118,34 @@ __global__ void __launch_bounds__(256) adjoint_walls_at(typename S::View scr, ty
   const uint32_t n0 = node_index<D>(j[0], j[1], j[2], g.oext);
 #pragma unroll 1
   for (int io = 0; io < D; ++io) {
-    T acc[NC];
+#pragma unroll 1
+    for (int rb = 0; rb < NRB; ++rb) {
+      T acc[RB];
 #pragma unroll
-    for (int r = 0; r < NC; ++r) acc[r] = T(0);
+      for (int r = 0; r < RB; ++r) acc[r] = T(0);
 #pragma unroll
-    for (int e = 0; e < (1 << D); ++e) {
-      bool valid = true;
-      int32_t c3[3] = {0, 0, 0};
+      for (int e = 0; e < (1 << D); ++e) {
+        bool valid = true;
+        int32_t c3[3] = {0, 0, 0};
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        const bool up = (e >> k) & 1;
-        valid = valid && (up ? vhi[k] : vlo[k]);
-        c3[k] = lo[k] + (up ? 1 : 0);
+        for (int k = 0; k < D; ++k) {
+          const bool up = (e >> k) & 1;
+          valid = valid && (up ? vhi[k] : vlo[k]);
+          c3[k] = lo[k] + (up ? 1 : 0);
+        }
+        if (!valid) continue;
+        const uint32_t cn = node_index<D>(c3[0], c3[1], c3[2], g.sext);
+        T src[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) src[c] = S::load(pb, c, cn);
+        dense_rows<NC, RB>(tab + ((int64_t)(e * D + io) * NC + rb * RB) * NC, rb * RB, src, acc);
       }
-      if (!valid) continue;
-      const uint32_t cn = node_index<D>(c3[0], c3[1], c3[2], g.sext);
-      T src[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) src[c] = S::load(pb, c, cn);
-      const T* __restrict__ Tb = tab + ((int64_t)(e * D + io) * NC) * NC;
-#pragma unroll
-      for (int r = 0; r < NC; ++r) {
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[r] = fma(Tb[r * NC + c], src[c], acc[r]);
+      for (int r = 0; r < RB; ++r) {
+        if (rb * RB + r >= NC) break;
+        S::update(scr, io * NC + rb * RB + r, n0, [&](T x) { return x - acc[r]; });
       }
     }
-#pragma unroll
-    for (int r = 0; r < NC; ++r) S::update(scr, io * NC + r, n0, [&](T x) { return x - acc[r]; });
   }
 }
 
@@ -249,6 +266,81 @@ struct VarArgs {
   T ratio[9];  // w_k / w_{k-1} = (dt/2)^2 / (2k (2k+1)), k = 1..kmax (kmax <= 8)
   T ih[3];     // 1 / h_k
 };
+
+// The truncated products of the adjoint kernels load their kappa terms in
+// groups of kKappaGroup, each group issued while the previous one is applied.
+// The plane base of every load is formed from an opaque scalar zero taken
+// once per group: otherwise the compiler keeps one 64-bit address per kappa
+// plane for the whole kernel (2 VGPRs per term: 128 at 2D m = 3), and with
+// the scheduling barrier after each group it cannot hoist every load of a
+// product to its start either.
+constexpr int kKappaGroup = 4;
+
+// out_b += kappa_A f_{b-A} (TR = false: T[kappa f]) or out_b += kappa_A f_{A+b}
+// (TR = true: T^T[kappa] f), for one term A.
+template <int D, int M, bool TR, int A, typename T>
+__device__ __forceinline__ void kterm_apply(T ka, const T* f, T* out) {
+  constexpr int N2 = 2 * M + 2, AX = A % N2, AY = (A / N2) % N2, AZ = A / (N2 * N2);
+  constexpr int NY = D > 1 ? N2 : 1, NZ = D > 2 ? N2 : 1;
+#pragma unroll
+  for (int bz = 0; bz + AZ < NZ; ++bz)
+#pragma unroll
+    for (int by = 0; by + AY < NY; ++by)
+#pragma unroll
+      for (int bx = 0; bx + AX < N2; ++bx) {
+        const int lo = bx + N2 * (by + N2 * bz), hi = (bx + AX) + N2 * ((by + AY) + N2 * (bz + AZ));
+        if constexpr (TR)
+          out[lo] = fma(ka, f[hi], out[lo]);
+        else
+          out[hi] = fma(ka, f[lo], out[hi]);
+      }
+}
+
+template <int D, int M, bool TR, int BASE, typename T, int... I>
+__device__ __forceinline__ void kgroup_apply(const T* kc, const T* f, T* out, std::integer_sequence<int, I...>) {
+  (kterm_apply<D, M, TR, BASE + I>(kc[I], f, out), ...);
+}
+
+// kb[i] = kappa_{BASE + i} for the terms BASE + i < NP.
+template <class S, int BASE, int NP>
+__device__ __forceinline__ void kgroup_load(const typename S::View& kv, uint32_t n0, typename S::C* kb) {
+  int zero;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
+#pragma unroll
+  for (int i = 0; i < kKappaGroup; ++i)
+    if (BASE + i < NP) kb[i] = S::load(kv, BASE + i + zero, n0);
+}
+
+template <int D, int M, bool TR, class S, int GRP>
+__device__ __forceinline__ void kgroup_step(const typename S::View& kv, uint32_t n0, const typename S::C* f,
+                                            typename S::C* out, typename S::C (*kb)[kKappaGroup]) {
+  constexpr int G = kKappaGroup, NP = VK<D, M>::NP, NG = (NP + G - 1) / G;
+  constexpr int CNT = NP - GRP * G < G ? NP - GRP * G : G;
+  if constexpr (GRP + 1 < NG) kgroup_load<S, (GRP + 1) * G, NP>(kv, n0, kb[(GRP + 1) & 1]);
+  kgroup_apply<D, M, TR, GRP * G>(kb[GRP & 1], f, out, std::make_integer_sequence<int, CNT>{});
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int D, int M, bool TR, class S, int... GRP>
+__device__ __forceinline__ void kgroup_steps(const typename S::View& kv, uint32_t n0, const typename S::C* f,
+                                             typename S::C* out, std::integer_sequence<int, GRP...>) {
+  typename S::C kb[2][kKappaGroup];
+  kgroup_load<S, 0, VK<D, M>::NP>(kv, n0, kb[0]);
+  (kgroup_step<D, M, TR, S, GRP>(kv, n0, f, out, kb), ...);
+}
+
+// out = T[kappa f] (TR = false) or T^T[kappa] f (TR = true), kappa_a read
+// from plane a of the kappa array at node n0.  The same terms in the same
+// order as tprod.
+template <int D, int M, bool TR, class S>
+__device__ __forceinline__ void tprod_grouped(const typename S::View& kv, uint32_t n0, const typename S::C* f,
+                                              typename S::C* out) {
+  using T = typename S::C;
+  constexpr int NP = VK<D, M>::NP, NG = (NP + kKappaGroup - 1) / kKappaGroup;
+#pragma unroll
+  for (int b = 0; b < NP; ++b) out[b] = T(0);
+  kgroup_steps<D, M, TR, S>(kv, n0, f, out, std::make_integer_sequence<int, NG>{});
+}
 
 // Full interpolant c[b_x + N2 (b_y + N2 b_z)] of one component from its 2^D
 // corner blocks.
@@ -519,55 +611,74 @@ __global__ void __launch_bounds__(256) u_half_var(typename S::View u, typename S
 // recomputed from t_0 for each k: no per-node stack of kmax polynomials.
 // ---------------------------------------------------------------------------
 
-// out_b += kappa_A g_{A+b} (one term of the transposed truncated product).
-template <int D, int M, int A, class S>
-__device__ __forceinline__ void tprodT_term(const typename S::View& kv, uint32_t n0, const typename S::C* g,
-                                            typename S::C* out) {
-  constexpr int N2 = 2 * M + 2, AX = A % N2, AY = A / N2, NY = D > 1 ? N2 : 1;
-  const typename S::C ka = S::load(kv, A, n0);
-#pragma unroll
-  for (int by = 0; by + AY < NY; ++by)
-#pragma unroll
-    for (int bx = 0; bx + AX < N2; ++bx) out[bx + N2 * by] = fma(ka, g[(bx + AX) + N2 * (by + AY)], out[bx + N2 * by]);
-}
+// Cell-polynomial slots on which the adjoint data y of a node can be nonzero:
+// b in {0..m}^D (pressure side: the node's data block) or b = s + e_i with s
+// in {0..m}^D (velocity side: the derivatives of Q that the velocity takes).
+// y is held compactly on these slots.
+template <int D, int M, bool PSIDE>
+struct YSupport {
+  static constexpr int N2 = 2 * M + 2, NP = VK<D, M>::NP;
+  static constexpr bool in(int b) {
+    const int dg[3] = {b % N2, D > 1 ? (b / N2) % N2 : 0, D > 2 ? b / (N2 * N2) : 0};
+    int over = 0, top = 0, sum = 0;
+    for (int k = 0; k < D; ++k) {
+      if (dg[k] > M + 1) return false;
+      top += dg[k] == M + 1;
+      over += dg[k] > M;
+      sum += dg[k];
+    }
+    return PSIDE ? over == 0 : top <= 1 && sum > 0;
+  }
+  static constexpr int count() {
+    int c = 0;
+    for (int b = 0; b < NP; ++b) c += in(b);
+    return c;
+  }
+  static constexpr int idx(int b) {  // compact slot of b, -1 off the support
+    int c = 0;
+    for (int x = 0; x < b; ++x) c += in(x);
+    return in(b) ? c : -1;
+  }
+  static constexpr int NY = count();
+};
 
-template <int D, int M, class S, int... A>
-__device__ __forceinline__ void tprodT_terms(const typename S::View& kv, uint32_t n0, const typename S::C* g,
-                                             typename S::C* out, std::integer_sequence<int, A...>) {
-  (tprodT_term<D, M, A, S>(kv, n0, g, out), ...);
-}
+// Per-work-item arrays in LDS, slot (a, b) of lane l at [(a NP + b) 64 + l]:
+// the adjoint kernels run 64 work-items per workgroup, consecutive lanes in
+// consecutive banks.
+template <typename T>
+struct LaneLds {
+  T* base;
+  int lane;
+  __device__ __forceinline__ T& operator()(int a, int b, int np) const { return base[(a * np + b) * 64 + lane]; }
+};
 
-// out = T^T[kappa] g.
-template <int D, int M, class S>
-__device__ __forceinline__ void tprodT(const typename S::View& kv, uint32_t n0, const typename S::C* g,
-                                       typename S::C* out) {
-  using T = typename S::C;
-  constexpr int NP = VK<D, M>::NP;
-#pragma unroll
-  for (int b = 0; b < NP; ++b) out[b] = T(0);
-  tprodT_terms<D, M, S>(kv, n0, g, out, std::make_integer_sequence<int, NP>{});
-}
+// The gradient accumulators live in LDS (slot GS); t_0 and, on the pressure
+// side, f as well when a cell polynomial takes 512 bytes or more (FP64 at
+// 2D m = 3), where registers would spill to scratch.
+template <int D, int M, typename T>
+constexpr bool kGradStage = sizeof(T) * VK<D, M>::NP >= 512;
 
 // grad_A += sum_b lam_{A+b} g_b (the kappa_A derivative of <lam, T[kappa g]>).
 template <int D, int M, int A, typename T>
-__device__ __forceinline__ void corr_term(const T* lam, const T* g, T* grad) {
-  constexpr int N2 = 2 * M + 2, AX = A % N2, AY = A / N2, NY = D > 1 ? N2 : 1;
-  T acc = grad[A];
+__device__ __forceinline__ void corr_term(const T* lam, const T* g, const LaneLds<T>& L, int gs) {
+  constexpr int N2 = 2 * M + 2, AX = A % N2, AY = A / N2, NY = D > 1 ? N2 : 1, NP = VK<D, M>::NP;
+  T acc = L(gs, A, NP);
 #pragma unroll
   for (int by = 0; by + AY < NY; ++by)
 #pragma unroll
     for (int bx = 0; bx + AX < N2; ++bx) acc = fma(lam[(bx + AX) + N2 * (by + AY)], g[bx + N2 * by], acc);
-  grad[A] = acc;
+  L(gs, A, NP) = acc;
 }
 
 template <int D, int M, typename T, int... A>
-__device__ __forceinline__ void corr_terms(const T* lam, const T* g, T* grad, std::integer_sequence<int, A...>) {
-  (corr_term<D, M, A>(lam, g, grad), ...);
+__device__ __forceinline__ void corr_terms(const T* lam, const T* g, const LaneLds<T>& L, int gs,
+                                           std::integer_sequence<int, A...>) {
+  (corr_term<D, M, A>(lam, g, L, gs), ...);
 }
 
 template <int D, int M, typename T>
-__device__ __forceinline__ void corr(const T* lam, const T* g, T* grad) {
-  corr_terms<D, M>(lam, g, grad, std::make_integer_sequence<int, VK<D, M>::NP>{});
+__device__ __forceinline__ void corr(const T* lam, const T* g, const LaneLds<T>& L, int gs) {
+  corr_terms<D, M>(lam, g, L, gs, std::make_integer_sequence<int, VK<D, M>::NP>{});
 }
 
 // out = sc Lap^T f: sc sum_i (b_i - 1) b_i / h_i^2 f_{b - 2 e_i}.
@@ -585,50 +696,67 @@ __device__ __forceinline__ void lapT_coef(const T* f, T* out, const T* ih, T sc)
   }
 }
 
-// The series part shared by both sides: given t_0 and y, returns lam_0 in lam
-// and adds sum_{k >= 1} sum_b lam_k[a + b] g_k[b] to grad.
-template <int D, int M, class S>
-__device__ __forceinline__ void adjoint_series(const typename S::View& kv, uint32_t n0, const typename S::C* t0,
-                                               const typename S::C* y, const VarArgs<typename S::C>& va,
-                                               typename S::C* lam, typename S::C* grad) {
+// The series part shared by both sides: given t_0 (registers t0r, or LDS
+// slot t0s when staged) and y (compact on its support), returns lam_0 in lam
+// and adds sum_{k >= 1} sum_b lam_k[a + b] g_k[b] to the gradient (LDS slot gs).
+template <int D, int M, bool PSIDE, class S>
+__device__ __forceinline__ void adjoint_series(const typename S::View& kv, uint32_t n0,
+                                               const LaneLds<typename S::C>& L, const typename S::C* t0r, int t0s,
+                                               int gs, const typename S::C* yc, const VarArgs<typename S::C>& va,
+                                               typename S::C* lam) {
   using T = typename S::C;
+  using Y = YSupport<D, M, PSIDE>;
   constexpr int NP = VK<D, M>::NP;
+  constexpr bool STAGE = kGradStage<D, M, T>;
 #pragma unroll
-  for (int b = 0; b < NP; ++b) lam[b] = y[b];
+  for (int b = 0; b < NP; ++b) {
+    const int yi = Y::idx(b);
+    lam[b] = yi >= 0 ? yc[yi < 0 ? 0 : yi] : T(0);
+  }
 #pragma unroll 1
   for (int k = VK<D, M>::KMAX; k >= 1; --k) {
     T t[NP], l[NP];
 #pragma unroll
-    for (int b = 0; b < NP; ++b) t[b] = t0[b];
+    for (int b = 0; b < NP; ++b) t[b] = STAGE ? L(t0s, b, NP) : t0r[b];
 #pragma unroll 1
     for (int q = 1; q < k; ++q) {  // t = t_{k-1}
       lap_coef<D, M>(t, l, va.ih, va.ratio[q]);
-      tprod<D, M, S>(kv, n0, l, t);
+      tprod_grouped<D, M, false, S>(kv, n0, l, t);
     }
     lap_coef<D, M>(t, l, va.ih, va.ratio[k]);  // g_k
-    corr<D, M>(lam, l, grad);
-    tprodT<D, M, S>(kv, n0, lam, t);
+    corr<D, M>(lam, l, L, gs);
+    tprod_grouped<D, M, true, S>(kv, n0, lam, t);
     lapT_coef<D, M>(t, l, va.ih, va.ratio[k]);
 #pragma unroll
-    for (int b = 0; b < NP; ++b) lam[b] = y[b] + l[b];
+    for (int b = 0; b < NP; ++b) {
+      const int yi = Y::idx(b);
+      lam[b] = (yi >= 0 ? yc[yi < 0 ? 0 : yi] : T(0)) + l[b];
+    }
   }
 }
 
 // Pressure side at primal node j: with Pb the adjoint pressure and U_t the
 // velocity before the step, gk -= dS/dkappa (FP64 accumulators, one plane per
 // kappa coefficient) and rho_i = d S / d c^(i) (D NP planes of scratch).
+// 64 work-items per workgroup (a 64 x 1 tile).
 template <int D, int M, class S>
-__global__ void __launch_bounds__(256) grad_p_var(typename S::View pb, typename S::View u, typename S::View kp,
-                                                  double* __restrict__ gk, typename S::View rho, Grid g,
-                                                  VarArgs<typename S::C> va) {
+__global__ void __launch_bounds__(64) grad_p_var(typename S::View pb, typename S::View u, typename S::View kp,
+                                                 double* __restrict__ gk, typename S::View rho, Grid g,
+                                                 VarArgs<typename S::C> va) {
+  static_assert(D <= 2, "the adjoint of the variable-kappa half-steps is built for d <= 2");
   using T = typename S::C;
+  using Y = YSupport<D, M, true>;
   constexpr int N2 = 2 * M + 2, MP = M + 1, NP = VK<D, M>::NP, NC = Dims<D, M>::NC;
+  constexpr bool STAGE = kGradStage<D, M, T>;
+  constexpr int FS = 0, T0S = 1, GS = STAGE ? 2 : 0;  // LDS slots
+  __shared__ T lds[(STAGE ? 3 : 1) * NP * 64];
+  const LaneLds<T> L{lds, (int)threadIdx.x};
   int32_t j[3];
   if (!node_of_block<D>(g, blockIdx.x, j)) return;
   uint32_t cn[1 << D];
   corner_nodes<D>(g, j, cn);  // dual q = j - 1 + e
   const uint32_t n0 = out_index<D>(g, j);
-  T f[NP];  // f = w_0 div c
+  T f[NP], t0[NP];  // f = w_0 div c, t_0 = T[kappa f]
 #pragma unroll
   for (int b = 0; b < NP; ++b) f[b] = T(0);
 #pragma unroll
@@ -643,21 +771,29 @@ __global__ void __launch_bounds__(256) grad_p_var(typename S::View pb, typename 
       if (bi + 1 < N2) f[b] = fma(T(bi + 1) * w, c[b + st], f[b]);
     }
   }
-  T y[NP], t0[NP], lam[NP], grad[NP];
+  tprod_grouped<D, M, false, S>(kp, n0, f, t0);
 #pragma unroll
   for (int b = 0; b < NP; ++b) {
-    y[b] = T(0);
-    grad[b] = T(0);
+    if (STAGE) {
+      L(FS, b, NP) = f[b];
+      L(T0S, b, NP) = t0[b];
+    }
+    L(GS, b, NP) = T(0);
   }
+  T yc[Y::NY];
 #pragma unroll
-  for (int s = 0; s < NC; ++s) y[(s % MP) + N2 * (s / MP)] = S::load(pb, s, n0);
-  tprod<D, M, S>(kp, n0, f, t0);
-  adjoint_series<D, M, S>(kp, n0, t0, y, va, lam, grad);
-  corr<D, M>(lam, f, grad);  // k = 0: t_0 = T[kappa f]
+  for (int s = 0; s < NC; ++s) yc[Y::idx((s % MP) + N2 * (s / MP))] = S::load(pb, s, n0);
+  T lam[NP];
+  adjoint_series<D, M, true, S>(kp, n0, L, t0, T0S, GS, yc, va, lam);
+  if (STAGE) {
 #pragma unroll
-  for (int b = 0; b < NP; ++b) gk[(size_t)b * g.onodes + n0] -= (double)grad[b];
+    for (int b = 0; b < NP; ++b) f[b] = L(FS, b, NP);
+  }
+  corr<D, M>(lam, f, L, GS);  // k = 0: t_0 = T[kappa f]
+#pragma unroll
+  for (int b = 0; b < NP; ++b) gk[(size_t)b * g.onodes + n0] -= (double)L(GS, b, NP);
   T phi[NP];  // dS/df
-  tprodT<D, M, S>(kp, n0, lam, phi);
+  tprod_grouped<D, M, true, S>(kp, n0, lam, phi);
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     const T w = va.w0 * va.ih[i];
@@ -672,39 +808,49 @@ __global__ void __launch_bounds__(256) grad_p_var(typename S::View pb, typename 
 
 // Velocity side at dual node q: with Ub the adjoint velocity and P' the
 // pressure after the step's pressure half-step, gk -= dS/dkappa and
-// z = dS/dc (NP planes of scratch).
+// z = dS/dc (NP planes of scratch).  64 work-items per workgroup.
 template <int D, int M, class S>
-__global__ void __launch_bounds__(256) grad_u_var(typename S::View ub, typename S::View p, typename S::View ku,
-                                                  double* __restrict__ gk, typename S::View z, Grid g,
-                                                  VarArgs<typename S::C> va) {
+__global__ void __launch_bounds__(64) grad_u_var(typename S::View ub, typename S::View p, typename S::View ku,
+                                                 double* __restrict__ gk, typename S::View z, Grid g,
+                                                 VarArgs<typename S::C> va) {
+  static_assert(D <= 2, "the adjoint of the variable-kappa half-steps is built for d <= 2");
   using T = typename S::C;
+  using Y = YSupport<D, M, false>;
   constexpr int N2 = 2 * M + 2, MP = M + 1, NP = VK<D, M>::NP, NC = Dims<D, M>::NC;
+  constexpr bool STAGE = kGradStage<D, M, T>;
+  constexpr int T0S = 0, GS = STAGE ? 1 : 0;  // LDS slots
+  __shared__ T lds[(STAGE ? 2 : 1) * NP * 64];
+  const LaneLds<T> L{lds, (int)threadIdx.x};
   int32_t j[3];
   if (!node_of_block<D>(g, blockIdx.x, j)) return;
   uint32_t cn[1 << D];
   corner_nodes<D>(g, j, cn);  // primal j = q + e
   const uint32_t n0 = out_index<D>(g, j);
-  T t0[NP], y[NP], lam[NP], grad[NP];
+  T t0[NP];
   interp_full<D, M, S>(p, 0, cn, t0);
 #pragma unroll
   for (int b = 0; b < NP; ++b) {
     t0[b] *= va.w0;
-    y[b] = T(0);
-    grad[b] = T(0);
+    if (STAGE) L(T0S, b, NP) = t0[b];
+    L(GS, b, NP) = T(0);
   }
   // S = sum_i sum_s Ub_i[s] (s_i + 1) / h_i Q[s + e_i]
+  T yc[Y::NY];
+#pragma unroll
+  for (int a = 0; a < Y::NY; ++a) yc[a] = T(0);
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
       const int sx = s % MP, sy = s / MP;
       const int si = i == 0 ? sx : sy;
-      y[(sx + (i == 0)) + N2 * (sy + (i == 1))] += T(si + 1) * va.ih[i] * S::load(ub, i * NC + s, n0);
+      yc[Y::idx((sx + (i == 0)) + N2 * (sy + (i == 1)))] += T(si + 1) * va.ih[i] * S::load(ub, i * NC + s, n0);
     }
-  adjoint_series<D, M, S>(ku, n0, t0, y, va, lam, grad);
+  T lam[NP];
+  adjoint_series<D, M, false, S>(ku, n0, L, t0, T0S, GS, yc, va, lam);
 #pragma unroll
   for (int b = 0; b < NP; ++b) {
-    gk[(size_t)b * g.onodes + n0] -= (double)grad[b];
+    gk[(size_t)b * g.onodes + n0] -= (double)L(GS, b, NP);
     S::store(z, b, n0, va.w0 * lam[b]);
   }
 }

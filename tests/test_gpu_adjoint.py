@@ -30,8 +30,10 @@ def _prob(d, m, K, dt, kappa):
     return oracle.Problem(d, m, tuple(K), tuple(1.0 for _ in K), dt, kappa)
 
 
+# nc > 27 (2D m >= 5, 3D m = 3) runs the dense blocks in passes of 16 rows
 CASES = [(1, 0, (9,)), (1, 3, (37,)), (1, 7, (11,)), (2, 1, (19, 6)), (2, 3, (13, 7)), (2, 4, (6, 5)),
-         (3, 1, (9, 5, 4)), (3, 2, (7, 4, 3)), (3, 2, (2, 2, 2))]
+         (2, 5, (7, 5)), (3, 1, (9, 5, 4)), (3, 2, (7, 4, 3)), (3, 2, (2, 2, 2)), (3, 3, (5, 4, 3)),
+         (3, 3, (2, 2, 2))]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -100,7 +102,8 @@ def test_autograd_backward_is_the_adjoint():
     _close(Ug, Ur, 1e-12 * n, 1e-11 * n)
 
 
-WALL_CASES = [(1, 2, (9,)), (2, 1, (11, 6)), (2, 3, (7, 5)), (3, 1, (5, 4, 3)), (3, 2, (4, 3, 3)), (3, 2, (2, 2, 2))]
+WALL_CASES = [(1, 2, (9,)), (2, 1, (11, 6)), (2, 3, (7, 5)), (2, 5, (5, 4)), (3, 1, (5, 4, 3)), (3, 2, (4, 3, 3)),
+              (3, 2, (2, 2, 2)), (3, 3, (3, 2, 2))]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -183,8 +186,7 @@ def test_walls_kappa_gradient_matches_oracle(d, m, K, n, prec):
 
 
 @pytest.mark.parametrize("kw", [dict(d=2, m=2, cells=(8, 8), boundary="walls", precision="fp32_comp"),
-                                dict(d=2, m=2, cells=(8, 8), precision="fp32_comp"),
-                                dict(d=3, m=3, cells=(4, 4, 4)), dict(d=2, m=5, cells=(8, 8))])
+                                dict(d=2, m=2, cells=(8, 8), precision="fp32_comp")])
 def test_adjoint_unsupported_cases(kw):
     plan = hl.Plan(**kw)
     p, u = plan.alloc()
@@ -203,7 +205,7 @@ def test_gradient_needs_forward_state():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("d,m,K,n", [(1, 3, (24,), 30), (2, 2, (16, 12), 12), (3, 1, (8, 6, 5), 6)])
+@pytest.mark.parametrize("d,m,K,n", [(1, 3, (24,), 30), (2, 2, (16, 12), 12), (3, 1, (8, 6, 5), 6), (3, 3, (4, 3, 3), 2)])
 def test_kappa_gradient_matches_oracle(d, m, K, n, prec):
     """d/dkappa of <Pb, P_n> + <Ub, U_n> and the adjoint state against the
     oracle (stored trajectory); the library recomputes the trajectory by the

@@ -61,7 +61,8 @@ def _setup(d, m, K, prec, seed, smooth, c=np.sqrt(2.0), cfl=0.5):
     return rng, plan, prob, kp, ku
 
 
-CASES = [(1, m, (37,)) for m in (0, 1, 3, 7)] + [(2, m, (70, 9)) for m in (0, 1, 2)] + [(2, 1, (2, 3))]
+CASES = ([(1, m, (37,)) for m in (0, 1, 3, 7)] + [(2, m, (70, 9)) for m in (0, 1, 2)] + [(2, 1, (2, 3))]
+         + [(2, 3, (66, 5))])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -99,7 +100,8 @@ def _receivers(rng, K, n):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("d,m,K,nsteps,seg", [(1, 3, (40,), 7, 3), (2, 2, (24, 18), 9, None), (2, 1, (66, 10), 5, 2)])
+@pytest.mark.parametrize("d,m,K,nsteps,seg", [(1, 3, (40,), 7, 3), (2, 2, (24, 18), 9, None), (2, 1, (66, 10), 5, 2),
+                                                (2, 3, (12, 10), 4, 2)])
 def test_checkpointed_receiver_gradient_matches_oracle(d, m, K, nsteps, seg, prec):
     _say(f"[kgrad] receivers d={d} m={m} K={K} n={nsteps} seg={seg} {prec}")
     rng, plan, prob, kp, ku = _setup(d, m, K, prec, 1300 + 10 * d + m, smooth=True)
@@ -189,6 +191,21 @@ def test_gradient_matches_central_differences_on_8_directions():
     rec = _receivers(rng, K, 4)
     data = rng.normal(size=(nsteps, len(rec))) * 0.01
     _fd_check(plan, kp, ku, p0, u0, nsteps, rec, data, 8, rng, 1e-3, 1e-7)
+
+
+def test_gradient_m3_central_differences_on_4_directions():
+    """2D m = 3 (the batched workload's order), FP64: the kappa-data gradient
+    against central differences of the GPU forward on 4 directions."""
+    _say("[kgrad] FD, 4 directions, 2D m=3 (20, 16) FP64")
+    d, m, K = 2, 3, (20, 16)
+    rng, plan, prob, kp, ku = _setup(d, m, K, "fp64", 1450, smooth=True)
+    p0, u0 = plan.alloc()
+    centre = tuple(rng.uniform(0.3, 0.7, d))
+    plan.init(p0, u0, inputs.gaussian_pulse(d, m, K, (1.0,) * d, centre, 0.1), np.zeros(plan.host_shapes()[1]))
+    nsteps = 8
+    rec = _receivers(rng, K, 4)
+    data = rng.normal(size=(nsteps, len(rec))) * 0.01
+    _fd_check(plan, kp, ku, p0, u0, nsteps, rec, data, 4, rng, 1e-3, 1e-7)
 
 
 def test_gradient_full_size_512_m2_central_differences():
