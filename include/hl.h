@@ -203,7 +203,7 @@ hl_status hl_add_source(hl_plan_t plan, void* p, const void* g, double a, void* 
  * this length is a reading for d >= 2).  The
  * plan's c must be the largest speed (it sets the CFL check and dt).  Both
  * pointers NULL: back to the plan's constant kappa = c^2.  Built for
- * d = 1 (all m), d = 2 (m <= 3) and d = 3 (m <= 1), HL_FP64 and HL_FP32,
+ * d = 1 and d = 2 (all m) and d = 3 (m <= 1), HL_FP64 and HL_FP32,
  * periodic or walls
  * (HL_ERR_UNSUPPORTED otherwise); hl_adjoint_step then returns
  * HL_ERR_UNSUPPORTED.  Synchronous. */
@@ -297,14 +297,20 @@ hl_status hl_tune(hl_plan_t plan, const void* p, const void* u, int32_t reps, vo
  * the adjoint of the truncated-product recurrence (recomputing its forward
  * terms) and spread the result over the neighbouring cells with a gather (no
  * atomics), through a plan-owned scratch of d (2m+2)^d planes allocated with
- * the accumulators on first use (zeroed then).  Built for periodic plans,
- * d = 1 (all m) and d = 2 (m <= 3), HL_FP64 and HL_FP32; HL_ERR_UNSUPPORTED
+ * the accumulators on first use (zeroed then).  Reflecting walls (Sec. 5):
+ * the step undone is P' = P - A G U, U' = U - B P' with G the ghost refresh,
+ * so u_prev's ghost layer is refreshed in a plan-owned copy before A_kappa
+ * reads it, the ghost slots of u_bar are cleared and stay zero, and A^T p_bar
+ * is formed on the whole padded velocity array and folded into the nodes the
+ * ghosts mirror (plan-owned scratch arrays, allocated on first use).  Built
+ * for d = 1 (all m) and d = 2 (m <= 3), HL_FP64 and HL_FP32; HL_ERR_UNSUPPORTED
  * otherwise, or without kappa data.  Asynchronous. */
 hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const void* p_next,
                               const void* u_prev, void* stream);
 
 /* The accumulated kappa gradient: grad_p (for kappa_p) and grad_u (for
- * kappa_u), host FP64 arrays in hl_set_kappa's layout, either may be NULL.
+ * kappa_u), host FP64 arrays in hl_set_kappa's layout (with walls: K+1 primal
+ * nodes and K dual nodes per dimension), either may be NULL.
  * reset != 0 zeroes the accumulators afterwards.  Synchronous. */
 hl_status hl_kappa_grad(hl_plan_t plan, double* grad_p, double* grad_u, int reset);
 

@@ -38,6 +38,8 @@ from .hermite_lf import (  # noqa: F401
     kappa_gradient,
     adjoint_step_var,
     kappa_field_gradient,
+    adjoint_step_var_bruteforce,
+    kappa_field_gradient_fd,
     kmax_var,
     p_half_var,
     u_half_var,

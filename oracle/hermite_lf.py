@@ -887,6 +887,58 @@ def kappa_field_gradient(prob: Problem, P0, U0, Kp, Ku, Pbn, Ubn, nsteps: int, p
 
 
 # ---------------------------------------------------------------------------
+# Variable kappa with reflecting walls: the transpose and the kappa gradient
+# by their definitions (tiny grids).  For fixed kappa data the walled
+# variable-kappa step is linear in the state (P, U), so its transpose is read
+# off the unit responses: entry x of J^T y is <step(e_x), y>.  The gradient of
+# L = <Pbn, P_n> + <Ubn, U_n> with respect to one kappa entry is taken by
+# fourth-order central differences of the step (L is a polynomial in the
+# kappa data).  Both work on the periodic grid too, where they check the
+# structured adjoint above.
+# ---------------------------------------------------------------------------
+
+def step_matrix_var(prob: Problem, Kp, Ku) -> np.ndarray:
+    """J with (P', U') = J (P, U), states flattened as the P entries then the U
+    entries in their array order; one `step_var` per unit state entry."""
+    ps, us = prob.p_shape(), prob.u_shape()
+    npn, nun = int(np.prod(ps)), int(np.prod(us))
+    J = np.zeros((npn + nun, npn + nun))
+    for x in range(npn + nun):
+        e = np.zeros(npn + nun)
+        e[x] = 1.0
+        P1, U1 = step_var(prob, e[:npn].reshape(ps), e[npn:].reshape(us), Kp, Ku, 1)
+        J[:, x] = np.concatenate([P1.ravel(), U1.ravel()])
+    return J
+
+
+def adjoint_step_var_bruteforce(prob: Problem, Pb, Ub, Kp, Ku, nsteps: int = 1):
+    """(J^T)^nsteps (Pb, Ub) for the step J of `step_var` (either boundary)."""
+    J = step_matrix_var(prob, Kp, Ku)
+    v = np.concatenate([np.ravel(Pb), np.ravel(Ub)]).astype(np.float64)
+    for _ in range(int(nsteps)):
+        v = J.T @ v
+    npn = int(np.prod(prob.p_shape()))
+    return v[:npn].reshape(prob.p_shape()), v[npn:].reshape(prob.u_shape())
+
+
+def kappa_field_gradient_fd(prob: Problem, P0, U0, Kp, Ku, Pbn, Ubn, nsteps: int, entries, eps: float = 1e-3):
+    """dL/dkappa at the listed entries (field, flat index) - field 0: Kp,
+    field 1: Ku - of L = <Pbn, P_n> + <Ubn, U_n> after nsteps of `step_var`
+    from (P0, U0), by fourth-order central differences with step eps."""
+    def L(kp, ku):
+        P, U = step_var(prob, P0, U0, kp, ku, nsteps)
+        return float(np.sum(Pbn * P) + np.sum(Ubn * U))
+
+    out = []
+    for f, i in entries:
+        def Ls(s):
+            kp, ku = np.array(Kp, dtype=np.float64), np.array(Ku, dtype=np.float64)
+            (kp if f == 0 else ku).reshape(-1)[int(i)] += s
+            return L(kp, ku)
+        out.append((-Ls(2 * eps) + 8 * Ls(eps) - 8 * Ls(-eps) + Ls(-2 * eps)) / (12 * eps))
+    return np.array(out)
+
+# ---------------------------------------------------------------------------
 # Source term (periodic or walls)
 # ---------------------------------------------------------------------------
 # p_t = -kappa div u + z(x, t) with z = r(t) g(x) (Sec. 4, eq. (waveEq1D)

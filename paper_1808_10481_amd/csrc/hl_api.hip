@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <array>
 #include <functional>
 #include <cmath>
@@ -183,6 +184,8 @@ struct hl_plan_s {
   double* gku = nullptr;
   void* vscr = nullptr;
   void* wscr = nullptr;  // walls adjoint: A^T p_bar on the padded velocity array (kept zeroed)
+  void* vzw = nullptr;   // walls, variable-kappa adjoint: dS/dc on the padded dual array (ghost slots zero)
+  void* ucw = nullptr;   // walls, variable-kappa adjoint: copy of U_t with its ghost layer refreshed
   void* tab_dk = nullptr;
   void* tab_rev = nullptr;
   void* fp = nullptr;
@@ -1136,7 +1139,8 @@ hl_status hl_plan_destroy(hl_plan_t plan) {
   if (plan->dtab) (void)hipFree(plan->dtab);
   if (plan->dadj) (void)hipFree(plan->dadj);
   for (void* q : {plan->dkap_p, plan->dkap_u, plan->tab_dk, plan->tab_rev, plan->fp, plan->fu, plan->sp, plan->su,
-                  (void*)plan->gpart, (void*)plan->gkp, (void*)plan->gku, plan->vscr, plan->wscr})
+                  (void*)plan->gpart, (void*)plan->gkp, (void*)plan->gku, plan->vscr, plan->wscr, plan->vzw,
+                  plan->ucw})
     if (q) (void)hipFree(q);
   if (plan->dpartial) (void)hipFree(plan->dpartial);
   delete plan;
@@ -1293,7 +1297,7 @@ hl_status hl_set_kappa(hl_plan_t plan, const double* kappa_p, const double* kapp
     return HL_OK;
   }
   if (!plan->ks.p_half_var)
-    return fail(HL_ERR_UNSUPPORTED, "hl_set_kappa: variable kappa is built for d = 1, d = 2 with m <= 3 and d = 3 "
+    return fail(HL_ERR_UNSUPPORTED, "hl_set_kappa: variable kappa is built for d = 1, d = 2 and d = 3 "
                                     "with m <= 1, in HL_FP64 or HL_FP32");
   // host layout [nodes][b_1..b_d], b_k in 0..2m+1: the field layout of order
   // 2m+1 of p (primal nodes, K+1 per dimension with walls) and of one velocity
@@ -1554,7 +1558,6 @@ hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const vo
   hl_status st = check_plan(plan, "hl_adjoint_step_var");
   if (st != HL_OK) return st;
   if (!plan->var_kappa) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: the plan has no kappa data (hl_set_kappa)");
-  if (plan->walls) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: built for periodic plans only");
   if (!plan->ks.grad_p_var)
     return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: built for d = 1 (all m) and d = 2 (m <= 3), HL_FP64 and "
                                     "HL_FP32");
@@ -1571,6 +1574,39 @@ hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const vo
   if (!build_grids(plan, 64, 1, plan->gp.ygroup, &v64.gp, &v64.gu))
     return fail(HL_ERR_ARG, "hl_adjoint_step_var: grid too large");
   hipStream_t s = (hipStream_t)stream;
+  if (plan->walls) {
+    // The walled step is P' = P - A G U, U' = U - B P' (G the ghost refresh),
+    // so: Pb -= B^T Ub from the K dual nodes (dS/dc held on the padded dual
+    // array, whose ghost slots stay zero), then Ub -= G^T A^T Pb with A^T on
+    // every slot of the padded array and the ghost fold; A_kappa reads G U_t.
+    hl::Grid gf;
+    const int32_t tile[3] = {plan->gu.tx, plan->gu.ty, 1};
+    if (!make_grid(plan, tile, plan->gu.ygroup, plan->uext, plan->uext, 0, plan->pext, -1, plan->unodes,
+                   plan->pnodes, &gf))
+      return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: grid too large for the launch");
+    const size_t zb = (size_t)kappa_planes(plan) * plan->unodes * plan->tab_bytes;
+    const size_t ub = (size_t)plan->d * plan->nc * plan->unodes * plan->word_bytes;
+    hipError_t e = hipSuccess;
+    for (auto [q, bytes] : {std::pair<void**, size_t>{&plan->vzw, zb}, {&plan->ucw, ub}, {&plan->wscr, ub}}) {
+      if (*q) continue;
+      e = hipMalloc(q, bytes);
+      if (e == hipSuccess) e = hipMemset(*q, 0, bytes);
+      if (e != hipSuccess) {
+        if (*q) (void)hipFree(*q);
+        *q = nullptr;
+        return fail(HL_ERR_NOMEM, std::string("hl_adjoint_step_var: wall buffers: ") + hipGetErrorString(e));
+      }
+    }
+    e = plan->ks.ghost_zero(v, u_bar, s);
+    if (e == hipSuccess) e = plan->ks.grad_u_var(v64, u_bar, p_next, plan->gku, plan->vzw, s);
+    if (e == hipSuccess) e = plan->ks.gather_p_var(v, p_bar, plan->vzw, s);               // Pb -= B^T Ub
+    if (e == hipSuccess) e = hipMemcpyAsync(plan->ucw, u_prev, ub, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = plan->ks.ghost(v, plan->ucw, s);                             // G U_t
+    if (e == hipSuccess) e = plan->ks.grad_p_var(v64, p_bar, plan->ucw, plan->gkp, plan->vscr, s);
+    if (e == hipSuccess) e = plan->ks.gather_u_var_walls(v, gf, u_bar, plan->vscr, plan->wscr, s);  // Ub -= G^T A^T Pb
+    if (e != hipSuccess) return hip_fail(e, "hl_adjoint_step_var: launch");
+    return HL_OK;
+  }
   // velocity half-step of the step being undone: gku -= d<Ub, B P'>/dkappa, z = d/dc
   hipError_t e = plan->ks.grad_u_var(v64, u_bar, p_next, plan->gku, plan->vscr, s);
   if (e == hipSuccess) e = plan->ks.gather_p_var(v, p_bar, plan->vscr, s);            // Pb -= B^T Ub
@@ -1585,18 +1621,18 @@ hl_status hl_kappa_grad(hl_plan_t plan, double* grad_p, double* grad_u, int rese
   g_last_error.clear();
   hl_status st = check_plan(plan, "hl_kappa_grad");
   if (st != HL_OK) return st;
-  if (plan->walls) return fail(HL_ERR_UNSUPPORTED, "hl_kappa_grad: built for periodic plans only");
   if (!plan->ks.grad_p_var)
     return fail(HL_ERR_UNSUPPORTED, "hl_kappa_grad: built for d = 1 (all m) and d = 2 (m <= 3), HL_FP64 and HL_FP32");
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hl_kappa_grad: pending work failed");
   if ((st = ensure_var_gradient(plan)) != HL_OK) return st;
-  const LayoutMap L = hl_host::field_layout(plan->d, 2 * plan->m + 1, plan->K, false, 0);
   const int64_t np = kappa_planes(plan);
   double* dev[2] = {plan->gkp, plan->gku};
   double* host[2] = {grad_p, grad_u};
   const int64_t nodes[2] = {plan->pnodes, plan->unodes};
   for (int f = 0; f < 2; ++f) {
+    // hl_set_kappa's layout (with walls: K+1 primal nodes, dual nodes in the padded array)
+    const LayoutMap L = hl_host::field_layout(plan->d, 2 * plan->m + 1, plan->K, plan->walls, f);
     if (host[f]) {
       std::vector<double> img((size_t)(np * nodes[f]));
       e = hipMemcpy(img.data(), dev[f], img.size() * sizeof(double), hipMemcpyDeviceToHost);

@@ -64,6 +64,7 @@ struct KernelSet {
   GhostFn ghost;         // ghost-shell refresh of a wall-bounded velocity array
   AdjFn adj_p, adj_u;    // transposed half-steps, NULL where not built
   AdjWallFn adj_u_walls; // walls: ub -= G^T A^T pb, NULL where not built
+  AdjWallFn gather_u_var_walls;  // walls, variable kappa: ub -= G^T (A^T pb from rho), NULL where not built
   GhostZeroFn ghost_zero;
   PHalfFn p_half_var;    // variable-kappa half-steps, NULL where not built
   UHalfFn u_half_var;
@@ -225,7 +226,8 @@ VarArgs<typename S::C> var_args(const PlanView& pv) {
   VarArgs<typename S::C> va;
   va.w0 = (typename S::C)pv.dt;
   va.ratio[0] = 0;
-  for (int k = 1; k < 9; ++k) va.ratio[k] = (typename S::C)(0.25 * pv.dt * pv.dt / ((2.0 * k) * (2.0 * k + 1.0)));
+  for (int k = 1; k <= kVarMaxK; ++k)
+    va.ratio[k] = (typename S::C)(0.25 * pv.dt * pv.dt / ((2.0 * k) * (2.0 * k + 1.0)));
   for (int k = 0; k < 3; ++k) va.ih[k] = (typename S::C)pv.ih[k];
   return va;
 }
@@ -294,13 +296,32 @@ hipError_t launch_gather_u_var(const PlanView& pv, void* ub, const void* scr, hi
   return hipGetLastError();
 }
 
+// Walls, variable kappa: scr -= the transposed interpolation of rho on every
+// slot of the padded velocity array (gf: the padded extents, primal corners
+// inside [0, K]), then ub += G^T scr (scratch left zeroed).
+template <int D, int M, class S>
+hipError_t launch_gather_u_var_walls(const PlanView& pv, const Grid& gf, void* ub, const void* rho, void* scr,
+                                     hipStream_t s) {
+  constexpr int NC = Dims<D, M>::NC, NP = VK<D, M>::NP;
+  const typename S::View vs = S::make(scr, D, NC, gf.onodes);
+  hipLaunchKernelGGL((var_adjoint_gather_walls<D, M, S>), grid_shape(gf), block_shape(gf), 0, s, vs,
+                     S::make(rho, D, NP, gf.snodes), gf);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t interior = 1;
+  for (int k = 0; k < D; ++k) interior *= pv.uext[k] - 2;
+  hipLaunchKernelGGL((ghost_fold<D, M, S>), dim3((unsigned)((interior + 255) / 256)), dim3(256), 0, s,
+                     S::make(ub, D, NC, gf.onodes), vs, pv.uext[0], pv.uext[1], pv.uext[2]);
+  return hipGetLastError();
+}
+
 template <class S>
 constexpr bool kPlain = false;
 template <typename W>
 constexpr bool kPlain<PlainStore<W>> = true;
 
 template <int D, int M, class S>
-constexpr bool kVarBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 3) || (D == 3 && M <= 1));
+constexpr bool kVarBuilt = kPlain<S> && (D <= 2 || (D == 3 && M <= 1));
 template <int D, int M, class S>
 constexpr bool kVarGradBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 3));
 
@@ -409,20 +430,22 @@ inline bool make_set(KernelSet* out) {
   out->p_batch = &launch_batch<D, M, S, true>;
   out->u_batch = &launch_batch<D, M, S, false>;
   out->batch_src = SrcLauncher<S>::fn;
-  // variable kappa: FP64 and FP32 storage, d = 1 (all m), d = 2 (m <= 3), d = 3 (m <= 1)
+  // variable kappa: FP64 and FP32 storage, d = 1 and 2 (all m), d = 3 (m <= 1)
   if constexpr (kVarBuilt<D, M, S>) {
     out->p_half_var = &launch_p_var<D, M, S>;
     out->u_half_var = &launch_u_var<D, M, S>;
   }
-  // variable-kappa adjoint and kappa gradient: d = 1 (all m) and d = 2 (m <= 2)
+  // variable-kappa adjoint and kappa gradient: d = 1 (all m) and d = 2 (m <= 3)
   out->grad_p_var = nullptr;
   out->grad_u_var = nullptr;
   out->gather_p_var = nullptr;
   out->gather_u_var = nullptr;
+  out->gather_u_var_walls = nullptr;
   if constexpr (kVarGradBuilt<D, M, S>) {
     out->grad_p_var = &launch_grad_p_var<D, M, S>;
     out->grad_u_var = &launch_grad_u_var<D, M, S>;
     out->gather_p_var = &launch_gather_p_var<D, M, S>;
+    out->gather_u_var_walls = &launch_gather_u_var_walls<D, M, S>;
     out->gather_u_var = &launch_gather_u_var<D, M, S>;
   }
   return true;

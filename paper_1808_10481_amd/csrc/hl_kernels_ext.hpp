@@ -256,6 +256,10 @@ struct VK {
   static constexpr int KMAX = D * M;
 };
 
+// w_k / w_{k-1} for k = 1..kVarMaxK (kmax = d m <= 10 for every built (d, m):
+// 2D m = 5 reaches 10).
+constexpr int kVarMaxK = 10;
+
 // The series is accumulated as t_k = w_k r_k with t_k = (w_k / w_{k-1})
 // T[kappa Lap t_{k-1}]: the ratio (dt/2)^2 / (2k (2k+1)) cancels the 1/h^2 of
 // each Laplacian, so every term stays O(1) (r_k alone grows like h^{-2k} and
@@ -263,7 +267,7 @@ struct VK {
 template <typename T>
 struct VarArgs {
   T w0;        // w_0 = dt
-  T ratio[9];  // w_k / w_{k-1} = (dt/2)^2 / (2k (2k+1)), k = 1..kmax (kmax <= 8)
+  T ratio[kVarMaxK + 1];  // w_k / w_{k-1} = (dt/2)^2 / (2k (2k+1)), k = 1..kmax
   T ih[3];     // 1 / h_k
 };
 
@@ -340,6 +344,19 @@ __device__ __forceinline__ void tprod_grouped(const typename S::View& kv, uint32
 #pragma unroll
   for (int b = 0; b < NP; ++b) out[b] = T(0);
   kgroup_steps<D, M, TR, S>(kv, n0, f, out, std::make_integer_sequence<int, NG>{});
+}
+
+// The forward variable-kappa half-steps take the grouped kappa loads from
+// m = 4 on, where the per-term loads' addresses spill (2D m = 4 FP64: 788 ->
+// 124 bytes of scratch per lane, m = 5 FP32: 507 -> 359 VGPRs); below, the
+// per-term loads measured faster (2D m = 3 1024^2 FP32 0.86 against 0.91 ms).
+template <int D, int M, class S>
+__device__ __forceinline__ void tprod_fwd(const typename S::View& kv, uint32_t n0, const typename S::C* f,
+                                          typename S::C* out) {
+  if constexpr (M >= 4)
+    tprod_grouped<D, M, false, S>(kv, n0, f, out);
+  else
+    tprod<D, M, S>(kv, n0, f, out);
 }
 
 // Full interpolant c[b_x + N2 (b_y + N2 b_z)] of one component from its 2^D
@@ -508,6 +525,7 @@ __device__ __forceinline__ void p_half_var_body(typename S::View p, typename S::
                                                 Grid g, VarArgs<typename S::C> va, int blk) {
   using T = typename S::C;
   constexpr int N2 = 2 * M + 2, MP = M + 1, NP = VK<D, M>::NP, NC = Dims<D, M>::NC;
+  static_assert(VK<D, M>::KMAX <= kVarMaxK, "series longer than the ratio table");
   int32_t j[3];
   if (!node_of_block<D>(g, blk, j)) return;
   uint32_t cn[1 << D];
@@ -529,14 +547,14 @@ __device__ __forceinline__ void p_half_var_body(typename S::View p, typename S::
     }
   }
   T t[NP], acc[NC];
-  tprod<D, M, S>(kp, n0, div, t);  // t_0 = w_0 r_0
+  tprod_fwd<D, M, S>(kp, n0, div, t);  // t_0 = w_0 r_0
 #pragma unroll
   for (int s = 0; s < NC; ++s) acc[s] = t[poly_index<D, M>(s, 0, 0, 0)];
 #pragma unroll 1
   for (int k = 1; k <= VK<D, M>::KMAX; ++k) {
     T l[NP];
     lap_coef<D, M>(t, l, va.ih, va.ratio[k]);
-    tprod<D, M, S>(kp, n0, l, t);  // t_k = w_k r_k
+    tprod_fwd<D, M, S>(kp, n0, l, t);  // t_k = w_k r_k
 #pragma unroll
     for (int s = 0; s < NC; ++s) acc[s] += t[poly_index<D, M>(s, 0, 0, 0)];
   }
@@ -570,7 +588,7 @@ __device__ __forceinline__ void u_half_var_body(typename S::View u, typename S::
   for (int k = 1; k <= VK<D, M>::KMAX; ++k) {
     T l[NP];
     lap_coef<D, M>(gk, l, va.ih, va.ratio[k]);
-    tprod<D, M, S>(ku, n0, l, gk);
+    tprod_fwd<D, M, S>(ku, n0, l, gk);
 #pragma unroll
     for (int b = 0; b < NP; ++b) q[b] += gk[b];
   }
@@ -919,6 +937,13 @@ __device__ __forceinline__ void gather_corners(const typename S::View& scr, int 
   (gather_corner<D, M, S, EP>(scr, comp, cn[EP], acc), ...);
 }
 
+template <int D, int M, class S, int... EP>
+__device__ __forceinline__ void gather_corners_masked(const typename S::View& scr, int comp, const uint32_t* cn,
+                                                      const bool* valid, typename S::C* acc,
+                                                      std::integer_sequence<int, EP...>) {
+  ((valid[EP] ? gather_corner<D, M, S, EP>(scr, comp, cn[EP], acc) : void()), ...);
+}
+
 // Second stage of a transposed variable-kappa half-step: out -= the
 // transposed interpolation of the per-cell dS/dc held in scr over the
 // output node's stencil (the source node's cell has the output node as
@@ -943,6 +968,44 @@ __global__ void __launch_bounds__(256) var_adjoint_gather(typename S::View out, 
     gather_corners<D, M, S>(scr, io, cn, acc, std::make_integer_sequence<int, (1 << D)>{});
 #pragma unroll
     for (int a = 0; a < NC; ++a) S::update(out, io * NC + a, n0, [&](T x) { return x - acc[a]; });
+  }
+}
+
+// Walls, velocity side: scr[s] -= the transposed interpolation of rho over the
+// primal corners of padded dual slot s (0..K+1 per dimension, dual node
+// q = s - 1) that lie inside [0, K] (corners past a wall are not nodes of the
+// walled step and contribute nothing).  The fold G^T (ghost_fold) then adds
+// each ghost slot, with its mirror sign, into the node it mirrors.  The grid's
+// K are the padded extents, sext the primal extents.
+template <int D, int M, class S>
+__global__ void __launch_bounds__(256) var_adjoint_gather_walls(typename S::View scr, typename S::View rho, Grid g) {
+  using T = typename S::C;
+  constexpr int NC = Dims<D, M>::NC;
+  int32_t j[3];
+  if (!node_of_block<D>(g, blockIdx.x, j)) return;
+  uint32_t cn[1 << D];
+  bool valid[1 << D];
+#pragma unroll
+  for (int e = 0; e < (1 << D); ++e) {
+    int32_t c3[3] = {0, 0, 0};
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      c3[k] = j[k] - 1 + ((e >> k) & 1);
+      ok = ok && c3[k] >= 0 && c3[k] < g.sext[k];
+    }
+    valid[e] = ok;
+    cn[e] = ok ? node_index<D>(c3[0], c3[1], c3[2], g.sext) : 0u;
+  }
+  const uint32_t n0 = node_index<D>(j[0], j[1], j[2], g.oext);
+#pragma unroll 1
+  for (int io = 0; io < D; ++io) {
+    T acc[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) acc[a] = T(0);
+    gather_corners_masked<D, M, S>(rho, io, cn, valid, acc, std::make_integer_sequence<int, (1 << D)>{});
+#pragma unroll
+    for (int a = 0; a < NC; ++a) S::update(scr, io * NC + a, n0, [&](T x) { return x - acc[a]; });
   }
 }
 

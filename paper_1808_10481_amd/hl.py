@@ -278,8 +278,9 @@ class Plan:
     def kappa_grad(self, reset=False):
         """(grad_p, grad_u): the accumulated gradient with respect to the kappa
         data, FP64 arrays shaped like set_kappa's inputs (hl_kappa_grad)."""
-        shape = self.cells + (2 * self.m + 2,) * self.d
-        gp, gu = np.zeros(shape), np.zeros(shape)
+        n2 = (2 * self.m + 2,) * self.d
+        gp = np.zeros(self.host_shapes()[0][:self.d] + n2)    # primal nodes (K+1 per dimension with walls)
+        gu = np.zeros(self.cells + n2)
         _check(lib().hl_kappa_grad(self._h, gp.ctypes.data_as(ctypes.c_void_p), gu.ctypes.data_as(ctypes.c_void_p),
                                    1 if reset else 0))
         return gp, gu

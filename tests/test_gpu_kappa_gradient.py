@@ -220,3 +220,54 @@ def test_gradient_full_size_512_m2_central_differences():
     rec = [(int(x), 256) for x in np.linspace(16, 496, 16)]   # 16 receivers on a line
     data = np.zeros((nsteps, len(rec)))
     _fd_check(plan, kp, ku, p0, u0, nsteps, rec, data, 2, rng, 1e-3, 1e-6)
+
+
+WALL_VAR_CASES = [(1, 3, (10,)), (2, 1, (6, 5)), (2, 2, (4, 3)), (2, 3, (3, 3))]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("d,m,K", WALL_VAR_CASES)
+def test_walls_adjoint_step_var_matches_oracle(d, m, K, prec):
+    """Reflecting walls: the transposed variable-kappa step (B^T from the K
+    dual nodes, G^T A^T with the ghost fold, A_kappa on the ghost-refreshed
+    U_t) against the oracle's transpose read off unit responses of its walled
+    step, and sampled kappa-gradient entries against central differences of
+    that step."""
+    _say(f"[kgrad] walls one step d={d} m={m} K={K} {prec}")
+    rng = np.random.default_rng(1500 + 10 * d + m)
+    plan = hl.Plan(d, m, K, cfl=0.5, c=np.sqrt(2.0), precision=prec, boundary="walls")
+    prob = oracle.Problem(d, m, tuple(K), (1.0,) * d, plan.dt, 1.0, "walls")
+    N2 = 2 * m + 2
+    kap = []
+    for nodes in (prob.p_nodes(), prob.u_nodes()):
+        kd = rng.uniform(-0.2, 0.2, nodes + (N2,) * d)
+        kd[(Ellipsis,) + (0,) * d] += 1.5
+        kap.append(kd)
+    kp, ku = kap
+    plan.set_kappa(kp, ku)
+    ps, us = plan.host_shapes()
+    p, u = plan.alloc()
+    plan.init(p, u, inputs.zero_on_walls(rng.uniform(-1, 1, ps), d), rng.uniform(-1, 1, us))
+    P_in, U_in = plan.export(p, u)
+    p_next, u_prev = p.clone(), u.clone()
+    plan.p_half(p_next, u_prev)                       # P' = P_{t+1} (ghost refresh first)
+    pb, ub = plan.alloc()
+    plan.init(pb, ub, rng.uniform(-1, 1, ps), rng.uniform(-1, 1, us))
+    Pb_in, Ub_in = plan.export(pb, ub)
+    plan.kappa_grad(reset=True)
+    plan.adjoint_step_var(pb, ub, p_next, u_prev)
+    gp, gu = plan.kappa_grad(reset=True)
+    Pa, Ua = plan.export(pb, ub)
+    oPb, oUb = oracle.adjoint_step_var_bruteforce(prob, Pb_in, Ub_in, kp, ku, 1)
+    t = gtol(prec, d, m)
+    _close(Pa, oPb, *t)
+    _close(Ua, oUb, *t)
+    ent = [(0, int(i)) for i in rng.choice(kp.size, 8, replace=False)] + \
+          [(1, int(i)) for i in rng.choice(ku.size, 8, replace=False)]
+    # kappa_0 of the nodes next to a wall and of an interior node
+    ent += [(0, 0), (1, 0), (0, kp.size - N2 ** d), (1, ku.size - N2 ** d)]
+    fd = oracle.kappa_field_gradient_fd(prob, P_in, U_in, kp, ku, Pb_in, Ub_in, 1, ent)
+    got = np.array([(gp if f == 0 else gu).reshape(-1)[i] for f, i in ent])
+    scale = np.max(np.abs(fd))
+    rt = 1e-8 if prec == "fp64" else 16 * t[1]
+    assert np.max(np.abs(got - fd)) <= rt * scale, (got, fd)

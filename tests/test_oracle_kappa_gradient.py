@@ -11,6 +11,13 @@ cell updates):
 * directional derivatives of <Pb, P_n> + <Ub, U_n>, and of a misfit of the
   pressure at receiver nodes after every step, match fourth-order central
   differences of step_var along random kappa directions.
+
+The definitions used with reflecting walls (the transpose read off unit
+responses of step_var, the gradient by central differences per kappa entry)
+are pinned on the periodic grid against the structured adjoint and gradient
+above, and on the walled box by their reduction, for constant kappa data, to
+the constant-coefficient walled adjoint and scalar gradient (pinned by the
+dot-product identity and central differences of the walled step).
 """
 
 import numpy as np
@@ -146,3 +153,83 @@ def test_directional_derivatives_match_central_differences(d, m, K):
         fd = (-L(2 * eps) + 8 * L(eps) - 8 * L(-eps) + L(-2 * eps)) / (12 * eps)
         an = _dot(gp, dp) + _dot(gu, du)
         assert abs(fd - an) <= 1e-7 * max(1.0, abs(fd)), (trial, fd, an)
+
+
+def _walls_prob(d, m, K, kappa=1.0, nu=0.6):
+    pr = oracle.Problem(d, m, tuple(K), (1.0,) * d, 0.0, kappa, "walls")
+    return pr.with_dt(nu * min(pr.h) / np.sqrt(1.6))
+
+
+def _walls_kappa(rng, prob, amp=0.1):
+    N2 = 2 * prob.m + 2
+    out = []
+    for nodes in (prob.p_nodes(), prob.u_nodes()):
+        Kd = rng.uniform(-amp, amp, size=nodes + (N2,) * prob.d)
+        Kd[(Ellipsis,) + (0,) * prob.d] = rng.uniform(1.0, 1.4, size=nodes)
+        out.append(Kd)
+    return out
+
+
+@pytest.mark.parametrize("d,m,K", [(1, 2, (5,)), (2, 1, (3, 4))])
+def test_bruteforce_transpose_and_fd_gradient_match_the_structured_ones(d, m, K):
+    """Periodic grid: the transpose from unit responses equals the structured
+    adjoint, and the central-difference gradient entries equal the
+    complex-step ones."""
+    rng = np.random.default_rng(800 + 10 * d + m)
+    prob = _prob(d, m, K)
+    Kp, Ku = _kappa(rng, d, m, K), _kappa(rng, d, m, K)
+    P, U = inputs.random_data(rng, d, m, K), inputs.random_data(rng, d, m, K, ncomp=d)
+    Pb, Ub = inputs.random_data(rng, d, m, K), inputs.random_data(rng, d, m, K, ncomp=d)
+    n = 2
+    Pa, Ua = H.adjoint_step_var_bruteforce(prob, Pb, Ub, Kp, Ku, n)
+    Ps, Us = H.adjoint_step_var(prob, Pb, Ub, Kp, Ku, n)
+    assert np.max(np.abs(Pa - Ps)) <= 1e-12 * np.max(np.abs(Ps))
+    assert np.max(np.abs(Ua - Us)) <= 1e-12 * np.max(np.abs(Us))
+    gp, gu, _, _ = H.kappa_field_gradient(prob, P, U, Kp, Ku, Pb, Ub, n)
+    entries = [(0, int(i)) for i in rng.choice(Kp.size, 6, replace=False)] + \
+              [(1, int(i)) for i in rng.choice(Ku.size, 6, replace=False)]
+    fd = H.kappa_field_gradient_fd(prob, P, U, Kp, Ku, Pb, Ub, n, entries)
+    ref = np.array([(gp if f == 0 else gu).reshape(-1)[i] for f, i in entries])
+    assert np.max(np.abs(fd - ref)) <= 1e-8 * np.max(np.abs(ref)), (fd, ref)
+
+
+@pytest.mark.parametrize("d,m,K", [(1, 3, (5,)), (2, 1, (3, 4))])
+def test_walls_bruteforce_reduces_to_the_constant_coefficient_walled_adjoint(d, m, K):
+    rng = np.random.default_rng(900 + 10 * d + m)
+    kappa = 1.3
+    prob = _walls_prob(d, m, K, kappa)
+    Kp = np.zeros(prob.p_nodes() + (2 * m + 2,) * d)
+    Ku = np.zeros(prob.u_nodes() + (2 * m + 2,) * d)
+    z = (Ellipsis,) + (0,) * d
+    Kp[z], Ku[z] = kappa, kappa
+    P, U = rng.uniform(-1, 1, prob.p_shape()), rng.uniform(-1, 1, prob.u_shape())
+    Pb, Ub = rng.uniform(-1, 1, prob.p_shape()), rng.uniform(-1, 1, prob.u_shape())
+    n = 2
+    Pa, Ua = H.adjoint_step_var_bruteforce(prob, Pb, Ub, Kp, Ku, n)
+    Pc, Uc = H.adjoint_step(prob, Pb, Ub, n)
+    assert np.max(np.abs(Pa - Pc)) <= 1e-12 * np.max(np.abs(Pc))
+    assert np.max(np.abs(Ua - Uc)) <= 1e-12 * np.max(np.abs(Uc))
+    # the kappa_0 entries summed over every node of both grids: the scalar kappa derivative
+    ent = [(0, i) for i in range(0, Kp.size, (2 * m + 2) ** d)] + [(1, i) for i in range(0, Ku.size, (2 * m + 2) ** d)]
+    fd = H.kappa_field_gradient_fd(prob, P, U, Kp, Ku, Pb, Ub, n, ent)
+    g, _, _ = H.kappa_gradient(prob, P, U, Pb, Ub, n)
+    assert abs(np.sum(fd) - g) <= 1e-8 * max(1.0, abs(g)), (np.sum(fd), g)
+
+
+def test_walls_bruteforce_transpose_with_variable_kappa():
+    """Non-constant kappa data on the walled box: the transpose satisfies the
+    dot-product identity with the walled step_var, and a planted error (one
+    kappa entry changed in the transpose only) breaks it."""
+    rng = np.random.default_rng(950)
+    prob = _walls_prob(2, 2, (3, 2))
+    Kp, Ku = _walls_kappa(rng, prob)
+    P, U = rng.uniform(-1, 1, prob.p_shape()), rng.uniform(-1, 1, prob.u_shape())
+    Pb, Ub = rng.uniform(-1, 1, prob.p_shape()), rng.uniform(-1, 1, prob.u_shape())
+    P1, U1 = H.step_var(prob, P, U, Kp, Ku, 2)
+    Pa, Ua = H.adjoint_step_var_bruteforce(prob, Pb, Ub, Kp, Ku, 2)
+    lhs, rhs = _dot(P1, Pb) + _dot(U1, Ub), _dot(P, Pa) + _dot(U, Ua)
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1.0)
+    Kbad = np.array(Kp)
+    Kbad.reshape(-1)[0] += 0.05  # kappa_0 at the corner node
+    Pw, Uw = H.adjoint_step_var_bruteforce(prob, Pb, Ub, Kbad, Ku, 2)
+    assert abs(lhs - (_dot(P, Pw) + _dot(U, Uw))) > 1e-6 * (abs(lhs) + 1.0)
