@@ -51,6 +51,19 @@
 #define HL_SCHED_MASK 0
 #endif
 // Minimum waves per SIMD requested from the register allocator (0 = none).
+// 3D m <= 2 half-steps: load the next datum's 8 corners before the current
+// datum's arithmetic (HL_PREFETCH3: 0 never, 1 for FP64 storage, 2 always).
+// With FP64 words the half-steps wait on memory at 3-5 resident waves per
+// SIMD, and a second datum in flight per wave pays (256^3 u half-step 7.57 ->
+// 7.05 ms, p half-step 7.70 -> 7.61); FP32 (VALU-bound p half-step 2.97 ->
+// 3.14 ms) and the split FP32+BF16 storage (16 loads per datum: u half-step
+// 7.01 -> 15.3 ms) run slower with it.
+#ifndef HL_PREFETCH3
+#define HL_PREFETCH3 1
+#endif
+template <class S>
+constexpr bool kPrefetch3 = HL_PREFETCH3 == 2 || (HL_PREFETCH3 == 1 && S::kBytes == 8);
+
 #ifndef HL_WAVES_PER_EU
 #define HL_WAVES_PER_EU 0
 #endif
@@ -438,16 +451,34 @@ __device__ __forceinline__ void p_half_3d_full_body(typename S::View p, typename
   T acc[NC];
 #pragma unroll
   for (int s = 0; s < NC; ++s) acc[s] = T(0);
+  T vn[8];  // the next datum's corners, loaded one datum ahead
+  if constexpr (kPrefetch3<S>) {
+    const typename S::Planes pr = S::planes(u, 0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) vn[e] = S::bload(pr, cn[e]);
+  }
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       // keep the scalar table loads of one datum together (SGPR pressure)
       __builtin_amdgcn_sched_barrier(0);
-      const typename S::Planes pr = S::planes(u, i * NC + a);
       T v[8];
+      if constexpr (kPrefetch3<S>) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = S::bload(pr, cn[e]);
+        for (int e = 0; e < 8; ++e) v[e] = vn[e];
+        if (i * NC + a + 1 < 3 * NC) {
+          int zero;  // opaque: the plane base is formed here, not hoisted to the kernel start
+          asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
+          const typename S::Planes pn = S::planes(u, i * NC + a + 1 + zero);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) vn[e] = S::bload(pn, cn[e]);
+        }
+      } else {
+        const typename S::Planes pr = S::planes(u, i * NC + a);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = S::bload(pr, cn[e]);
+      }
       T X[8];  // [k_x + 2 k_y + 4 k_z]
 #pragma unroll
       for (int q = 0; q < 4; ++q) {  // x: corners (2q, 2q+1)
@@ -543,14 +574,32 @@ __device__ __forceinline__ void u3_full_Q(const typename S::View& p, const uint3
   constexpr int MP = M + 1, NC = Dims<3, M>::NC, NG = GSet<3, M>::NG;
 #pragma unroll
   for (int o = 0; o < NG; ++o) Q[o] = T(0);
+  T vn[8];  // the next datum's corners, loaded one datum ahead
+  if constexpr (kPrefetch3<S>) {
+    const typename S::Planes pr = S::planes(p, 0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) vn[e] = S::bload(pr, cn[e]);
+  }
 #pragma unroll
   for (int a = 0; a < NC; ++a) {
     // keep the scalar table loads of one datum together (SGPR pressure)
     __builtin_amdgcn_sched_barrier(0);
-    const typename S::Planes pr = S::planes(p, a);
     T v[8];
+    if constexpr (kPrefetch3<S>) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = S::bload(pr, cn[e]);
+      for (int e = 0; e < 8; ++e) v[e] = vn[e];
+      if (a + 1 < NC) {
+        int zero;  // opaque: the plane base is formed here, not hoisted to the kernel start
+        asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
+        const typename S::Planes pn = S::planes(p, a + 1 + zero);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) vn[e] = S::bload(pn, cn[e]);
+      }
+    } else {
+      const typename S::Planes pr = S::planes(p, a);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = S::bload(pr, cn[e]);
+    }
     T X[8];  // [k_x + 2 k_y + 4 k_z]
 #pragma unroll
     for (int q = 0; q < 4; ++q) {  // x: corners (2q, 2q+1)
