@@ -6,8 +6,8 @@ The n-step map (P, U) -> (P_n, U_n) is linear in the state, so its
 vector-Jacobian product with respect to the state is the discrete adjoint
 applied to the incoming gradients.  The derivative with respect to kappa = c^2
 (dt held fixed) comes from the same call, which walks the forward state back
-with the reversed step.  Tensors are the plan's device state buffers (periodic
-plans, FP64 or FP32).
+with the reversed step.  Tensors are the plan's device state buffers (FP64 or
+FP32; periodic or walled plans).
 """
 
 from __future__ import annotations
@@ -62,17 +62,18 @@ def hermite_steps(p, u, plan, nsteps, kappa=None):
 
 def receiver_index(plan, receivers):
     """Device word index of coefficient 0 of the pressure at each receiver
-    (host node tuples (j_1, .., j_d)): the p layout stores plane 0 first,
-    nodes with j_1 fastest (periodic plans: the variable-kappa adjoint is
-    built for them only)."""
-    if plan.boundary != "periodic":
-        raise ValueError("receiver traces are differentiated on periodic plans only")
+    (host node tuples (j_1, .., j_d) of the primal nodes: K per dimension, or
+    K+1 with walls): the p layout stores plane 0 first, nodes with j_1
+    fastest."""
+    ext = plan.host_shapes()[0][:plan.d]
     idx = []
     for r in receivers:
         n, stride = 0, 1
         for k, j in enumerate(r):
+            if not 0 <= int(j) < ext[k]:
+                raise ValueError(f"receiver {r} outside the primal nodes {ext}")
             n += int(j) * stride
-            stride *= plan.cells[k]
+            stride *= ext[k]
         idx.append(n)
     return torch.tensor(idx, dtype=torch.int64, device="cuda")
 

@@ -271,3 +271,23 @@ def test_walls_adjoint_step_var_matches_oracle(d, m, K, prec):
     scale = np.max(np.abs(fd))
     rt = 1e-8 if prec == "fp64" else 16 * t[1]
     assert np.max(np.abs(got - fd)) <= rt * scale, (got, fd)
+
+
+def test_walls_receiver_gradient_matches_central_differences():
+    """Reflecting walls, 2D m = 2 FP64: the checkpointed receiver-trace
+    gradient (walled transposed steps) against central differences of the
+    GPU's walled forward on 4 random kappa directions."""
+    _say("[kgrad] FD, 4 directions, walls 2D m=2 (16, 12) FP64")
+    d, m, K = 2, 2, (16, 12)
+    rng = np.random.default_rng(1600)
+    plan = hl.Plan(d, m, K, cfl=0.5, c=np.sqrt(2.0), precision="fp64", boundary="walls")
+    amps = tuple(rng.uniform(0.1, 0.3, d))
+    kp = inputs.kappa_box(d, m, K, (1.0,) * d, amps, "primal")
+    ku = inputs.kappa_box(d, m, K, (1.0,) * d, amps, "dual")
+    p0, u0 = plan.alloc()
+    ps, us = plan.host_shapes()
+    plan.init(p0, u0, inputs.zero_on_walls(rng.uniform(-1, 1, ps) * 0.1, d), np.zeros(us))
+    nsteps = 10
+    rec = [tuple(int(rng.integers(1, k)) for k in K) for _ in range(4)]
+    data = rng.normal(size=(nsteps, len(rec))) * 0.01
+    _fd_check(plan, kp, ku, p0, u0, nsteps, rec, data, 4, rng, 1e-3, 1e-7)
