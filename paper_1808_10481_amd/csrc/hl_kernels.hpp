@@ -50,8 +50,7 @@
 #ifndef HL_SCHED_MASK
 #define HL_SCHED_MASK 0
 #endif
-// Minimum waves per SIMD requested from the register allocator (0 = none).
-// 3D m <= 2 half-steps: load the next datum's 8 corners before the current
+// 3D half-steps (fully merged tables): load the next datum's 8 corners before the current
 // datum's arithmetic (HL_PREFETCH3: 0 never, 1 for FP64 storage, 2 always).
 // With FP64 words the half-steps wait on memory at 3-5 resident waves per
 // SIMD, and a second datum in flight per wave pays (256^3 u half-step 7.57 ->
@@ -64,11 +63,12 @@
 template <class S>
 constexpr bool kPrefetch3 = HL_PREFETCH3 == 2 || (HL_PREFETCH3 == 1 && S::kBytes == 8);
 
+// Minimum waves per SIMD requested from the register allocator (0 = none).
 #ifndef HL_WAVES_PER_EU
 #define HL_WAVES_PER_EU 0
 #endif
-// 3D velocity half-step for m <= 2 through the fully merged table (1) or the
-// explicit x pass plus the (y, z) merged table (0).
+// 3D velocity half-step through the fully merged table (1) or the explicit x
+// pass plus the (y, z) merged table (0).
 #ifndef HL_U3_FULL
 #define HL_U3_FULL 1
 #endif
@@ -430,7 +430,7 @@ __device__ __forceinline__ void merge3(TP Mt, int ay, int az, const T (&X)[2][2]
   }
 }
 
-// Pressure half-step, 3D, m <= 2: the x interpolation is merged into the
+// Pressure half-step, 3D: the x interpolation is merged into the
 // table as well.  Per component i and datum a the 8 corners are combined into
 // sigma/delta in x, y and z (X[k], k = k_x + 2 k_y + 4 k_z, 0 = sigma); output
 // o takes the combination whose parity in each dimension is that of
@@ -559,7 +559,7 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) p_half_3d(typename S::Vi
     p_half_3d_body<M, S, const typename S::C* __restrict__>(p, u, tab, g, blockIdx.x);
 }
 
-// Velocity half-step, 3D, m <= 2: the x interpolation merged into the table
+// Velocity half-step, 3D: the x interpolation merged into the table
 // as well (as for the pressure half-step).  Per datum a of the primal corners
 // the 8 corner values are combined into the sigma/delta products X[k] (x, y
 // and z, k = k_x + 2 k_y + 4 k_z); member o of G takes the product whose

@@ -358,10 +358,22 @@ struct TableLayout {
   static constexpr int p_off(int i) { return (D > 1 && i == 0) ? P_A_OFF : P_B_OFF; }
 };
 
-// 3D: one pressure table per component (derivative dimension), then Q; for
-// m <= 2 then the fully merged pressure table (x merged too):
-// F[i][a][o], component i, datum a, output o, (m+1)^3 x (m+1)^3 per component,
-// and the fully merged velocity table Fu[a][o] over the members o of G.
+// 3D: one pressure table per component (derivative dimension), then Q (the
+// (y, z) merged tables of the explicit x-pass path); then the fully merged
+// pressure table (x merged too): F[i][a][o], component i, datum a, output o,
+// (m+1)^3 x (m+1)^3 per component, and the fully merged velocity table
+// Fu[a][o] over the members o of G.  The kernels use the fully merged tables
+// (one FMA per entry after the corner butterfly) for every m;
+// HL_FULLP_MAXM / HL_FULLU_MAXM below 3 select the explicit x pass plus the
+// (y, z) tables for the larger m instead (at m = 3 that path needs 512 VGPRs
+// and spills 1.8-2.6 KB per lane).
+#ifndef HL_FULLP_MAXM
+#define HL_FULLP_MAXM 3
+#endif
+#ifndef HL_FULLU_MAXM
+#define HL_FULLU_MAXM 3
+#endif
+
 template <int M>
 struct TableLayout<3, M> {
   static constexpr int PG = merge3_size<M, false>();
@@ -369,11 +381,11 @@ struct TableLayout<3, M> {
   static constexpr int P_A_OFF = 0;
   static constexpr int P_B_OFF = 2 * PG;
   static constexpr int U_OFF = 3 * PG;
-  static constexpr bool FULL_P = M <= 2;
+  static constexpr bool FULL_P = M <= HL_FULLP_MAXM;
   static constexpr int NC = (M + 1) * (M + 1) * (M + 1);
   static constexpr int F_OFF = U_OFF + merge3_size<M, true>();
-  // m <= 2: the fully merged velocity table Fu[a][o], datum a, member o of G
-  static constexpr bool FULL_U = M <= 2;
+  // the fully merged velocity table Fu[a][o], datum a, member o of G
+  static constexpr bool FULL_U = M <= HL_FULLU_MAXM;
   static constexpr int FU_OFF = F_OFF + (FULL_P ? 3 * NC * NC : 0);
   static constexpr int TOTAL = FU_OFF + (FULL_U ? NC * GSet<3, M>::NG : 0);
 };
