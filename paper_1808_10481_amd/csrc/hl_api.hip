@@ -1297,8 +1297,7 @@ hl_status hl_set_kappa(hl_plan_t plan, const double* kappa_p, const double* kapp
     return HL_OK;
   }
   if (!plan->ks.p_half_var)
-    return fail(HL_ERR_UNSUPPORTED, "hl_set_kappa: variable kappa is built for d = 1, d = 2 and d = 3 "
-                                    "with m <= 1, in HL_FP64 or HL_FP32");
+    return fail(HL_ERR_UNSUPPORTED, "hl_set_kappa: variable kappa is built in HL_FP64 and HL_FP32");
   // host layout [nodes][b_1..b_d], b_k in 0..2m+1: the field layout of order
   // 2m+1 of p (primal nodes, K+1 per dimension with walls) and of one velocity
   // component (dual nodes; with walls stored in the padded array, whose ghost
@@ -1792,8 +1791,9 @@ hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_
     if (batch->plans[i]->var_kappa != var)
       return fail(HL_ERR_ARG, "hl_batch_step: variable kappa must be set on every plan of the batch or on none");
   }
-  if (var && !batch->ks.p_half_var)
-    return fail(HL_ERR_UNSUPPORTED, "hl_batch_step: variable kappa is not built for this (d, m, precision)");
+  if (var && !batch->ks.batch_var)
+    return fail(HL_ERR_UNSUPPORTED, "hl_batch_step: batched variable kappa is built for d = 1, d = 2 and d = 3 "
+                                    "with m <= 1, in HL_FP64 or HL_FP32");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipSuccess;
   bool same = var == batch->var && batch->bp.size() == (size_t)n && batch->gens.size() == (size_t)n &&

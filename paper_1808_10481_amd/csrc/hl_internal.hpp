@@ -68,6 +68,7 @@ struct KernelSet {
   GhostZeroFn ghost_zero;
   PHalfFn p_half_var;    // variable-kappa half-steps, NULL where not built
   UHalfFn u_half_var;
+  bool batch_var;        // variable kappa in batched steps
   VarGradFn grad_p_var, grad_u_var;      // variable-kappa adjoint, NULL where not built
   VarGatherFn gather_p_var, gather_u_var;
   BatchDescFn batch_desc;
@@ -252,6 +253,32 @@ hipError_t launch_u_var(const PlanView& pv, void* u, const void* p, double wscal
   return hipGetLastError();
 }
 
+// 3D m >= 2: one workgroup (one wavefront) per node, nodes in XCD-contiguous runs.
+template <int M, class S>
+hipError_t launch_p_var_wave(const PlanView& pv, void* p, const void* u, hipStream_t s) {
+  constexpr int NC = Dims<3, M>::NC, NP = VK<3, M>::NP;
+  const Grid& g = pv.gp;
+  const int64_t per = ((int64_t)g.K[0] * g.K[1] * g.K[2] + kXcds - 1) / kXcds;
+  if (per * kXcds > INT32_MAX) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((p_half_var_wave<M, S>), dim3((unsigned)(per * kXcds)), dim3(64), 0, s,
+                     S::make(p, 1, NC, g.onodes), S::make(u, 3, NC, g.snodes), S::make(pv.kap_p, 1, NP, g.onodes), g,
+                     var_args<S>(pv), (int32_t)per);
+  return hipGetLastError();
+}
+
+template <int M, class S>
+hipError_t launch_u_var_wave(const PlanView& pv, void* u, const void* p, double wscale, hipStream_t s) {
+  using T = typename S::C;
+  constexpr int NC = Dims<3, M>::NC, NP = VK<3, M>::NP;
+  const Grid& g = pv.gu;
+  const int64_t per = ((int64_t)g.K[0] * g.K[1] * g.K[2] + kXcds - 1) / kXcds;
+  if (per * kXcds > INT32_MAX) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((u_half_var_wave<M, S>), dim3((unsigned)(per * kXcds)), dim3(64), 0, s,
+                     S::make(u, 3, NC, g.onodes), S::make(p, 1, NC, g.snodes), S::make(pv.kap_u, 1, NP, g.onodes), g,
+                     var_args<S>(pv), (T)wscale, (int32_t)per);
+  return hipGetLastError();
+}
+
 template <int D, int M, class S>
 hipError_t launch_grad_p_var(const PlanView& pv, const void* pb, const void* u, double* gk, void* scr,
                              hipStream_t s) {
@@ -322,6 +349,8 @@ constexpr bool kPlain<PlainStore<W>> = true;
 
 template <int D, int M, class S>
 constexpr bool kVarBuilt = kPlain<S> && (D <= 2 || (D == 3 && M <= 1));
+template <int D, int M, class S>
+constexpr bool kVarWaveBuilt = kPlain<S> && D == 3 && M >= 2 && M <= 3;
 template <int D, int M, class S>
 constexpr bool kVarGradBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 3));
 
@@ -430,10 +459,16 @@ inline bool make_set(KernelSet* out) {
   out->p_batch = &launch_batch<D, M, S, true>;
   out->u_batch = &launch_batch<D, M, S, false>;
   out->batch_src = SrcLauncher<S>::fn;
-  // variable kappa: FP64 and FP32 storage, d = 1 and 2 (all m), d = 3 (m <= 1)
+  // variable kappa: FP64 and FP32 storage, every (d, m); batched for d <= 2
+  // and d = 3, m <= 1
+  out->batch_var = false;
   if constexpr (kVarBuilt<D, M, S>) {
     out->p_half_var = &launch_p_var<D, M, S>;
     out->u_half_var = &launch_u_var<D, M, S>;
+    out->batch_var = true;
+  } else if constexpr (kVarWaveBuilt<D, M, S>) {
+    out->p_half_var = &launch_p_var_wave<M, S>;
+    out->u_half_var = &launch_u_var_wave<M, S>;
   }
   // variable-kappa adjoint and kappa gradient: d = 1 (all m) and d = 2 (m <= 3)
   out->grad_p_var = nullptr;

@@ -246,8 +246,9 @@ __global__ void __launch_bounds__(256) ghost_zero(typename S::View u, int32_t E0
 //   P <- P - sum_k w_k r_k,   r_0 = T[kappa div c],  r_k = T[kappa Lap r_{k-1}]
 //   U_i <- U_i - sum_k w_k D_i g_k,   g_0 = c,  g_k = T[kappa Lap g_{k-1}].
 // No operator can be merged into a constant table here (kappa differs per
-// cell), so the kernels build the full (2m+2)^d interpolant in registers;
-// built for d = 1 (all m) and d = 2 (m <= 3).
+// cell), so the kernels build the full (2m+2)^d interpolant in registers, one
+// work-item per node (d = 1, d = 2, and d = 3 with m <= 1); 3D m >= 2 uses
+// one wavefront per node (below).
 // ---------------------------------------------------------------------------
 template <int D, int M>
 struct VK {
@@ -610,6 +611,290 @@ template <int D, int M, class S>
 __global__ void __launch_bounds__(256) u_half_var(typename S::View u, typename S::View p, typename S::View ku,
                                                   Grid g, VarArgs<typename S::C> va, typename S::C wscale) {
   u_half_var_body<D, M, S>(u, p, ku, g, va, wscale, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Variable kappa, 3D m = 2 and 3: one wavefront per node.  The cell
+// polynomial has (2m+2)^3 coefficients per field (216 at m = 2, 512 at
+// m = 3): two of them (the current term and its Laplacian) no longer fit in
+// one work-item's registers, so the 64 work-items of a workgroup share one
+// node.  Its polynomials live in LDS, and in the products and Laplacians
+// lane l < (2m+2)^2 owns the x-pencil b_y = l mod (2m+2), b_z = l div (2m+2)
+// (2m+2 coefficients along x, held in registers).  The arithmetic is that of
+// the per-node kernels above: the same tensor-product passes, and every
+// output of T[kappa f] sums kappa_a f_{b-a} over a in the same increasing
+// order.
+// ---------------------------------------------------------------------------
+template <int M>
+struct VW {
+  static constexpr int MP = M + 1, N2 = 2 * M + 2, NP = N2 * N2 * N2, NPEN = N2 * N2, NC = MP * MP * MP;
+  static_assert(NPEN <= 64 && 8 * NC == NP && 4 * MP * MP == NPEN, "one pencil and one line per lane");
+};
+
+// Node of workgroup blk when every workgroup updates one node: consecutive
+// node numbers (x fastest) go to one XCD, so neighbours share its L2.
+__device__ __forceinline__ bool wave_node(const Grid& g, int blk, int32_t per_xcd, int32_t* j) {
+  const int64_t t = (int64_t)(blk % kXcds) * per_xcd + blk / kXcds;
+  if (t >= (int64_t)g.K[0] * g.K[1] * g.K[2]) return false;
+  j[0] = (int32_t)(t % g.K[0]);
+  j[1] = (int32_t)((t / g.K[0]) % g.K[1]);
+  j[2] = (int32_t)(t / ((int64_t)g.K[0] * g.K[1]));
+  return true;
+}
+
+// Corner e of the node's cell (bit k of e: upper side in dimension k), wrapped
+// as corner_nodes wraps it.
+__device__ __forceinline__ uint32_t corner_node_of(const Grid& g, const int32_t* j, int e) {
+  int32_t c[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int32_t lo = j[k] + g.soff, hi = lo + 1;
+    if (lo < 0) lo += g.sext[k];
+    if (hi == g.sext[k]) hi = 0;
+    c[k] = ((e >> k) & 1) ? hi : lo;
+  }
+  return node_index<3>(c[0], c[1], c[2], g.sext);
+}
+
+// Full interpolant of component comp into B[b_x + N2 (b_y + N2 b_z)], through
+// A: the raw corner data A[e + 8 a], the x pass into B (line ey + 2 ez + 4
+// (ay + MP az), entries b_x), the y pass into A (line ez + 2 (az + MP b_x),
+// entries b_y), the z pass into B.  Every line is one lane's.
+template <int M, class S>
+__device__ __forceinline__ void interp_wave(const typename S::View& f, int comp, uint32_t cnl, int lane,
+                                            typename S::C* A, typename S::C* B) {
+  using T = typename S::C;
+  constexpr int MP = VW<M>::MP, N2 = VW<M>::N2, NC = VW<M>::NC, NL = VW<M>::NPEN;
+  for (int a = lane >> 3; a < NC; a += 8) A[(lane & 7) + 8 * a] = S::load(f, comp * NC + a, cnl);
+  __syncthreads();
+  if (lane < NL) {
+    const int ey = lane & 1, ez = (lane >> 1) & 1, ay = (lane >> 2) % MP, az = (lane >> 2) / MP;
+    T L[MP], R[MP], o[N2];
+#pragma unroll
+    for (int ax = 0; ax < MP; ++ax) {
+      const int a = ax + MP * (ay + MP * az);
+      L[ax] = A[2 * ey + 4 * ez + 8 * a];
+      R[ax] = A[1 + 2 * ey + 4 * ez + 8 * a];
+    }
+    pass1d<M, 0>(L, R, o);
+#pragma unroll
+    for (int b = 0; b < N2; ++b) B[lane * N2 + b] = o[b];
+  }
+  __syncthreads();
+  if (lane < NL) {
+    const int ez = lane & 1, az = (lane >> 1) % MP, bx = (lane >> 1) / MP;
+    T L[MP], R[MP], o[N2];
+#pragma unroll
+    for (int ay = 0; ay < MP; ++ay) {
+      L[ay] = B[(2 * ez + 4 * (ay + MP * az)) * N2 + bx];
+      R[ay] = B[(1 + 2 * ez + 4 * (ay + MP * az)) * N2 + bx];
+    }
+    pass1d<M, 0>(L, R, o);
+#pragma unroll
+    for (int b = 0; b < N2; ++b) A[lane * N2 + b] = o[b];
+  }
+  __syncthreads();
+  if (lane < NL) {
+    const int bx = lane % N2, by = lane / N2;
+    T L[MP], R[MP], o[N2];
+#pragma unroll
+    for (int az = 0; az < MP; ++az) {
+      L[az] = A[(2 * (az + MP * bx)) * N2 + by];
+      R[az] = A[(1 + 2 * (az + MP * bx)) * N2 + by];
+    }
+    pass1d<M, 0>(L, R, o);
+#pragma unroll
+    for (int b = 0; b < N2; ++b) B[bx + N2 * (by + N2 * b)] = o[b];
+  }
+  __syncthreads();
+}
+
+// Pencil (by, bz) of T[kappa f]: out[b_x] = sum over a <= b of kappa_a
+// f_{b-a}, K and F in LDS.
+template <int M, typename T>
+__device__ __forceinline__ void tprod_pencil(const T* KA, const T* F, int by, int bz, T* out) {
+  constexpr int N2 = VW<M>::N2;
+#pragma unroll
+  for (int b = 0; b < N2; ++b) out[b] = T(0);
+  for (int az = 0; az <= bz; ++az)
+    for (int ay = 0; ay <= by; ++ay) {
+      T kp[N2], fp[N2];
+      const T* kr = KA + N2 * (ay + N2 * az);
+      const T* fr = F + N2 * ((by - ay) + N2 * (bz - az));
+#pragma unroll
+      for (int b = 0; b < N2; ++b) {
+        kp[b] = kr[b];
+        fp[b] = fr[b];
+      }
+#pragma unroll
+      for (int bx = 0; bx < N2; ++bx)
+#pragma unroll
+        for (int ax = 0; ax <= bx; ++ax) out[bx] = fma(kp[ax], fp[bx - ax], out[bx]);
+    }
+}
+
+// Pencil (by, bz) of sc Lap t (coefficient space), t in LDS.
+template <int M, typename T>
+__device__ __forceinline__ void lap_pencil(const T* t, int by, int bz, const T* ih, T sc, T* out) {
+  constexpr int N2 = VW<M>::N2;
+  const T ix2 = sc * ih[0] * ih[0], iy2 = sc * ih[1] * ih[1], iz2 = sc * ih[2] * ih[2];
+  const T* r0 = t + N2 * (by + N2 * bz);
+#pragma unroll
+  for (int bx = 0; bx < N2; ++bx) {
+    T v = T(0);
+    if (bx + 2 < N2) v = fma(T((bx + 1) * (bx + 2)) * ix2, r0[bx + 2], v);
+    if (by + 2 < N2) v = fma(T((by + 1) * (by + 2)) * iy2, r0[bx + 2 * N2], v);
+    if (bz + 2 < N2) v = fma(T((bz + 1) * (bz + 2)) * iz2, r0[bx + 2 * N2 * N2], v);
+    out[bx] = v;
+  }
+}
+
+template <int M, class S>
+__global__ void __launch_bounds__(64) p_half_var_wave(typename S::View p, typename S::View u, typename S::View kp,
+                                                      Grid g, VarArgs<typename S::C> va, int32_t per_xcd) {
+  using T = typename S::C;
+  constexpr int MP = VW<M>::MP, N2 = VW<M>::N2, NP = VW<M>::NP, NL = VW<M>::NPEN;
+  static_assert(VK<3, M>::KMAX <= kVarMaxK, "series longer than the ratio table");
+  __shared__ T A[NP], B[NP], KA[NP];
+  int32_t j[3];
+  if (!wave_node(g, blockIdx.x, per_xcd, j)) return;  // uniform over the workgroup
+  const int lane = threadIdx.x;
+  const uint32_t n0 = out_index<3>(g, j);
+  const uint32_t cnl = corner_node_of(g, j, lane & 7);  // dual q = j - 1 + e
+  for (int a = lane; a < NP; a += 64) KA[a] = S::load(kp, a, n0);
+  const bool pen = lane < NL;
+  const int by = pen ? lane % N2 : 0, bz = pen ? lane / N2 : 0;
+  T dv[N2];  // w_0 div c on the lane's pencil
+#pragma unroll
+  for (int b = 0; b < N2; ++b) dv[b] = T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    interp_wave<M, S>(u, i, cnl, lane, A, B);
+    if (pen) {
+      const T f = va.w0 * va.ih[i];
+      const T* r = B + N2 * (by + N2 * bz);
+#pragma unroll
+      for (int bx = 0; bx < N2; ++bx) {
+        if (i == 0 && bx + 1 < N2) dv[bx] = fma(T(bx + 1) * f, r[bx + 1], dv[bx]);
+        if (i == 1 && by + 1 < N2) dv[bx] = fma(T(by + 1) * f, r[bx + N2], dv[bx]);
+        if (i == 2 && bz + 1 < N2) dv[bx] = fma(T(bz + 1) * f, r[bx + N2 * N2], dv[bx]);
+      }
+    }
+    __syncthreads();
+  }
+  T* F = A;  // Laplacian of the current term (input of the product)
+  T* Tc = B;  // current term t_k
+  if (pen) {
+#pragma unroll
+    for (int b = 0; b < N2; ++b) F[N2 * (by + N2 * bz) + b] = dv[b];
+  }
+  __syncthreads();
+  const bool own = pen && by < MP && bz < MP;  // pencil holds data entries (b_x < MP)
+  T acc[MP], t[N2];
+#pragma unroll
+  for (int b = 0; b < N2; ++b) t[b] = T(0);
+  if (pen) tprod_pencil<M>(KA, F, by, bz, t);  // t_0 = w_0 r_0
+#pragma unroll
+  for (int b = 0; b < MP; ++b) acc[b] = t[b];
+#pragma unroll 1
+  for (int k = 1; k <= VK<3, M>::KMAX; ++k) {
+    if (pen) {
+#pragma unroll
+      for (int b = 0; b < N2; ++b) Tc[N2 * (by + N2 * bz) + b] = t[b];
+    }
+    __syncthreads();
+    if (pen) {
+      T l[N2];
+      lap_pencil<M>(Tc, by, bz, va.ih, va.ratio[k], l);
+#pragma unroll
+      for (int b = 0; b < N2; ++b) F[N2 * (by + N2 * bz) + b] = l[b];
+    }
+    __syncthreads();
+    if (pen) tprod_pencil<M>(KA, F, by, bz, t);  // t_k = w_k r_k
+#pragma unroll
+    for (int b = 0; b < MP; ++b) acc[b] += t[b];
+  }
+  if (own) {
+#pragma unroll
+    for (int bx = 0; bx < MP; ++bx)
+      S::update(p, bx + MP * (by + MP * bz), n0, [&](T x) { return x - acc[bx]; });
+  }
+}
+
+template <int M, class S>
+__global__ void __launch_bounds__(64) u_half_var_wave(typename S::View u, typename S::View p, typename S::View ku,
+                                                      Grid g, VarArgs<typename S::C> va, typename S::C wscale,
+                                                      int32_t per_xcd) {
+  using T = typename S::C;
+  constexpr int MP = VW<M>::MP, N2 = VW<M>::N2, NP = VW<M>::NP, NL = VW<M>::NPEN, NC = VW<M>::NC;
+  __shared__ T A[NP], B[NP], KA[NP];
+  int32_t j[3];
+  if (!wave_node(g, blockIdx.x, per_xcd, j)) return;  // uniform over the workgroup
+  const int lane = threadIdx.x;
+  const uint32_t n0 = out_index<3>(g, j);
+  const uint32_t cnl = corner_node_of(g, j, lane & 7);  // primal j = q + e
+  for (int a = lane; a < NP; a += 64) KA[a] = S::load(ku, a, n0);
+  const bool pen = lane < NL;
+  const int by = pen ? lane % N2 : 0, bz = pen ? lane / N2 : 0;
+  interp_wave<M, S>(p, 0, cnl, lane, A, B);
+  T* F = A;  // Laplacian of the current term (input of the product)
+  T* Tc = B;  // current term g_k
+  T gk[N2], q[N2];
+#pragma unroll
+  for (int b = 0; b < N2; ++b) gk[b] = T(0);
+  if (pen) {
+#pragma unroll
+    for (int b = 0; b < N2; ++b) gk[b] = Tc[N2 * (by + N2 * bz) + b] * va.w0;
+  }
+#pragma unroll
+  for (int b = 0; b < N2; ++b) q[b] = gk[b];
+  __syncthreads();
+#pragma unroll 1
+  for (int k = 1; k <= VK<3, M>::KMAX; ++k) {
+    if (pen) {
+#pragma unroll
+      for (int b = 0; b < N2; ++b) Tc[N2 * (by + N2 * bz) + b] = gk[b];
+    }
+    __syncthreads();
+    if (pen) {
+      T l[N2];
+      lap_pencil<M>(Tc, by, bz, va.ih, va.ratio[k], l);
+#pragma unroll
+      for (int b = 0; b < N2; ++b) F[N2 * (by + N2 * bz) + b] = l[b];
+    }
+    __syncthreads();
+    if (pen) tprod_pencil<M>(KA, F, by, bz, gk);
+#pragma unroll
+    for (int b = 0; b < N2; ++b) q[b] += gk[b];
+  }
+  // u_i[s] -= wscale (s_i + 1) / h_i q[s + e_i]: the pencil holding q[s + e_i]
+  // updates u_i[s]
+  if (pen) {
+    if (by < MP && bz < MP) {
+      const T f = wscale * va.ih[0];
+#pragma unroll
+      for (int sx = 0; sx < MP; ++sx) {
+        const T a = -(T)(sx + 1) * f, qv = q[sx + 1];
+        S::update(u, sx + MP * (by + MP * bz), n0, [&](T x) { return fma(a, qv, x); });
+      }
+    }
+    if (by >= 1 && by <= MP && bz < MP) {
+      const T a = -(T)by * (wscale * va.ih[1]);
+#pragma unroll
+      for (int sx = 0; sx < MP; ++sx) {
+        const T qv = q[sx];
+        S::update(u, NC + sx + MP * ((by - 1) + MP * bz), n0, [&](T x) { return fma(a, qv, x); });
+      }
+    }
+    if (by < MP && bz >= 1 && bz <= MP) {
+      const T a = -(T)bz * (wscale * va.ih[2]);
+#pragma unroll
+      for (int sx = 0; sx < MP; ++sx) {
+        const T qv = q[sx];
+        S::update(u, 2 * NC + sx + MP * (by + MP * (bz - 1)), n0, [&](T x) { return fma(a, qv, x); });
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -44,7 +44,8 @@ def _kappa(d, m, K, rng, smooth):
 
 
 CASES = ([(1, m, (37,)) for m in (0, 1, 3, 5, 7)] + [(1, 2, (2,))] + [(2, m, (41, 9)) for m in (0, 1, 2, 3, 4)]
-         + [(2, 5, (20, 7)), (2, 1, (2, 3)), (3, 0, (9, 7, 5)), (3, 1, (70, 6, 5)), (3, 1, (2, 3, 2))])
+         + [(2, 5, (20, 7)), (2, 1, (2, 3)), (3, 0, (9, 7, 5)), (3, 1, (70, 6, 5)), (3, 1, (2, 3, 2)),
+            (3, 2, (5, 4, 3)), (3, 2, (2, 2, 2)), (3, 3, (3, 3, 2))])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -68,7 +69,7 @@ def test_varkappa_half_steps_match_oracle(d, m, K, prec):
     _close(Ug, oracle.u_half_var(prob, U_in, Pg, ku), *vtol(prec, d, m))
 
 
-@pytest.mark.parametrize("d,m,K,n", [(1, 3, (40,), 20), (2, 2, (24, 18), 17)])
+@pytest.mark.parametrize("d,m,K,n", [(1, 3, (40,), 20), (2, 2, (24, 18), 17), (3, 2, (6, 5, 4), 17)])
 def test_varkappa_multistep_and_startup(d, m, K, n):
     """Start-up with half weights, then n >= 16 steps (graph replay) in FP64."""
     _say(f"[varkappa] start-up + {n} steps d={d} m={m}")
@@ -111,7 +112,7 @@ def test_set_kappa_none_restores_constant_and_adjoint_refuses():
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
-@pytest.mark.parametrize("kw", [dict(d=3, m=2, cells=(4, 4, 4)), dict(d=3, m=2, cells=(4, 4, 4), boundary="walls"),
+@pytest.mark.parametrize("kw", [dict(d=3, m=2, cells=(4, 4, 4), precision="fp32_comp"),
                                 dict(d=2, m=2, cells=(8, 8), precision="fp32_comp")])
 def test_varkappa_unsupported_cases(kw):
     plan = hl.Plan(**kw)
@@ -124,7 +125,7 @@ def test_varkappa_unsupported_cases(kw):
 
 
 WALL_CASES = [(1, 3, (37,)), (1, 0, (5,)), (1, 7, (20,)), (2, 1, (70, 9)), (2, 3, (41, 10)), (2, 2, (3, 2)),
-              (2, 4, (20, 9)), (2, 5, (12, 7)), (3, 1, (9, 6, 5))]
+              (2, 4, (20, 9)), (2, 5, (12, 7)), (3, 1, (9, 6, 5)), (3, 2, (4, 3, 3)), (3, 3, (2, 2, 2))]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -206,3 +207,46 @@ def test_varkappa_2d_m3_1024_sampled_fp32():
     _, Ug = plan.export(p, u)
     ref = oracle.u_half_var(prob, U_in, Pg, ku, nodes=nodes)
     _close(np.stack([Ug[i][nodes[:, 0], nodes[:, 1]] for i in range(d)]), ref, *vtol("fp32", d, m))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_varkappa_3d_m2_sampled(prec):
+    """3D m=2 (one wavefront per node) on a grid of many workgroups per XCD
+    run (80 x 36 x 30, smooth kappa): one step checked on sampled nodes,
+    corners and faces included."""
+    _say(f"[varkappa] 3D m=2 (80, 36, 30) {prec} sampled")
+    d, m, K = 3, 2, (80, 36, 30)
+    rng = np.random.default_rng(13)
+    plan = hl.Plan(d, m, K, cfl=0.5, c=np.sqrt(1.6), precision=prec)
+    prob = oracle.Problem(d, m, K, (1.0,) * 3, plan.dt, 1.0)
+    kp = inputs.kappa_sines(d, m, K, (1.0,) * 3, (0.35, 0.25, 0.2), (2, 3, 1), "primal")
+    ku = inputs.kappa_sines(d, m, K, (1.0,) * 3, (0.35, 0.25, 0.2), (2, 3, 1), "dual")
+    plan.set_kappa(kp, ku)
+    P, U = inputs.random_data(rng, d, m, K), inputs.random_data(rng, d, m, K, ncomp=d)
+    p, u = plan.alloc()
+    plan.init(p, u, P, U)
+    P_in, U_in = plan.export(p, u)
+    nodes = np.stack([rng.integers(0, k, 150) for k in K], axis=1)
+    nodes[0], nodes[1], nodes[2] = (0, 0, 0), (79, 35, 29), (79, 0, 29)
+    idx = tuple(nodes[:, k] for k in range(d))
+    plan.p_half(p, u)
+    Pg, _ = plan.export(p, u)
+    _close(Pg[idx], oracle.p_half_var(prob, P_in, U_in, kp, nodes=nodes), *vtol(prec, d, m))
+    plan.u_half(u, p)
+    _, Ug = plan.export(p, u)
+    ref = oracle.u_half_var(prob, U_in, Pg, ku, nodes=nodes)
+    _close(np.stack([Ug[i][idx] for i in range(d)]), ref, *vtol(prec, d, m))
+
+
+def test_varkappa_3d_batch_refused():
+    """Batched steps take variable kappa in 3D for m <= 1 only."""
+    plans = [hl.Plan(3, 2, (4, 4, 4), precision="fp32") for _ in range(2)]
+    bufs = []
+    for pl in plans:
+        kp, ku = _kappa(3, 2, (4, 4, 4), np.random.default_rng(5), smooth=False)
+        pl.set_kappa(kp, ku)
+        bufs.append(pl.alloc())
+    b = hl.Batch(plans)
+    with pytest.raises(hl.HLError) as ei:
+        b.step([x[0] for x in bufs], [x[1] for x in bufs], 1)
+    assert ei.value.status == hl.HL_ERR_UNSUPPORTED
