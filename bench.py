@@ -379,6 +379,53 @@ def run_varkappa(hl, torch, steps, K=1024, m=3):
     return res
 
 
+def run_varkappa_3d(hl, torch, steps, K=128, m=2):
+    """Variable coefficient in 3D at the headline's order (m=2; one wavefront
+    per node): smooth kappa = 1 + 0.35 sin(4 pi x) + 0.25 sin(6 pi y)
+    + 0.2 sin(2 pi z) on 128^3 (the kappa Taylor data of 256^3 would take
+    29 GB per array in FP64), Gaussian pulse data of width 0.05: `steps` steps
+    timed after 2 untimed ones, FP32 and FP64."""
+    from paper_1808_10481_amd import inputs
+    res = {}
+    L = (1.0, 1.0, 1.0)
+    amps, waves = (0.35, 0.25, 0.2), (2, 3, 1)
+    kp = inputs.kappa_sines(3, m, (K,) * 3, L, amps, waves, "primal")
+    ku = inputs.kappa_sines(3, m, (K,) * 3, L, amps, waves, "dual")
+    P0 = inputs.gaussian_pulse(3, m, (K,) * 3, L, (0.43, 0.52, 0.61), 0.05)
+    fin = {}
+    for prec in ("fp32", "fp64"):
+        log(f"[bench] variable kappa 3d m={m} {K}^3 {prec}: {steps} steps")
+        plan = hl.Plan(3, m, (K,) * 3, cfl=0.5, c=float(np.sqrt(1.8)), precision=prec)
+        plan.set_kappa(kp, ku)
+        p, u = plan.alloc()
+        plan.init(p, u, P0, None)
+        plan.step(p, u, 2)
+        stream = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for n in range(steps):
+            plan.p_half(p, u)
+            ev[2 * n + 1].record(stream)
+            plan.u_half(u, p)
+            ev[2 * n + 2].record(stream)
+        torch.cuda.synchronize()
+        total = ev[0].elapsed_time(ev[-1])
+        tp = float(np.mean([ev[2 * n].elapsed_time(ev[2 * n + 1]) for n in range(steps)]))
+        tu = float(np.mean([ev[2 * n + 1].elapsed_time(ev[2 * n + 2]) for n in range(steps)]))
+        res[prec] = {"value": K ** 3 * steps / (total * 1e-3), "unit": "cell-updates/s",
+                     "ms_per_step": total / steps, "p_half_ms": tp, "u_half_ms": tu, "steps": steps}
+        fin[prec] = plan.export(p, u)
+        if prec == "fp64":
+            res["fp32"]["rel_l2_vs_fp64_state"] = _rel_state(fin["fp32"], fin["fp64"])
+        plan.close()
+        del p, u
+        torch.cuda.empty_cache()
+    res["config"] = {"workload": f"variable_kappa_3d m={m} {K}^3 kappa=1+0.35sin(4pi x)+0.25sin(6pi y)"
+                                 "+0.2sin(2pi z), gaussian pulse width 0.05", "d": 3, "m": m, "cells": [K] * 3}
+    return res
+
+
 def run_batch(hl, torch, steps, nshots=32, m=3):
     """Batched shots: `nshots` periodic square grids with seeded sizes in
     [256, 1024] (the batched configuration's size mix), m=3 FP32, each with
@@ -757,6 +804,8 @@ def main():
     ap.add_argument("--no-walls", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-varkappa", action="store_true")
+    ap.add_argument("--no-varkappa-3d", action="store_true")
+    ap.add_argument("--steps-varkappa-3d", type=int, default=10)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--steps-batch", type=int, default=2000)
     ap.add_argument("--steps-varkappa", type=int, default=50)
@@ -827,6 +876,8 @@ def main():
         out["gaussian_pulse_walls_2d"] = run_walls(hl, torch, args.steps_walls)
     if not args.no_varkappa:
         out["variable_kappa_2d"] = run_varkappa(hl, torch, args.steps_varkappa)
+    if not args.no_varkappa_3d:
+        out["variable_kappa_3d"] = run_varkappa_3d(hl, torch, args.steps_varkappa_3d)
     if not args.no_batch:
         out["batched_shots_2d"] = run_batch(hl, torch, args.steps_batch)
     if not args.no_adjoint:

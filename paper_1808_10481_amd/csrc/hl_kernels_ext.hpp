@@ -621,9 +621,9 @@ __global__ void __launch_bounds__(256) u_half_var(typename S::View u, typename S
 // node.  Its polynomials live in LDS, and in the products and Laplacians
 // lane l < (2m+2)^2 owns the x-pencil b_y = l mod (2m+2), b_z = l div (2m+2)
 // (2m+2 coefficients along x, held in registers).  The arithmetic is that of
-// the per-node kernels above: the same tensor-product passes, and every
-// output of T[kappa f] sums kappa_a f_{b-a} over a in the same increasing
-// order.
+// the per-node kernels above (the same tensor-product passes, and the same
+// products kappa_a f_{b-a}), except that at m = 2 a pencil's sum is formed
+// from partial sums over chunks of its terms (below).
 // ---------------------------------------------------------------------------
 template <int M>
 struct VW {
@@ -709,8 +709,101 @@ __device__ __forceinline__ void interp_wave(const typename S::View& f, int comp,
   __syncthreads();
 }
 
-// Pencil (by, bz) of T[kappa f]: out[b_x] = sum over a <= b of kappa_a
-// f_{b-a}, K and F in LDS.
+// Work split of one truncated product over the 64 lanes.  Pencil (by, bz)
+// sums over the (by+1)(bz+1) pairs (a_y, a_z) <= (by, bz) (a_z outer), 2m+2
+// to 36 of them at m = 2; one lane per pencil would leave 28 lanes idle and
+// wait on the longest pencil.  Instead every pencil's pairs are cut into
+// chunks of at most C consecutive pairs, one chunk per lane, C the smallest
+// length that needs at most 64 chunks (m = 2: C = 10, 60 chunks; m = 3: no
+// cut, the 64 pencils take the 64 lanes), and each pencil then adds its
+// chunks' partial sums in chunk order.
+template <int M>
+struct WaveSched {
+  int C, n;
+  int8_t by[64], bz[64], i0[64], cnt[64];  // chunk (lane) -> pencil, first pair, pairs
+  int8_t first[64], nch[64];               // pencil -> its first chunk, chunks
+};
+
+template <int M>
+constexpr WaveSched<M> wave_sched() {
+  constexpr int N2 = 2 * M + 2;
+  WaveSched<M> s{};
+  int C = 1;
+  for (;; ++C) {
+    int n = 0;
+    for (int q = 0; q < N2 * N2; ++q) n += ((q % N2 + 1) * (q / N2 + 1) + C - 1) / C;
+    if (n <= 64) break;
+  }
+  s.C = C;
+  int c = 0;
+  for (int q = 0; q < N2 * N2; ++q) {
+    const int w = (q % N2 + 1) * (q / N2 + 1);
+    s.first[q] = (int8_t)c;
+    s.nch[q] = (int8_t)((w + C - 1) / C);
+    for (int i = 0; i < w; i += C, ++c) {
+      s.by[c] = (int8_t)(q % N2);
+      s.bz[c] = (int8_t)(q / N2);
+      s.i0[c] = (int8_t)i;
+      s.cnt[c] = (int8_t)(w - i < C ? w - i : C);
+    }
+  }
+  s.n = c;
+  return s;
+}
+
+// Every pencil's pairs covered once, in order, by its chunks.
+template <int M>
+constexpr bool wave_sched_ok(const WaveSched<M>& s) {
+  constexpr int N2 = 2 * M + 2;
+  if (s.n > 64) return false;
+  for (int q = 0; q < N2 * N2; ++q) {
+    int next = 0;
+    for (int c = s.first[q]; c < s.first[q] + s.nch[q]; ++c) {
+      if (s.by[c] != q % N2 || s.bz[c] != q / N2 || s.i0[c] != next || s.cnt[c] < 1 || s.cnt[c] > s.C) return false;
+      next += s.cnt[c];
+    }
+    if (next != (q % N2 + 1) * (q / N2 + 1)) return false;
+  }
+  return true;
+}
+
+template <int M>
+constexpr WaveSched<M> kWaveSched = wave_sched<M>();
+static_assert(wave_sched_ok<2>(kWaveSched<2>) && kWaveSched<2>.C == 10 && kWaveSched<2>.n == 60, "m = 2 split");
+static_assert(wave_sched_ok<3>(kWaveSched<3>) && kWaveSched<3>.n == 64, "m = 3: one chunk per pencil");
+// LDS words for the chunks' partial sums (1 when no pencil is cut)
+template <int M>
+constexpr int kWaveRed = kWaveSched<M>.n > VW<M>::NPEN ? 64 * VW<M>::N2 : 1;
+
+// Partial sum of pencil (by, bz) of T[kappa f] over the pairs i0 .. i0+cnt-1:
+// out[b_x] = sum of kappa_a f_{b-a}, a_x <= b_x, K and F in LDS.
+template <int M, typename T>
+__device__ __forceinline__ void tprod_chunk(const T* KA, const T* F, int by, int bz, int i0, int cnt, T* out) {
+  constexpr int N2 = VW<M>::N2;
+#pragma unroll
+  for (int b = 0; b < N2; ++b) out[b] = T(0);
+  int ay = i0 % (by + 1), az = i0 / (by + 1);
+  for (int i = 0; i < cnt; ++i) {
+    T kp[N2], fp[N2];
+    const T* kr = KA + N2 * (ay + N2 * az);
+    const T* fr = F + N2 * ((by - ay) + N2 * (bz - az));
+#pragma unroll
+    for (int b = 0; b < N2; ++b) {
+      kp[b] = kr[b];
+      fp[b] = fr[b];
+    }
+#pragma unroll
+    for (int bx = 0; bx < N2; ++bx)
+#pragma unroll
+      for (int ax = 0; ax <= bx; ++ax) out[bx] = fma(kp[ax], fp[bx - ax], out[bx]);
+    if (++ay > by) {
+      ay = 0;
+      ++az;
+    }
+  }
+}
+
+// Pencil (by, bz) of T[kappa f] in one lane (no cut): a_z outer, a_y inner.
 template <int M, typename T>
 __device__ __forceinline__ void tprod_pencil(const T* KA, const T* F, int by, int bz, T* out) {
   constexpr int N2 = VW<M>::N2;
@@ -733,6 +826,56 @@ __device__ __forceinline__ void tprod_pencil(const T* KA, const T* F, int by, in
     }
 }
 
+// This lane's chunk of a truncated product, and the pencil totals.
+template <int M>
+struct WaveLane {
+  int lane, cby, cbz, ci0, ccnt;  // the lane's chunk
+  bool pen;                       // lane < (2m+2)^2 owns pencil (by, bz) = (lane mod N2, lane div N2)
+  int by, bz, first, nch;
+  __device__ __forceinline__ explicit WaveLane(int l) : lane(l) {
+    constexpr int N2 = VW<M>::N2;
+    const WaveSched<M>& s = kWaveSched<M>;
+    const bool has = l < s.n;
+    cby = has ? s.by[l] : 0;
+    cbz = has ? s.bz[l] : 0;
+    ci0 = has ? s.i0[l] : 0;
+    ccnt = has ? s.cnt[l] : 0;
+    pen = l < VW<M>::NPEN;
+    by = pen ? l % N2 : 0;
+    bz = pen ? l / N2 : 0;
+    first = pen ? s.first[l] : 0;
+    nch = pen ? s.nch[l] : 0;
+  }
+};
+
+// t = pencil (by, bz) of T[kappa F] on the owning lanes; RED: 64 (2m+2)
+// partial sums.  Begins and ends with LDS reads only; callers separate it
+// from the next writes of F and RED by a barrier.
+template <int M, typename T>
+__device__ __forceinline__ void tprod_wave(const T* KA, const T* F, T* RED, const WaveLane<M>& w, T* t) {
+  constexpr int N2 = VW<M>::N2;
+  constexpr bool kSplit = kWaveSched<M>.n > VW<M>::NPEN;
+  T part[N2];
+  if constexpr (kSplit)
+    tprod_chunk<M>(KA, F, w.cby, w.cbz, w.ci0, w.ccnt, part);
+  else
+    tprod_pencil<M>(KA, F, w.cby, w.cbz, part);
+  if constexpr (kSplit) {
+#pragma unroll
+    for (int b = 0; b < N2; ++b) RED[w.lane * N2 + b] = part[b];
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < N2; ++b) t[b] = T(0);
+    for (int q = 0; q < w.nch; ++q) {
+#pragma unroll
+      for (int b = 0; b < N2; ++b) t[b] += RED[(w.first + q) * N2 + b];
+    }
+  } else {  // chunk c is pencil c
+#pragma unroll
+    for (int b = 0; b < N2; ++b) t[b] = part[b];
+  }
+}
+
 // Pencil (by, bz) of sc Lap t (coefficient space), t in LDS.
 template <int M, typename T>
 __device__ __forceinline__ void lap_pencil(const T* t, int by, int bz, const T* ih, T sc, T* out) {
@@ -753,17 +896,18 @@ template <int M, class S>
 __global__ void __launch_bounds__(64) p_half_var_wave(typename S::View p, typename S::View u, typename S::View kp,
                                                       Grid g, VarArgs<typename S::C> va, int32_t per_xcd) {
   using T = typename S::C;
-  constexpr int MP = VW<M>::MP, N2 = VW<M>::N2, NP = VW<M>::NP, NL = VW<M>::NPEN;
+  constexpr int MP = VW<M>::MP, N2 = VW<M>::N2, NP = VW<M>::NP;
   static_assert(VK<3, M>::KMAX <= kVarMaxK, "series longer than the ratio table");
-  __shared__ T A[NP], B[NP], KA[NP];
+  __shared__ T A[NP], B[NP], KA[NP], RED[kWaveRed<M>];
   int32_t j[3];
   if (!wave_node(g, blockIdx.x, per_xcd, j)) return;  // uniform over the workgroup
   const int lane = threadIdx.x;
+  const WaveLane<M> w(lane);
   const uint32_t n0 = out_index<3>(g, j);
   const uint32_t cnl = corner_node_of(g, j, lane & 7);  // dual q = j - 1 + e
   for (int a = lane; a < NP; a += 64) KA[a] = S::load(kp, a, n0);
-  const bool pen = lane < NL;
-  const int by = pen ? lane % N2 : 0, bz = pen ? lane / N2 : 0;
+  const bool pen = w.pen;
+  const int by = w.by, bz = w.bz;
   T dv[N2];  // w_0 div c on the lane's pencil
 #pragma unroll
   for (int b = 0; b < N2; ++b) dv[b] = T(0);
@@ -793,7 +937,7 @@ __global__ void __launch_bounds__(64) p_half_var_wave(typename S::View p, typena
   T acc[MP], t[N2];
 #pragma unroll
   for (int b = 0; b < N2; ++b) t[b] = T(0);
-  if (pen) tprod_pencil<M>(KA, F, by, bz, t);  // t_0 = w_0 r_0
+  tprod_wave<M>(KA, F, RED, w, t);  // t_0 = w_0 r_0
 #pragma unroll
   for (int b = 0; b < MP; ++b) acc[b] = t[b];
 #pragma unroll 1
@@ -810,7 +954,7 @@ __global__ void __launch_bounds__(64) p_half_var_wave(typename S::View p, typena
       for (int b = 0; b < N2; ++b) F[N2 * (by + N2 * bz) + b] = l[b];
     }
     __syncthreads();
-    if (pen) tprod_pencil<M>(KA, F, by, bz, t);  // t_k = w_k r_k
+    tprod_wave<M>(KA, F, RED, w, t);  // t_k = w_k r_k
 #pragma unroll
     for (int b = 0; b < MP; ++b) acc[b] += t[b];
   }
@@ -826,16 +970,17 @@ __global__ void __launch_bounds__(64) u_half_var_wave(typename S::View u, typena
                                                       Grid g, VarArgs<typename S::C> va, typename S::C wscale,
                                                       int32_t per_xcd) {
   using T = typename S::C;
-  constexpr int MP = VW<M>::MP, N2 = VW<M>::N2, NP = VW<M>::NP, NL = VW<M>::NPEN, NC = VW<M>::NC;
-  __shared__ T A[NP], B[NP], KA[NP];
+  constexpr int MP = VW<M>::MP, N2 = VW<M>::N2, NP = VW<M>::NP, NC = VW<M>::NC;
+  __shared__ T A[NP], B[NP], KA[NP], RED[kWaveRed<M>];
   int32_t j[3];
   if (!wave_node(g, blockIdx.x, per_xcd, j)) return;  // uniform over the workgroup
   const int lane = threadIdx.x;
+  const WaveLane<M> w(lane);
   const uint32_t n0 = out_index<3>(g, j);
   const uint32_t cnl = corner_node_of(g, j, lane & 7);  // primal j = q + e
   for (int a = lane; a < NP; a += 64) KA[a] = S::load(ku, a, n0);
-  const bool pen = lane < NL;
-  const int by = pen ? lane % N2 : 0, bz = pen ? lane / N2 : 0;
+  const bool pen = w.pen;
+  const int by = w.by, bz = w.bz;
   interp_wave<M, S>(p, 0, cnl, lane, A, B);
   T* F = A;  // Laplacian of the current term (input of the product)
   T* Tc = B;  // current term g_k
@@ -863,7 +1008,7 @@ __global__ void __launch_bounds__(64) u_half_var_wave(typename S::View u, typena
       for (int b = 0; b < N2; ++b) F[N2 * (by + N2 * bz) + b] = l[b];
     }
     __syncthreads();
-    if (pen) tprod_pencil<M>(KA, F, by, bz, gk);
+    tprod_wave<M>(KA, F, RED, w, gk);
 #pragma unroll
     for (int b = 0; b < N2; ++b) q[b] += gk[b];
   }
