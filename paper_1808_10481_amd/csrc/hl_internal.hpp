@@ -352,7 +352,7 @@ constexpr bool kVarBuilt = kPlain<S> && (D <= 2 || (D == 3 && M <= 1));
 template <int D, int M, class S>
 constexpr bool kVarWaveBuilt = kPlain<S> && D == 3 && M >= 2 && M <= 3;
 template <int D, int M, class S>
-constexpr bool kVarGradBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 3));
+constexpr bool kVarGradBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 3) || (D == 3 && M <= 1));
 
 template <int D, int M, class S>
 void batch_desc(const BatchShot* shots, int n, bool var, std::vector<unsigned char>* pdesc,
@@ -470,7 +470,7 @@ inline bool make_set(KernelSet* out) {
     out->p_half_var = &launch_p_var_wave<M, S>;
     out->u_half_var = &launch_u_var_wave<M, S>;
   }
-  // variable-kappa adjoint and kappa gradient: d = 1 (all m) and d = 2 (m <= 3)
+  // variable-kappa adjoint and kappa gradient: d = 1 (all m), d = 2 (m <= 3), d = 3 (m <= 1)
   out->grad_p_var = nullptr;
   out->grad_u_var = nullptr;
   out->gather_p_var = nullptr;

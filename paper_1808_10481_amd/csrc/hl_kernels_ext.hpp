@@ -1109,12 +1109,16 @@ constexpr bool kGradStage = sizeof(T) * VK<D, M>::NP >= 512;
 // grad_A += sum_b lam_{A+b} g_b (the kappa_A derivative of <lam, T[kappa g]>).
 template <int D, int M, int A, typename T>
 __device__ __forceinline__ void corr_term(const T* lam, const T* g, const LaneLds<T>& L, int gs) {
-  constexpr int N2 = 2 * M + 2, AX = A % N2, AY = A / N2, NY = D > 1 ? N2 : 1, NP = VK<D, M>::NP;
+  constexpr int N2 = 2 * M + 2, AX = A % N2, AY = (A / N2) % N2, AZ = A / (N2 * N2);
+  constexpr int NY = D > 1 ? N2 : 1, NZ = D > 2 ? N2 : 1, NP = VK<D, M>::NP;
   T acc = L(gs, A, NP);
 #pragma unroll
-  for (int by = 0; by + AY < NY; ++by)
+  for (int bz = 0; bz + AZ < NZ; ++bz)
 #pragma unroll
-    for (int bx = 0; bx + AX < N2; ++bx) acc = fma(lam[(bx + AX) + N2 * (by + AY)], g[bx + N2 * by], acc);
+    for (int by = 0; by + AY < NY; ++by)
+#pragma unroll
+      for (int bx = 0; bx + AX < N2; ++bx)
+        acc = fma(lam[(bx + AX) + N2 * ((by + AY) + N2 * (bz + AZ))], g[bx + N2 * (by + N2 * bz)], acc);
   L(gs, A, NP) = acc;
 }
 
@@ -1133,13 +1137,14 @@ __device__ __forceinline__ void corr(const T* lam, const T* g, const LaneLds<T>&
 template <int D, int M, typename T>
 __device__ __forceinline__ void lapT_coef(const T* f, T* out, const T* ih, T sc) {
   constexpr int N2 = 2 * M + 2, NP = VK<D, M>::NP;
-  const T ix2 = sc * ih[0] * ih[0], iy2 = sc * ih[1] * ih[1];
+  const T ix2 = sc * ih[0] * ih[0], iy2 = sc * ih[1] * ih[1], iz2 = sc * ih[2] * ih[2];
 #pragma unroll
   for (int b = 0; b < NP; ++b) {
-    const int bx = b % N2, by = b / N2;
+    const int bx = b % N2, by = (b / N2) % N2, bz = b / (N2 * N2);
     T v = T(0);
     if (bx >= 2) v = fma(T((bx - 1) * bx) * ix2, f[b - 2], v);
     if (D > 1 && by >= 2) v = fma(T((by - 1) * by) * iy2, f[b - 2 * N2], v);
+    if (D > 2 && bz >= 2) v = fma(T((bz - 1) * bz) * iz2, f[b - 2 * N2 * N2], v);
     out[b] = v;
   }
 }
@@ -1191,7 +1196,7 @@ template <int D, int M, class S>
 __global__ void __launch_bounds__(64) grad_p_var(typename S::View pb, typename S::View u, typename S::View kp,
                                                  double* __restrict__ gk, typename S::View rho, Grid g,
                                                  VarArgs<typename S::C> va) {
-  static_assert(D <= 2, "the adjoint of the variable-kappa half-steps is built for d <= 2");
+  static_assert(D <= 2 || M <= 1, "the adjoint of the variable-kappa half-steps: d <= 2, or d = 3 with m <= 1");
   using T = typename S::C;
   using Y = YSupport<D, M, true>;
   constexpr int N2 = 2 * M + 2, MP = M + 1, NP = VK<D, M>::NP, NC = Dims<D, M>::NC;
@@ -1211,11 +1216,11 @@ __global__ void __launch_bounds__(64) grad_p_var(typename S::View pb, typename S
   for (int i = 0; i < D; ++i) {
     T c[NP];
     interp_full<D, M, S>(u, i, cn, c);
-    const int st = i == 0 ? 1 : N2;
+    const int st = i == 0 ? 1 : i == 1 ? N2 : N2 * N2;
     const T w = va.w0 * va.ih[i];
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
-      const int bi = i == 0 ? b % N2 : b / N2;
+      const int bi = digit(b, N2, i);
       if (bi + 1 < N2) f[b] = fma(T(bi + 1) * w, c[b + st], f[b]);
     }
   }
@@ -1230,7 +1235,7 @@ __global__ void __launch_bounds__(64) grad_p_var(typename S::View pb, typename S
   }
   T yc[Y::NY];
 #pragma unroll
-  for (int s = 0; s < NC; ++s) yc[Y::idx((s % MP) + N2 * (s / MP))] = S::load(pb, s, n0);
+  for (int s = 0; s < NC; ++s) yc[Y::idx(poly_index<D, M>(s, 0, 0, 0))] = S::load(pb, s, n0);
   T lam[NP];
   adjoint_series<D, M, true, S>(kp, n0, L, t0, T0S, GS, yc, va, lam);
   if (STAGE) {
@@ -1245,10 +1250,11 @@ __global__ void __launch_bounds__(64) grad_p_var(typename S::View pb, typename S
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     const T w = va.w0 * va.ih[i];
+    const int st = i == 0 ? 1 : i == 1 ? N2 : N2 * N2;
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
-      const int bi = i == 0 ? b % N2 : b / N2;
-      const T v = bi >= 1 ? T(bi) * w * phi[b - (i == 0 ? 1 : N2)] : T(0);
+      const int bi = digit(b, N2, i);
+      const T v = bi >= 1 ? T(bi) * w * phi[b - st] : T(0);
       S::store(rho, i * NP + b, n0, v);
     }
   }
@@ -1261,7 +1267,7 @@ template <int D, int M, class S>
 __global__ void __launch_bounds__(64) grad_u_var(typename S::View ub, typename S::View p, typename S::View ku,
                                                  double* __restrict__ gk, typename S::View z, Grid g,
                                                  VarArgs<typename S::C> va) {
-  static_assert(D <= 2, "the adjoint of the variable-kappa half-steps is built for d <= 2");
+  static_assert(D <= 2 || M <= 1, "the adjoint of the variable-kappa half-steps: d <= 2, or d = 3 with m <= 1");
   using T = typename S::C;
   using Y = YSupport<D, M, false>;
   constexpr int N2 = 2 * M + 2, MP = M + 1, NP = VK<D, M>::NP, NC = Dims<D, M>::NC;
@@ -1290,9 +1296,8 @@ __global__ void __launch_bounds__(64) grad_u_var(typename S::View ub, typename S
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
-      const int sx = s % MP, sy = s / MP;
-      const int si = i == 0 ? sx : sy;
-      yc[Y::idx((sx + (i == 0)) + N2 * (sy + (i == 1)))] += T(si + 1) * va.ih[i] * S::load(ub, i * NC + s, n0);
+      const int si = digit(s, MP, i);
+      yc[Y::idx(poly_index<D, M>(s, i == 0, i == 1, i == 2))] += T(si + 1) * va.ih[i] * S::load(ub, i * NC + s, n0);
     }
   T lam[NP];
   adjoint_series<D, M, false, S>(ku, n0, L, t0, T0S, GS, yc, va, lam);
@@ -1323,6 +1328,48 @@ __device__ __forceinline__ void interp_T(const T* z, T* acc) {
         const double h = hcol<M, E & 1>(b, a);
         if (h != 0.0) acc[a] = fma(T(h), z[b], acc[a]);
       }
+  } else if constexpr (D == 3) {
+    T zz[N2][N2][MP];  // [b_x][b_y][a_z]
+#pragma unroll
+    for (int bx = 0; bx < N2; ++bx)
+#pragma unroll
+      for (int by = 0; by < N2; ++by)
+#pragma unroll
+        for (int az = 0; az < MP; ++az) {
+          T v = T(0);
+#pragma unroll
+          for (int bz = 0; bz < N2; ++bz) {
+            const double h = hcol<M, (E >> 2) & 1>(bz, az);
+            if (h != 0.0) v = fma(T(h), z[bx + N2 * (by + N2 * bz)], v);
+          }
+          zz[bx][by][az] = v;
+        }
+    T zy[N2][MP][MP];  // [b_x][a_y][a_z]
+#pragma unroll
+    for (int bx = 0; bx < N2; ++bx)
+#pragma unroll
+      for (int ay = 0; ay < MP; ++ay)
+#pragma unroll
+        for (int az = 0; az < MP; ++az) {
+          T v = T(0);
+#pragma unroll
+          for (int by = 0; by < N2; ++by) {
+            const double h = hcol<M, (E >> 1) & 1>(by, ay);
+            if (h != 0.0) v = fma(T(h), zz[bx][by][az], v);
+          }
+          zy[bx][ay][az] = v;
+        }
+#pragma unroll
+    for (int az = 0; az < MP; ++az)
+#pragma unroll
+      for (int ay = 0; ay < MP; ++ay)
+#pragma unroll
+        for (int ax = 0; ax < MP; ++ax)
+#pragma unroll
+          for (int bx = 0; bx < N2; ++bx) {
+            const double h = hcol<M, E & 1>(bx, ax);
+            if (h != 0.0) acc[ax + MP * (ay + MP * az)] = fma(T(h), zy[bx][ay][az], acc[ax + MP * (ay + MP * az)]);
+          }
   } else {
     T zy[N2][MP];
 #pragma unroll
@@ -1361,10 +1408,20 @@ __device__ __forceinline__ void gather_corner(const typename S::View& scr, int c
   interp_T<D, M, EP ^ ((1 << D) - 1)>(z, acc);
 }
 
+// In 3D a scheduling barrier after each corner keeps the compiler from
+// issuing all 8 corners' (2m+2)^3 loads up front (2 KB of scratch per lane at
+// m = 1 in FP64).
+template <int D, int M, class S, int EP>
+__device__ __forceinline__ void gather_corner_fenced(const typename S::View& scr, int comp, uint32_t node,
+                                                     typename S::C* acc) {
+  gather_corner<D, M, S, EP>(scr, comp, node, acc);
+  if constexpr (D == 3) __builtin_amdgcn_sched_barrier(0);
+}
+
 template <int D, int M, class S, int... EP>
 __device__ __forceinline__ void gather_corners(const typename S::View& scr, int comp, const uint32_t* cn,
                                                typename S::C* acc, std::integer_sequence<int, EP...>) {
-  (gather_corner<D, M, S, EP>(scr, comp, cn[EP], acc), ...);
+  (gather_corner_fenced<D, M, S, EP>(scr, comp, cn[EP], acc), ...);
 }
 
 template <int D, int M, class S, int... EP>
@@ -1390,8 +1447,12 @@ __global__ void __launch_bounds__(256) var_adjoint_gather(typename S::View out, 
   uint32_t cn[1 << D];
   corner_nodes<D>(g, j, cn);
   const uint32_t n0 = out_index<D>(g, j);
+  // The output loop stays a loop even for one output (an opaque bound): in 3D,
+  // straight-line code let the compiler issue every corner's loads at once.
+  int zero = 0;
+  if constexpr (D == 3) asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
 #pragma unroll 1
-  for (int io = 0; io < NO; ++io) {
+  for (int io = 0; io < NO + zero; ++io) {
     T acc[NC];
 #pragma unroll
     for (int a = 0; a < NC; ++a) acc[a] = T(0);

@@ -62,7 +62,7 @@ def _setup(d, m, K, prec, seed, smooth, c=np.sqrt(2.0), cfl=0.5):
 
 
 CASES = ([(1, m, (37,)) for m in (0, 1, 3, 7)] + [(2, m, (70, 9)) for m in (0, 1, 2)] + [(2, 1, (2, 3))]
-         + [(2, 3, (66, 5))])
+         + [(2, 3, (66, 5)), (3, 0, (5, 4, 3)), (3, 1, (70, 3, 3)), (3, 1, (2, 2, 2))])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -101,7 +101,7 @@ def _receivers(rng, K, n):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("d,m,K,nsteps,seg", [(1, 3, (40,), 7, 3), (2, 2, (24, 18), 9, None), (2, 1, (66, 10), 5, 2),
-                                                (2, 3, (12, 10), 4, 2)])
+                                                (2, 3, (12, 10), 4, 2), (3, 1, (5, 4, 3), 4, 2)])
 def test_checkpointed_receiver_gradient_matches_oracle(d, m, K, nsteps, seg, prec):
     _say(f"[kgrad] receivers d={d} m={m} K={K} n={nsteps} seg={seg} {prec}")
     rng, plan, prob, kp, ku = _setup(d, m, K, prec, 1300 + 10 * d + m, smooth=True)
@@ -222,7 +222,7 @@ def test_gradient_full_size_512_m2_central_differences():
     _fd_check(plan, kp, ku, p0, u0, nsteps, rec, data, 2, rng, 1e-3, 1e-6)
 
 
-WALL_VAR_CASES = [(1, 3, (10,)), (2, 1, (6, 5)), (2, 2, (4, 3)), (2, 3, (3, 3))]
+WALL_VAR_CASES = [(1, 3, (10,)), (2, 1, (6, 5)), (2, 2, (4, 3)), (2, 3, (3, 3)), (3, 1, (3, 2, 2))]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -291,3 +291,17 @@ def test_walls_receiver_gradient_matches_central_differences():
     rec = [tuple(int(rng.integers(1, k)) for k in K) for _ in range(4)]
     data = rng.normal(size=(nsteps, len(rec))) * 0.01
     _fd_check(plan, kp, ku, p0, u0, nsteps, rec, data, 4, rng, 1e-3, 1e-7)
+
+
+def test_adjoint_step_var_3d_m2_unsupported():
+    """3D m = 2 has the variable-kappa forward (one wavefront per node) but no
+    transposed step: the adjoint and the kappa gradient refuse it."""
+    rng, plan, prob, kp, ku = _setup(3, 2, (4, 4, 4), "fp32", 7, smooth=False)
+    p, u = plan.alloc()
+    pb, ub = plan.alloc()
+    with pytest.raises(hl.HLError) as ei:
+        plan.adjoint_step_var(pb, ub, p, u)
+    assert ei.value.status == hl.HL_ERR_UNSUPPORTED
+    with pytest.raises(hl.HLError) as ei:
+        plan.kappa_grad()
+    assert ei.value.status == hl.HL_ERR_UNSUPPORTED
