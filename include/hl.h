@@ -256,8 +256,9 @@ hl_status hl_norms_noalloc(hl_plan_t plan, const void* p, const void* u, double*
  * pressure-side operators read it).
  * The transposed half-steps apply dense per-corner blocks of nc x nc
  * (nc = (m+1)^d), all output rows at once up to nc = 27 and in passes of 16
- * rows beyond.  Built in HL_FP64 and HL_FP32 for every d and m;
- * HL_ERR_UNSUPPORTED for HL_FP32_COMP.  Asynchronous. */
+ * rows beyond.  Built in every precision for every d and m (HL_FP32_COMP:
+ * FP64 arithmetic on the hi + lo data, each update rounded back to hi + lo as
+ * in the forward step).  Asynchronous. */
 hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* p,
                           const void* u, void* grad_kappa, int64_t nsteps, void* stream);
 

@@ -771,12 +771,19 @@ __global__ void add_partials(const double* __restrict__ partial, int n, double* 
 }
 
 // *acc += <a, b> for two p-shaped (field 0) or u-shaped (field 1) buffers.
+// Bytes per stored coefficient (FP32_COMP: an FP32 hi word and a BF16 lo word).
+size_t state_bytes(const hl_plan_s* pl) { return (size_t)pl->word_bytes * pl->words_per_coef; }
+
 hipError_t dot_into(const hl_plan_s* pl, const void* a, const void* b, int field, double* acc, hipStream_t s) {
   const int planes = (field == 0 ? 1 : pl->d) * pl->nc;
   const int64_t nodes = field == 0 ? pl->pnodes : pl->unodes;
   const int ncomp = field == 0 ? 1 : pl->d;
   if (pl->precision == HL_FP64) {
     using S = hl::PlainStore<double>;
+    hipLaunchKernelGGL(dot_kernel<S>, dim3(kNormBlocks), dim3(256), 0, s, S::make(a, ncomp, pl->nc, nodes),
+                       S::make(b, ncomp, pl->nc, nodes), planes, pl->gpart);
+  } else if (pl->precision == HL_FP32_COMP) {
+    using S = hl::SplitStore;
     hipLaunchKernelGGL(dot_kernel<S>, dim3(kNormBlocks), dim3(256), 0, s, S::make(a, ncomp, pl->nc, nodes),
                        S::make(b, ncomp, pl->nc, nodes), planes, pl->gpart);
   } else {
@@ -818,8 +825,8 @@ hl_status ensure_gradient(hl_plan_s* pl) {
   hl_status st = build_tables(pl, tdk, WeightMode{pl->dt, true});
   if (st == HL_OK) st = build_tables(pl, trev, WeightMode{-pl->dt, false});
   if (st != HL_OK) return st;
-  const size_t pbytes = (size_t)pl->nc * pl->pnodes * pl->tab_bytes;
-  const size_t ubytes = (size_t)pl->d * pl->nc * pl->unodes * pl->tab_bytes;
+  const size_t pbytes = (size_t)pl->nc * pl->pnodes * state_bytes(pl);
+  const size_t ubytes = (size_t)pl->d * pl->nc * pl->unodes * state_bytes(pl);
   hipError_t e = upload_table(pl, tdk, &pl->tab_dk);
   if (e == hipSuccess) e = upload_table(pl, trev, &pl->tab_rev);
   if (e == hipSuccess) e = hipMalloc(&pl->fp, pbytes);
@@ -1385,7 +1392,7 @@ hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* 
                    plan->pnodes, &gf))
       return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step: grid too large for the launch");
     if (!plan->wscr) {
-      const size_t ub = (size_t)plan->d * plan->nc * plan->unodes * plan->word_bytes;
+      const size_t ub = (size_t)plan->d * plan->nc * plan->unodes * state_bytes(plan);
       hipError_t e = hipMalloc(&plan->wscr, ub);
       if (e == hipSuccess) e = hipMemset(plan->wscr, 0, ub);  // the fold leaves it zeroed after each use
       if (e != hipSuccess) {
@@ -1408,8 +1415,8 @@ hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* 
     hl::PlanView vdk = v, vrev = v;
     vdk.tab = plan->tab_dk;
     vrev.tab = plan->tab_rev;
-    const size_t pbytes = (size_t)plan->nc * plan->pnodes * plan->tab_bytes;
-    const size_t ubytes = (size_t)plan->d * plan->nc * plan->unodes * plan->tab_bytes;
+    const size_t pbytes = (size_t)plan->nc * plan->pnodes * state_bytes(plan);
+    const size_t ubytes = (size_t)plan->d * plan->nc * plan->unodes * state_bytes(plan);
     double* g = static_cast<double*>(grad_kappa);
     if (e == hipSuccess) e = hipMemcpyAsync(plan->fp, p, pbytes, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(plan->fu, u, ubytes, hipMemcpyDeviceToDevice, s);
@@ -1445,8 +1452,8 @@ hl_status hl_adjoint_step(hl_plan_t plan, void* p_bar, void* u_bar, const void* 
   hl::PlanView vdk = v, vrev = v;
   vdk.tab = plan->tab_dk;
   vrev.tab = plan->tab_rev;
-  const size_t pbytes = (size_t)plan->nc * plan->pnodes * plan->tab_bytes;
-  const size_t ubytes = (size_t)plan->d * plan->nc * plan->unodes * plan->tab_bytes;
+  const size_t pbytes = (size_t)plan->nc * plan->pnodes * state_bytes(plan);
+  const size_t ubytes = (size_t)plan->d * plan->nc * plan->unodes * state_bytes(plan);
   double* g = static_cast<double*>(grad_kappa);
   hipError_t e = hipMemcpyAsync(plan->fp, p, pbytes, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(plan->fu, u, ubytes, hipMemcpyDeviceToDevice, s);
@@ -1497,8 +1504,8 @@ hl_status hl_tune(hl_plan_t plan, const void* p, const void* u, int32_t reps, vo
   if (!p || !u || p == u) return fail(HL_ERR_ARG, "hl_tune: p and u must be distinct non-NULL buffers");
   if (reps < 1) return fail(HL_ERR_ARG, "hl_tune: reps must be >= 1");
   hipStream_t s = (hipStream_t)stream;
-  const size_t pbytes = (size_t)plan->words_per_coef * plan->nc * plan->pnodes * plan->word_bytes;
-  const size_t ubytes = (size_t)plan->words_per_coef * plan->d * plan->nc * plan->unodes * plan->word_bytes;
+  const size_t pbytes = (size_t)plan->nc * plan->pnodes * state_bytes(plan);
+  const size_t ubytes = (size_t)plan->d * plan->nc * plan->unodes * state_bytes(plan);
   void *tp = nullptr, *tu = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipMalloc(&tp, pbytes);
@@ -1584,7 +1591,7 @@ hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const vo
                    plan->pnodes, &gf))
       return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: grid too large for the launch");
     const size_t zb = (size_t)kappa_planes(plan) * plan->unodes * plan->tab_bytes;
-    const size_t ub = (size_t)plan->d * plan->nc * plan->unodes * plan->word_bytes;
+    const size_t ub = (size_t)plan->d * plan->nc * plan->unodes * state_bytes(plan);
     hipError_t e = hipSuccess;
     for (auto [q, bytes] : {std::pair<void**, size_t>{&plan->vzw, zb}, {&plan->ucw, ub}, {&plan->wscr, ub}}) {
       if (*q) continue;

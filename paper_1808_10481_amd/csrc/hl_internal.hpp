@@ -446,13 +446,11 @@ inline bool make_set(KernelSet* out) {
   out->adj_u = nullptr;
   out->adj_u_walls = nullptr;
   out->ghost_zero = nullptr;
-  // adjoint: FP64 and FP32 storage, every (d, m)
-  if constexpr (kPlain<S>) {
-    out->adj_p = &launch_adjoint<D, M, S, true>;
-    out->adj_u = &launch_adjoint<D, M, S, false>;
-    out->adj_u_walls = &launch_adj_u_walls<D, M, S>;
-    out->ghost_zero = &launch_ghost_zero<D, M, S>;
-  }
+  // adjoint: every storage and (d, m)
+  out->adj_p = &launch_adjoint<D, M, S, true>;
+  out->adj_u = &launch_adjoint<D, M, S, false>;
+  out->adj_u_walls = &launch_adj_u_walls<D, M, S>;
+  out->ghost_zero = &launch_ghost_zero<D, M, S>;
   out->p_half_var = nullptr;
   out->u_half_var = nullptr;
   out->batch_desc = &batch_desc<D, M, S>;
