@@ -203,8 +203,8 @@ hl_status hl_add_source(hl_plan_t plan, void* p, const void* g, double a, void* 
  * this length is a reading for d >= 2).  The
  * plan's c must be the largest speed (it sets the CFL check and dt).  Both
  * pointers NULL: back to the plan's constant kappa = c^2.  Built for
- * every (d, m) in HL_FP64 and HL_FP32, periodic or walls (HL_ERR_UNSUPPORTED
- * in HL_FP32_COMP); in 3D from m = 2 on, one wavefront of 64 work-items
+ * every (d, m) and precision, periodic or walls (HL_FP32_COMP keeps the kappa
+ * data as hi + lo like the state); in 3D from m = 2 on, one wavefront of 64 work-items
  * updates each node (its (2m+2)^3-coefficient polynomials in LDS), and such
  * plans are not batched (hl_batch_step returns HL_ERR_UNSUPPORTED).
  * hl_adjoint_step then returns HL_ERR_UNSUPPORTED.  Synchronous. */

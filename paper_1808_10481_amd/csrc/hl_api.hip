@@ -1303,8 +1303,7 @@ hl_status hl_set_kappa(hl_plan_t plan, const double* kappa_p, const double* kapp
     }
     return HL_OK;
   }
-  if (!plan->ks.p_half_var)
-    return fail(HL_ERR_UNSUPPORTED, "hl_set_kappa: variable kappa is built in HL_FP64 and HL_FP32");
+  if (!plan->ks.p_half_var) return fail(HL_ERR_UNSUPPORTED, "hl_set_kappa: variable kappa is not built for this plan");
   // host layout [nodes][b_1..b_d], b_k in 0..2m+1: the field layout of order
   // 2m+1 of p (primal nodes, K+1 per dimension with walls) and of one velocity
   // component (dual nodes; with walls stored in the padded array, whose ghost
@@ -1321,10 +1320,13 @@ hl_status hl_set_kappa(hl_plan_t plan, const double* kappa_p, const double* kapp
     const LayoutMap L = hl_host::field_layout(plan->d, 2 * plan->m + 1, plan->K, plan->walls, f);
     FieldImage im{plan->precision, (int64_t)L.nc * L.nodes, {}, {}};
     if (!im.alloc()) return fail(HL_ERR_NOMEM, "hl_set_kappa: host staging allocation failed");
-    if (!*dsts[f] && (e = hipMalloc(dsts[f], im.hi_bytes())) != hipSuccess)
+    // the kappa data in the plan's storage (FP32_COMP: hi planes, then lo planes)
+    if (!*dsts[f] && (e = hipMalloc(dsts[f], im.hi_bytes() + im.lo_bytes())) != hipSuccess)
       return fail(HL_ERR_NOMEM, std::string("hl_set_kappa: device allocation: ") + hipGetErrorString(e));
     L.for_each([&](int64_t h, int64_t dv) { im.put(dv, srcs[f][h]); });
     e = hipMemcpy(*dsts[f], im.hi.data(), im.hi_bytes(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && im.lo_bytes())
+      e = hipMemcpy(static_cast<char*>(*dsts[f]) + im.hi_bytes(), im.lo.data(), im.lo_bytes(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hl_set_kappa: copy to device");
   }
   plan->var_kappa = true;
@@ -1801,7 +1803,7 @@ hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_
   }
   if (var && !batch->ks.batch_var)
     return fail(HL_ERR_UNSUPPORTED, "hl_batch_step: batched variable kappa is built for d = 1, d = 2 and d = 3 "
-                                    "with m <= 1, in HL_FP64 or HL_FP32");
+                                    "with m <= 1");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipSuccess;
   bool same = var == batch->var && batch->bp.size() == (size_t)n && batch->gens.size() == (size_t)n &&

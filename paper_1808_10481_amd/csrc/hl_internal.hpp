@@ -348,9 +348,9 @@ template <typename W>
 constexpr bool kPlain<PlainStore<W>> = true;
 
 template <int D, int M, class S>
-constexpr bool kVarBuilt = kPlain<S> && (D <= 2 || (D == 3 && M <= 1));
+constexpr bool kVarBuilt = D <= 2 || (D == 3 && M <= 1);
 template <int D, int M, class S>
-constexpr bool kVarWaveBuilt = kPlain<S> && D == 3 && M >= 2 && M <= 3;
+constexpr bool kVarWaveBuilt = D == 3 && M >= 2 && M <= 3;
 template <int D, int M, class S>
 constexpr bool kVarGradBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 3) || (D == 3 && M <= 1));
 
@@ -457,8 +457,8 @@ inline bool make_set(KernelSet* out) {
   out->p_batch = &launch_batch<D, M, S, true>;
   out->u_batch = &launch_batch<D, M, S, false>;
   out->batch_src = SrcLauncher<S>::fn;
-  // variable kappa: FP64 and FP32 storage, every (d, m); batched for d <= 2
-  // and d = 3, m <= 1
+  // variable kappa: every storage and (d, m); batched for d <= 2 and d = 3,
+  // m <= 1
   out->batch_var = false;
   if constexpr (kVarBuilt<D, M, S>) {
     out->p_half_var = &launch_p_var<D, M, S>;

@@ -55,6 +55,7 @@ def _shots(d, m, prec, sizes, rng, var=False, walls=()):
     (2, 3, "fp32", [(64, 48), (100, 37), (33, 20)], False, (0, 2)),
     (2, 2, "fp64", [(40, 24), (17, 9)], True, (1,)),
     (3, 1, "fp32_comp", [(12, 9, 5), (6, 7, 4)], False, (0, 1)),
+    (2, 3, "fp32_comp", [(40, 24), (17, 9)], True, (1,)),
 ])
 def test_batch_equals_per_plan_steps(d, m, prec, sizes, var, walls):
     _say(f"[batch] d={d} m={m} {prec} shots={sizes} var={var} walls={walls}")
