@@ -305,7 +305,7 @@ hl_status hl_tune(hl_plan_t plan, const void* p, const void* u, int32_t reps, vo
  * reads it, the ghost slots of u_bar are cleared and stay zero, and A^T p_bar
  * is formed on the whole padded velocity array and folded into the nodes the
  * ghosts mirror (plan-owned scratch arrays, allocated on first use).  Built
- * for d = 1 (all m), d = 2 (m <= 3) and d = 3 (m <= 1), HL_FP64 and HL_FP32;
+ * for d = 1 (all m), d = 2 (m <= 3) and d = 3 (m <= 1), every precision;
  * HL_ERR_UNSUPPORTED otherwise, or without kappa data.  Asynchronous. */
 hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const void* p_next,
                               const void* u_prev, void* stream);

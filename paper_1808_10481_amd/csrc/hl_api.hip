@@ -1568,7 +1568,7 @@ hl_status hl_adjoint_step_var(hl_plan_t plan, void* p_bar, void* u_bar, const vo
   if (!plan->var_kappa) return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: the plan has no kappa data (hl_set_kappa)");
   if (!plan->ks.grad_p_var)
     return fail(HL_ERR_UNSUPPORTED, "hl_adjoint_step_var: built for d = 1 (all m), d = 2 (m <= 3) and d = 3 "
-                                    "(m <= 1), HL_FP64 and HL_FP32");
+                                    "(m <= 1)");
   if (!p_bar || !u_bar || !p_next || !u_prev)
     return fail(HL_ERR_ARG, "hl_adjoint_step_var: NULL buffer");
   const void* bufs[4] = {p_bar, u_bar, p_next, u_prev};
@@ -1630,8 +1630,7 @@ hl_status hl_kappa_grad(hl_plan_t plan, double* grad_p, double* grad_u, int rese
   hl_status st = check_plan(plan, "hl_kappa_grad");
   if (st != HL_OK) return st;
   if (!plan->ks.grad_p_var)
-    return fail(HL_ERR_UNSUPPORTED, "hl_kappa_grad: built for d = 1 (all m), d = 2 (m <= 3) and d = 3 (m <= 1), "
-                                    "HL_FP64 and HL_FP32");
+    return fail(HL_ERR_UNSUPPORTED, "hl_kappa_grad: built for d = 1 (all m), d = 2 (m <= 3) and d = 3 (m <= 1)");
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hl_kappa_grad: pending work failed");
   if ((st = ensure_var_gradient(plan)) != HL_OK) return st;

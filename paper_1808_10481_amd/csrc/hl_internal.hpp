@@ -352,7 +352,7 @@ constexpr bool kVarBuilt = D <= 2 || (D == 3 && M <= 1);
 template <int D, int M, class S>
 constexpr bool kVarWaveBuilt = D == 3 && M >= 2 && M <= 3;
 template <int D, int M, class S>
-constexpr bool kVarGradBuilt = kPlain<S> && (D == 1 || (D == 2 && M <= 3) || (D == 3 && M <= 1));
+constexpr bool kVarGradBuilt = D == 1 || (D == 2 && M <= 3) || (D == 3 && M <= 1);
 
 template <int D, int M, class S>
 void batch_desc(const BatchShot* shots, int n, bool var, std::vector<unsigned char>* pdesc,
