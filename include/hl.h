@@ -205,8 +205,7 @@ hl_status hl_add_source(hl_plan_t plan, void* p, const void* g, double a, void* 
  * pointers NULL: back to the plan's constant kappa = c^2.  Built for
  * every (d, m) and precision, periodic or walls (HL_FP32_COMP keeps the kappa
  * data as hi + lo like the state); in 3D from m = 2 on, one wavefront of 64 work-items
- * updates each node (its (2m+2)^3-coefficient polynomials in LDS), and such
- * plans are not batched (hl_batch_step returns HL_ERR_UNSUPPORTED).
+ * updates each node (its (2m+2)^3-coefficient polynomials in LDS).
  * hl_adjoint_step then returns HL_ERR_UNSUPPORTED.  Synchronous. */
 hl_status hl_set_kappa(hl_plan_t plan, const double* kappa_p, const double* kappa_u);
 
@@ -326,8 +325,8 @@ hl_status hl_kappa_grad(hl_plan_t plan, double* grad_p, double* grad_u, int rese
  * waiting for the stream) when the buffers change, and nsteps >= 16 replays a
  * captured graph of 16 batched steps.  Shots may have reflecting walls
  * (HL_WALLS): their ghost refresh is launched per shot before the batched
- * pressure half-step.  Variable kappa is batched for d <= 2 and for d = 3
- * with m <= 1 (hl_batch_step returns HL_ERR_UNSUPPORTED otherwise). */
+ * pressure half-step.  Variable kappa is batched for every d and m (3D
+ * m >= 2: one workgroup per node of each shot, as in hl_step). */
 typedef struct hl_batch_s* hl_batch_t;
 hl_status hl_batch_create(const hl_plan_t* plans, int32_t n, hl_batch_t* out);
 hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_t nsteps, void* stream);

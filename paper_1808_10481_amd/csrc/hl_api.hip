@@ -1801,8 +1801,7 @@ hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_
       return fail(HL_ERR_ARG, "hl_batch_step: variable kappa must be set on every plan of the batch or on none");
   }
   if (var && !batch->ks.batch_var)
-    return fail(HL_ERR_UNSUPPORTED, "hl_batch_step: batched variable kappa is built for d = 1, d = 2 and d = 3 "
-                                    "with m <= 1");
+    return fail(HL_ERR_UNSUPPORTED, "hl_batch_step: batched variable kappa is not built for this (d, m)");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipSuccess;
   bool same = var == batch->var && batch->bp.size() == (size_t)n && batch->gens.size() == (size_t)n &&

@@ -374,7 +374,12 @@ void batch_desc(const BatchShot* shots, int n, bool var, std::vector<unsigned ch
     a.wscale = T(1);
     for (int k = 0; k < 3; ++k) a.ih[k] = (T)v.ih[k];
     a.first_block = fp;
-    fp += v.gp.per_xcd * kXcds;
+    if (var && kVarWaveBuilt<D, M, S>) {  // one workgroup per node
+      a.wave_per_xcd = (int32_t)(((int64_t)v.gp.K[0] * v.gp.K[1] * v.gp.K[2] + kXcds - 1) / kXcds);
+      fp += a.wave_per_xcd * kXcds;
+    } else {
+      fp += v.gp.per_xcd * kXcds;
+    }
     ShotHalf<S>& b = U[i];
     b = ShotHalf<S>{};
     b.out = S::make(shots[i].u, D, NC, v.gu.onodes);
@@ -386,7 +391,12 @@ void batch_desc(const BatchShot* shots, int n, bool var, std::vector<unsigned ch
     b.wscale = T(1);
     for (int k = 0; k < 3; ++k) b.ih[k] = (T)v.ih[k];
     b.first_block = fu;
-    fu += v.gu.per_xcd * kXcds;
+    if (var && kVarWaveBuilt<D, M, S>) {
+      b.wave_per_xcd = (int32_t)(((int64_t)v.gu.K[0] * v.gu.K[1] * v.gu.K[2] + kXcds - 1) / kXcds);
+      fu += b.wave_per_xcd * kXcds;
+    } else {
+      fu += v.gu.per_xcd * kXcds;
+    }
   }
   const size_t bytes = (size_t)n * sizeof(ShotHalf<S>);
   pdesc->resize(bytes);
@@ -406,6 +416,11 @@ hipError_t launch_batch(const void* desc, int n, int blocks, bool var, dim3 bloc
         hipLaunchKernelGGL((p_half_batch<D, M, S, true>), dim3((unsigned)blocks), block, 0, s, d, n);
       else
         hipLaunchKernelGGL((u_half_batch<D, M, S, true>), dim3((unsigned)blocks), block, 0, s, d, n);
+    } else if constexpr (kVarWaveBuilt<D, M, S>) {
+      if (P)
+        hipLaunchKernelGGL((p_half_batch_wave<M, S>), dim3((unsigned)blocks), dim3(64), 0, s, d, n);
+      else
+        hipLaunchKernelGGL((u_half_batch_wave<M, S>), dim3((unsigned)blocks), dim3(64), 0, s, d, n);
     } else {
       return hipErrorInvalidValue;
     }
@@ -457,8 +472,7 @@ inline bool make_set(KernelSet* out) {
   out->p_batch = &launch_batch<D, M, S, true>;
   out->u_batch = &launch_batch<D, M, S, false>;
   out->batch_src = SrcLauncher<S>::fn;
-  // variable kappa: every storage and (d, m); batched for d <= 2 and d = 3,
-  // m <= 1
+  // variable kappa: every storage and (d, m), batched too
   out->batch_var = false;
   if constexpr (kVarBuilt<D, M, S>) {
     out->p_half_var = &launch_p_var<D, M, S>;
@@ -467,6 +481,7 @@ inline bool make_set(KernelSet* out) {
   } else if constexpr (kVarWaveBuilt<D, M, S>) {
     out->p_half_var = &launch_p_var_wave<M, S>;
     out->u_half_var = &launch_u_var_wave<M, S>;
+    out->batch_var = true;
   }
   // variable-kappa adjoint and kappa gradient: d = 1 (all m), d = 2 (m <= 3), d = 3 (m <= 1)
   out->grad_p_var = nullptr;

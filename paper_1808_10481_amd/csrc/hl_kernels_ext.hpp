@@ -893,14 +893,14 @@ __device__ __forceinline__ void lap_pencil(const T* t, int by, int bz, const T* 
 }
 
 template <int M, class S>
-__global__ void __launch_bounds__(64) p_half_var_wave(typename S::View p, typename S::View u, typename S::View kp,
-                                                      Grid g, VarArgs<typename S::C> va, int32_t per_xcd) {
+__device__ __forceinline__ void p_half_var_wave_body(typename S::View p, typename S::View u, typename S::View kp,
+                                                     Grid g, VarArgs<typename S::C> va, int32_t per_xcd, int blk) {
   using T = typename S::C;
   constexpr int MP = VW<M>::MP, N2 = VW<M>::N2, NP = VW<M>::NP;
   static_assert(VK<3, M>::KMAX <= kVarMaxK, "series longer than the ratio table");
   __shared__ T A[NP], B[NP], KA[NP], RED[kWaveRed<M>];
   int32_t j[3];
-  if (!wave_node(g, blockIdx.x, per_xcd, j)) return;  // uniform over the workgroup
+  if (!wave_node(g, blk, per_xcd, j)) return;  // uniform over the workgroup
   const int lane = threadIdx.x;
   const WaveLane<M> w(lane);
   const uint32_t n0 = out_index<3>(g, j);
@@ -966,14 +966,14 @@ __global__ void __launch_bounds__(64) p_half_var_wave(typename S::View p, typena
 }
 
 template <int M, class S>
-__global__ void __launch_bounds__(64) u_half_var_wave(typename S::View u, typename S::View p, typename S::View ku,
-                                                      Grid g, VarArgs<typename S::C> va, typename S::C wscale,
-                                                      int32_t per_xcd) {
+__device__ __forceinline__ void u_half_var_wave_body(typename S::View u, typename S::View p, typename S::View ku,
+                                                     Grid g, VarArgs<typename S::C> va, typename S::C wscale,
+                                                     int32_t per_xcd, int blk) {
   using T = typename S::C;
   constexpr int MP = VW<M>::MP, N2 = VW<M>::N2, NP = VW<M>::NP, NC = VW<M>::NC;
   __shared__ T A[NP], B[NP], KA[NP], RED[kWaveRed<M>];
   int32_t j[3];
-  if (!wave_node(g, blockIdx.x, per_xcd, j)) return;  // uniform over the workgroup
+  if (!wave_node(g, blk, per_xcd, j)) return;  // uniform over the workgroup
   const int lane = threadIdx.x;
   const WaveLane<M> w(lane);
   const uint32_t n0 = out_index<3>(g, j);
@@ -1040,6 +1040,19 @@ __global__ void __launch_bounds__(64) u_half_var_wave(typename S::View u, typena
       }
     }
   }
+}
+
+template <int M, class S>
+__global__ void __launch_bounds__(64) p_half_var_wave(typename S::View p, typename S::View u, typename S::View kp,
+                                                      Grid g, VarArgs<typename S::C> va, int32_t per_xcd) {
+  p_half_var_wave_body<M, S>(p, u, kp, g, va, per_xcd, blockIdx.x);
+}
+
+template <int M, class S>
+__global__ void __launch_bounds__(64) u_half_var_wave(typename S::View u, typename S::View p, typename S::View ku,
+                                                      Grid g, VarArgs<typename S::C> va, typename S::C wscale,
+                                                      int32_t per_xcd) {
+  u_half_var_wave_body<M, S>(u, p, ku, g, va, wscale, per_xcd, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1516,7 +1529,8 @@ struct ShotHalf {
   Grid g;
   VarArgs<typename S::C> va;       // variable kappa
   typename S::C wscale, ih[3];     // velocity half-step
-  int32_t first_block, pad;
+  int32_t first_block;
+  int32_t wave_per_xcd;            // variable kappa, 3D m >= 2: nodes per XCD run (one workgroup per node)
 };
 
 // A table pointer read from memory, recast to the constant address space so
@@ -1582,6 +1596,24 @@ __global__ void __launch_bounds__(256, HL_WAVES_PER_EU) u_half_batch(const ShotH
     u_half_3d_body<M, G>(out, in, tab, sh.g, sh.wscale, sh.ih[0], sh.ih[1], sh.ih[2], blk);
   else
     u_half_body<D, M, G>(out, in, tab, sh.g, sh.wscale, sh.ih[0], sh.ih[1], sh.ih[2], blk);
+}
+
+// Variable kappa, 3D m >= 2, batched: one 64-wide workgroup per node of each
+// shot, as in the single-shot launch.
+template <int M, class S>
+__global__ void __launch_bounds__(64) p_half_batch_wave(const ShotHalf<S>* __restrict__ shots, int n) {
+  const ShotHalf<S> sh = shot_desc(shots, shot_of(shots, n, blockIdx.x));
+  using G = typename S::Global;
+  p_half_var_wave_body<M, G>(S::global(sh.out), S::global(sh.in), S::global(sh.kap), sh.g, sh.va, sh.wave_per_xcd,
+                             (int)blockIdx.x - sh.first_block);
+}
+
+template <int M, class S>
+__global__ void __launch_bounds__(64) u_half_batch_wave(const ShotHalf<S>* __restrict__ shots, int n) {
+  const ShotHalf<S> sh = shot_desc(shots, shot_of(shots, n, blockIdx.x));
+  using G = typename S::Global;
+  u_half_var_wave_body<M, G>(S::global(sh.out), S::global(sh.in), S::global(sh.kap), sh.g, sh.va, sh.wscale,
+                             sh.wave_per_xcd, (int)blockIdx.x - sh.first_block);
 }
 
 // Sources inside a batch (the source term z = r(t) g(x) of Sec. 4, added by

@@ -56,6 +56,9 @@ def _shots(d, m, prec, sizes, rng, var=False, walls=()):
     (2, 2, "fp64", [(40, 24), (17, 9)], True, (1,)),
     (3, 1, "fp32_comp", [(12, 9, 5), (6, 7, 4)], False, (0, 1)),
     (2, 3, "fp32_comp", [(40, 24), (17, 9)], True, (1,)),
+    (3, 2, "fp32", [(9, 8, 7), (6, 5, 4), (2, 2, 2)], True, ()),
+    (3, 2, "fp64", [(6, 5, 4), (5, 4, 3)], True, (1,)),
+    (3, 3, "fp32_comp", [(4, 3, 3), (3, 3, 2)], True, ()),
 ])
 def test_batch_equals_per_plan_steps(d, m, prec, sizes, var, walls):
     _say(f"[batch] d={d} m={m} {prec} shots={sizes} var={var} walls={walls}")

@@ -226,17 +226,3 @@ def test_varkappa_3d_m2_sampled(prec):
     _, Ug = plan.export(p, u)
     ref = oracle.u_half_var(prob, U_in, Pg, ku, nodes=nodes)
     _close(np.stack([Ug[i][idx] for i in range(d)]), ref, *vtol(prec, d, m))
-
-
-def test_varkappa_3d_batch_refused():
-    """Batched steps take variable kappa in 3D for m <= 1 only."""
-    plans = [hl.Plan(3, 2, (4, 4, 4), precision="fp32") for _ in range(2)]
-    bufs = []
-    for pl in plans:
-        kp, ku = _kappa(3, 2, (4, 4, 4), np.random.default_rng(5), smooth=False)
-        pl.set_kappa(kp, ku)
-        bufs.append(pl.alloc())
-    b = hl.Batch(plans)
-    with pytest.raises(hl.HLError) as ei:
-        b.step([x[0] for x in bufs], [x[1] for x in bufs], 1)
-    assert ei.value.status == hl.HL_ERR_UNSUPPORTED
