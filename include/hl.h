@@ -342,10 +342,11 @@ hl_status hl_batch_destroy(hl_batch_t batch);
  * scaled Taylor data of g there, counts[i] x (m+1)^d in hl_init's coefficient
  * order.  amps[i] (namps values, NULL: zeros) are the amplitudes
  * a = dt_i r(t_n + dt_i/2) of shot i.  Host arrays, copied (values and
- * amplitudes rounded to the batch's precision).  counts == NULL removes the
- * sources.  HL_FP64 and HL_FP32 batches; the added launch (one work-item per
- * source datum) and the step counter's update join each batched step and its
- * captured graph.  Synchronous. */
+ * amplitudes rounded to the batch's precision; HL_FP32_COMP: the values to
+ * hi + lo, as its g buffer would hold them, the amplitudes kept in FP64).
+ * counts == NULL removes the sources.  Every precision; the added launch (one
+ * work-item per source datum) and the step counter's update join each batched
+ * step and its captured graph.  Synchronous. */
 hl_status hl_batch_set_sources(hl_batch_t batch, const int64_t* counts, const int64_t* const* nodes,
                                const double* const* values, const double* const* amps, int64_t namps);
 

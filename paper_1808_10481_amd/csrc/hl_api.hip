@@ -1696,13 +1696,15 @@ hl_status hl_batch_set_sources(hl_batch_t batch, const int64_t* counts, const in
   batch->bp.clear();  // the next hl_batch_step rebuilds its tables
   drop_sources(batch);
   if (!counts) return HL_OK;
-  if (!batch->ks.batch_src)
-    return fail(HL_ERR_UNSUPPORTED, "hl_batch_set_sources: built for HL_FP64 and HL_FP32 batches");
+  if (!batch->ks.batch_src) return fail(HL_ERR_UNSUPPORTED, "hl_batch_set_sources: not built for this batch");
   if (namps < 0 || !nodes || !values || !amps) return fail(HL_ERR_ARG, "hl_batch_set_sources: bad arguments");
   const int n = (int)batch->plans.size();
   const hl_plan_s* p0 = batch->plans[0];
   const int d = p0->d, mp = p0->m + 1, nc = p0->nc;
-  const bool f64 = p0->precision == HL_FP64;
+  // values and amplitudes in the storage's arithmetic type: FP64 words for
+  // FP64 and FP32_COMP (whose values are first rounded to hi + lo, as the
+  // split storage would hold g), FP32 words for FP32
+  const bool f64 = p0->precision != HL_FP32, split = p0->precision == HL_FP32_COMP;
   std::vector<hl::BatchSource> ent;
   std::vector<double> val, amp((size_t)n * (size_t)namps, 0.0);
   for (int i = 0; i < n; ++i) {
@@ -1738,7 +1740,14 @@ hl_status hl_batch_set_sources(hl_batch_t batch, const int64_t* counts, const in
         const double v = values[i][q * nc + c];
         if (!std::isfinite(v)) return fail(HL_ERR_ARG, "hl_batch_set_sources: values must be finite");
         ent.push_back(hl::BatchSource{(int32_t)i, (uint32_t)(plane * pl->pnodes + dn)});
-        val.push_back(v);
+        if (split) {
+          hl_host::FieldImage one{HL_FP32_COMP, 1, {}, {}};
+          if (!one.alloc()) return fail(HL_ERR_NOMEM, "hl_batch_set_sources: out of host memory");
+          one.put(0, v);
+          val.push_back(one.get(0));
+        } else {
+          val.push_back(v);
+        }
       }
     }
     if (amps[i])
@@ -1762,7 +1771,7 @@ hl_status hl_batch_set_sources(hl_batch_t batch, const int64_t* counts, const in
   };
   const std::vector<unsigned char> vw = words(val), aw = words(amp);
   const int64_t zero = 0;
-  e = hipMalloc(&batch->d_pbase, (size_t)n * sizeof(void*));
+  e = hipMalloc(&batch->d_pbase, (size_t)(split ? 2 : 1) * n * sizeof(void*));
   if (e == hipSuccess) e = hipMalloc(&batch->d_ent, std::max<size_t>(ent.size(), 1) * sizeof(hl::BatchSource));
   if (e == hipSuccess) e = hipMalloc(&batch->d_val, vw.size());
   if (e == hipSuccess) e = hipMalloc(&batch->d_amps, aw.size());
@@ -1848,7 +1857,16 @@ hl_status hl_batch_step(hl_batch_t batch, void* const* p, void* const* u, int64_
     if (e == hipSuccess) e = hipMemcpy(batch->du, ud.data(), ud.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hl_batch_step: descriptor upload");
     if (batch->src) {
-      e = hipMemcpy(batch->d_pbase, p, (size_t)n * sizeof(void*), hipMemcpyHostToDevice);
+      if (batch->plans[0]->precision == HL_FP32_COMP) {  // hi and lo bases per shot
+        std::vector<void*> hl2((size_t)2 * n);
+        for (int i = 0; i < n; ++i) {
+          hl2[2 * i] = p[i];
+          hl2[2 * i + 1] = static_cast<char*>(p[i]) + (size_t)4 * batch->plans[i]->nc * batch->plans[i]->pnodes;
+        }
+        e = hipMemcpy(batch->d_pbase, hl2.data(), hl2.size() * sizeof(void*), hipMemcpyHostToDevice);
+      } else {
+        e = hipMemcpy(batch->d_pbase, p, (size_t)n * sizeof(void*), hipMemcpyHostToDevice);
+      }
       if (e != hipSuccess) return hip_fail(e, "hl_batch_step: source buffer table upload");
     }
     batch->bp.assign(p, p + n);

@@ -73,7 +73,7 @@ struct KernelSet {
   VarGatherFn gather_p_var, gather_u_var;
   BatchDescFn batch_desc;
   BatchHalfFn p_batch, u_batch;
-  BatchSrcFn batch_src;  // plain storage only, else NULL
+  BatchSrcFn batch_src;
   int table_words;       // TableLayout<D, M>::TOTAL
   int p_off[3];          // offsets of the pressure merged tables, per component
   int u_off;             // offset of the velocity (Q) merged table
@@ -442,9 +442,18 @@ hipError_t launch_batch_src(const void* pbase, const void* ent, const void* val,
   return hipGetLastError();
 }
 
+inline hipError_t launch_batch_src_split(const void* pbase, const void* ent, const void* val, const void* amps,
+                                         int64_t namps, const int64_t* counter, int64_t nent, hipStream_t s) {
+  if (nent <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_source_add_split<SplitStore>, dim3((unsigned)((nent + 255) / 256)), dim3(256), 0, s,
+                     static_cast<void* const*>(pbase), static_cast<const BatchSource*>(ent),
+                     static_cast<const double*>(val), static_cast<const double*>(amps), namps, counter, nent);
+  return hipGetLastError();
+}
+
 template <class S>
 struct SrcLauncher {
-  static constexpr BatchSrcFn fn = nullptr;
+  static constexpr BatchSrcFn fn = &launch_batch_src_split;  // FP32_COMP
 };
 template <typename W>
 struct SrcLauncher<PlainStore<W>> {

@@ -1641,4 +1641,24 @@ __global__ void __launch_bounds__(256) batch_source_add(W* const* __restrict__ p
   *q = fma(amps[(int64_t)e.shot * namps + n], val[i], *q);
 }
 
+// The same in FP32_COMP storage: pbase holds each shot's hi base and lo base
+// (entries 2s and 2s + 1); values and amplitudes are FP64 (the values as the
+// split storage holds them), and the update rounds to hi + lo as every write
+// of that storage does.
+template <class S>
+__global__ void __launch_bounds__(256) batch_source_add_split(void* const* __restrict__ pbase,
+                                                              const BatchSource* __restrict__ ent,
+                                                              const double* __restrict__ val,
+                                                              const double* __restrict__ amps, int64_t namps,
+                                                              const int64_t* __restrict__ counter, int64_t nent) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nent) return;
+  const int64_t n = counter[0];
+  if (n < 0 || n >= namps) return;
+  const BatchSource e = ent[i];
+  const typename S::View v{static_cast<float*>(pbase[2 * e.shot]), static_cast<uint16_t*>(pbase[2 * e.shot + 1]), 0};
+  const double a = amps[(int64_t)e.shot * namps + n], g = val[i];
+  S::update(v, 0, e.word, [&](double x) { return fma(a, g, x); });
+}
+
 }  // namespace hl

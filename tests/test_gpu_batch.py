@@ -159,11 +159,15 @@ def _point_source(d, m, K, centre, width):
     (2, 2, "fp64", [(40, 24), (17, 9), (64, 64)], True),
     (1, 3, "fp32", [(37,), (120,), (2,)], False),
     (2, 3, "fp32", [(64, 48), (100, 37), (5, 3)], False),
+    (2, 2, "fp32_comp", [(40, 24), (17, 9)], True),
 ])
 def test_batch_sources_equal_per_plan_steps_and_oracle(d, m, prec, sizes, var):
     """Sources inside the batched launch: bit-identical to each plan's own
     pressure half-step, hl_add_source of the dense g and velocity half-step;
-    the FP64 case also against the oracle's midpoint-rule source step."""
+    the FP64 case also against the oracle's midpoint-rule source step.
+    FP32_COMP compares the stored values: the dense add rewrites every entry,
+    and an entry whose lo word is exactly half an FP32 ulp may come back with
+    its hi word rounded to even and the opposite lo (the same value)."""
     import oracle
     from tolerances import _close, tol
     _say(f"[batch] sources d={d} m={m} {prec} shots={sizes} var={var}")
@@ -207,8 +211,12 @@ def test_batch_sources_equal_per_plan_steps_and_oracle(d, m, prec, sizes, var):
                 plan.u_half(u, p)
         t += n
         torch.cuda.synchronize()
-        for (p, u), (pr, ur) in zip(states, ref):
-            assert torch.equal(p, pr) and torch.equal(u, ur)
+        for plan, (p, u), (pr, ur) in zip(plans, states, ref):
+            if prec == "fp32_comp":
+                got, want = plan.export(p, u), plan.export(pr, ur)
+                assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+            else:
+                assert torch.equal(p, pr) and torch.equal(u, ur)
     assert t == total
     if prec == "fp64":
         for i in range(len(plans)):
@@ -226,8 +234,12 @@ def test_batch_sources_equal_per_plan_steps_and_oracle(d, m, prec, sizes, var):
     for plan, (p, u) in zip(plans, ref):
         plan.step(p, u, 2)
     torch.cuda.synchronize()
-    for (p, u), (pr, ur) in zip(states, ref):
-        assert torch.equal(p, pr) and torch.equal(u, ur)
+    for plan, (p, u), (pr, ur) in zip(plans, states, ref):
+        if prec == "fp32_comp":
+            got, want = plan.export(p, u), plan.export(pr, ur)
+            assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+        else:
+            assert torch.equal(p, pr) and torch.equal(u, ur)
     batch.close()
 
 
@@ -238,13 +250,7 @@ def test_batch_sources_reject_bad_input():
     with pytest.raises(hl.HLError) as ei:
         batch.set_sources([(nodes, np.ones((2, 2, 2)))], [np.ones(3)])
     assert ei.value.status == hl.HL_ERR_ARG
-    c = hl.Plan(2, 1, (8, 6), precision="fp32_comp")
-    bc = hl.Batch([c])
-    with pytest.raises(hl.HLError) as ei:
-        bc.set_sources([(nodes[:1], np.ones((1, 2, 2)))], [np.ones(3)])
-    assert ei.value.status == hl.HL_ERR_UNSUPPORTED
     batch.close()
-    bc.close()
 
 
 def test_batch_sources_on_walled_shots_equal_per_plan_steps():
