@@ -25,7 +25,7 @@ from paper_1808_10481_amd import inputs
 import polyutil as pu
 
 
-@pytest.mark.parametrize("d,m,K", [(1, 2, (7,)), (2, 1, (5, 4)), (2, 3, (4, 3)), (3, 1, (3, 3, 2))])
+@pytest.mark.parametrize("d,m,K", [(1, 2, (7,)), (2, 1, (5, 4)), (2, 3, (4, 3)), (3, 1, (3, 3, 2)), (3, 2, (3, 2, 2))])
 def test_constant_kappa_data_reproduce_constant_step(d, m, K):
     rng = np.random.default_rng(d + 10 * m)
     kappa = 1.7
@@ -60,7 +60,7 @@ def _kappa_data(k0, kgrad, centre, h, m, d):
     return kap[None]
 
 
-@pytest.mark.parametrize("d,m", [(1, 1), (1, 2), (2, 1), (2, 2)])
+@pytest.mark.parametrize("d,m", [(1, 1), (1, 2), (2, 1), (2, 2), (3, 1)])
 def test_half_steps_exact_for_affine_kappa(d, m):
     rng = np.random.default_rng(500 + 10 * d + m)
     deg = 2 * m                                          # total degree <= 2m
