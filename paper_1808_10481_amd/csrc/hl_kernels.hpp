@@ -60,6 +60,14 @@
 #ifndef HL_PREFETCH3
 #define HL_PREFETCH3 1
 #endif
+// Cache policy of the 3D half-steps' read-modify-write of their outputs: 2,
+// the non-temporal bit.  Each output word is read and written once per
+// half-step, while the corner words are read by up to 8 neighbouring nodes;
+// streaming the outputs leaves the L2 to the corners (256^3 m = 2 step: FP64
+// 14.68 -> 14.27 ms, FP32 6.20 -> 6.06 ms).
+#ifndef HL_STREAM_AUX
+#define HL_STREAM_AUX 2
+#endif
 template <class S>
 constexpr bool kPrefetch3 = HL_PREFETCH3 == 2 || (HL_PREFETCH3 == 1 && S::kBytes == 8);
 
@@ -200,7 +208,7 @@ template <int D, class S, class F>
 __device__ __forceinline__ void update_entry(const typename S::View& v, int pl, uint32_t n0, F f) {
   if constexpr (D == 3) {
     const typename S::Planes pr = S::planes(v, pl);
-    S::bstore(pr, n0, f(S::bload(pr, n0)));
+    S::template bstore<HL_STREAM_AUX>(pr, n0, f(S::template bload<HL_STREAM_AUX>(pr, n0)));
   } else {
     S::update(v, pl, n0, f);
   }

@@ -85,20 +85,23 @@ struct PlainStore {
   __device__ static __forceinline__ Planes planes(const View& v, int pl) {
     return Planes{raw_rsrc((const void*)(uintptr_t)plane(v, pl), (uint32_t)(v.nodes * (int64_t)sizeof(W)))};
   }
+  // AUX: the cache-policy operand of the buffer instruction (0: default).
+  template <int AUX = 0>
   __device__ static __forceinline__ C bload(const Planes& p, uint32_t node) {
     const uint32_t off = node * (uint32_t)sizeof(W);
     if constexpr (sizeof(W) == 4)
-      return __builtin_bit_cast(W, __builtin_amdgcn_raw_buffer_load_b32(p.r, off, 0u, 0));
+      return __builtin_bit_cast(W, __builtin_amdgcn_raw_buffer_load_b32(p.r, off, 0u, AUX));
     else
-      return __builtin_bit_cast(W, __builtin_amdgcn_raw_buffer_load_b64(p.r, off, 0u, 0));
+      return __builtin_bit_cast(W, __builtin_amdgcn_raw_buffer_load_b64(p.r, off, 0u, AUX));
   }
+  template <int AUX = 0>
   __device__ static __forceinline__ void bstore(const Planes& p, uint32_t node, C x) {
     const uint32_t off = node * (uint32_t)sizeof(W);
     if constexpr (sizeof(W) == 4) {
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), p.r, off, 0u, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), p.r, off, 0u, AUX);
     } else {
       typedef uint32_t u2 __attribute__((ext_vector_type(2)));
-      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), p.r, off, 0u, 0);
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), p.r, off, 0u, AUX);
     }
   }
 };
@@ -162,16 +165,18 @@ struct SplitStoreT {
     return Planes{raw_rsrc((const void*)(uintptr_t)hi_plane(v, pl), 4u * n),
                   raw_rsrc((const void*)(uintptr_t)lo_plane(v, pl), 2u * n)};
   }
+  template <int AUX = 0>
   __device__ static __forceinline__ C bload(const Planes& p, uint32_t node) {
-    const float hi = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(p.hi, node * 4u, 0u, 0));
-    const uint16_t lo = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(p.lo, node * 2u, 0u, 0);
+    const float hi = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(p.hi, node * 4u, 0u, AUX));
+    const uint16_t lo = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(p.lo, node * 2u, 0u, AUX);
     return widen(hi, lo);
   }
   // The same rounding as update / store: hi = FP32 of x, lo = BF16 of x - hi.
+  template <int AUX = 0>
   __device__ static __forceinline__ void bstore(const Planes& p, uint32_t node, C x) {
     const float hi = (float)x;
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, hi), p.hi, node * 4u, 0u, 0);
-    __builtin_amdgcn_raw_buffer_store_b16(to_bf16((float)(x - (double)hi)), p.lo, node * 2u, 0u, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, hi), p.hi, node * 4u, 0u, AUX);
+    __builtin_amdgcn_raw_buffer_store_b16(to_bf16((float)(x - (double)hi)), p.lo, node * 2u, 0u, AUX);
   }
 };
 
