@@ -74,6 +74,12 @@ struct PlainStore {
     WP q = reinterpret_cast<WP>(plane(v, pl) + node * (uint32_t)sizeof(W));
     *q = f(*q);
   }
+  // the same with non-temporal accesses
+  template <class F>
+  __device__ static __forceinline__ void update_nt(const View& v, int pl, uint32_t node, F f) {
+    WP q = reinterpret_cast<WP>(plane(v, pl) + node * (uint32_t)sizeof(W));
+    __builtin_nontemporal_store(f(__builtin_nontemporal_load(q)), q);
+  }
   __device__ static __forceinline__ void store(const View& v, int pl, uint32_t node, C x) {
     *reinterpret_cast<WP>(plane(v, pl) + node * (uint32_t)sizeof(W)) = x;
   }
@@ -155,6 +161,15 @@ struct SplitStoreT {
   }
   __device__ static __forceinline__ void store(const View& v, int pl, uint32_t node, C x) {
     update(v, pl, node, [&](C) { return x; });
+  }
+  template <class F>
+  __device__ static __forceinline__ void update_nt(const View& v, int pl, uint32_t node, F f) {
+    FP qh = reinterpret_cast<FP>(reinterpret_cast<CP>(hi_plane(v, pl)) + node * 4u);
+    HP ql = reinterpret_cast<HP>(reinterpret_cast<CP>(lo_plane(v, pl)) + node * 2u);
+    const double val = f(widen(__builtin_nontemporal_load(qh), __builtin_nontemporal_load(ql)));
+    const float hi = (float)val;
+    __builtin_nontemporal_store(hi, qh);
+    __builtin_nontemporal_store(to_bf16((float)(val - (double)hi)), ql);
   }
 
   struct Planes {
